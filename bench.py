@@ -1,0 +1,216 @@
+"""Throughput of the DPDE VV+SER step on one MI355X.
+
+Default workload: the learned-EOS system, N = 1,048,576 particles at number
+density 3 in a periodic cube (side 70.4411, 70^3 cells), soft DPD force
+a = 25, gamma = 4.5, kT = 1, Einstein internal EOS (n = 50, w = 2, c0 = 10)
+inverted by the surrogate network (trained on the GPU first) with Newton
+outside its range, dt = 0.005, FP64 pair terms.  Inputs are synthetic
+(uniform positions, Maxwell momenta, theta_i = 1) and resident in HBM before
+the timed region.
+
+One JSON line on stdout: metric, value (particle-steps/s), roofline of the
+dominant kernel (per-kernel HIP-event times over a profiled stretch of the
+same run), the CPU oracle timed on a bounded sample of the same workload, and
+the other variants of the same geometry.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+N_1M = 1_048_576
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_system(dp, W, n, *, eos, theta_mode, precision, dt, seed=7, init_seed=20260101):
+    L = W.cubic_side(n)
+    box = [L, L, L]
+    cfg = dp.Config(n=n, box=box, dt=dt, eos=eos, theta_mode=theta_mode, precision=precision,
+                    seed=seed)
+    if eos == dp.EOS_EINSTEIN:
+        # eps_i = eps(theta = 1) from the library's own EOS (a small helper handle)
+        nh = 200
+        Lh = W.cubic_side(nh)
+        qh, ph, eh = W.equilibrium_state(nh, [Lh] * 3, eps0=10.0, seed=1)
+        helper = dp.System(dp.Config(n=nh, box=[Lh] * 3, eos=eos), qh, ph, eh)
+        import torch
+        eps0 = float(helper.eos_energy(torch.ones(1, dtype=torch.float64)).cpu()[0])
+        helper.close()
+    else:
+        eps0 = cfg.cv * 1.0
+    q, p, e = W.equilibrium_state(n, box, eps0=eps0, seed=init_seed)
+    return dp.System(cfg, q, p, e), cfg, (q, p, e), eps0
+
+
+def timed(sysm, steps, warmup):
+    import torch
+    sysm.step(warmup)
+    sysm.history()  # drop warm-up records
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sysm.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return t1 - t0, sysm.history()
+
+
+def drift_per_1e4(hist):
+    E = hist[:, 3]
+    if len(E) < 3:
+        return None
+    n = np.arange(len(E), dtype=float)
+    s = np.polyfit(n, (E - E[0]) / abs(E[0]), 1)[0]
+    return float(1e4 * s)
+
+
+def kernel_profile(sysm, steps):
+    sysm.profile(True)
+    sysm.step(steps)
+    prof = sysm.profile_read()
+    sysm.profile(False)
+    return {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in prof.items()}
+
+
+def mean_neighbours(sysm, n):
+    pr = sysm.debug_pairs()
+    return 2.0 * len(pr) / n
+
+
+def pair_kernel_bytes(name, nbar, fp32=False):
+    """Algorithmic HBM bytes per particle of the pair kernels: every
+    per-particle array read or written once, neighbour-list words 4 B each;
+    neighbour gathers are re-reads served on chip and not counted."""
+    lst = 4.0 + 4.0 * nbar  # count + entries
+    if name.startswith("pass_a"):
+        return 24 + 24 + 4 + (24 + 24 + 8) + lst  # q, p, cell offsets ~4 | F, p, U | list
+    if name.startswith("pass_b"):
+        return 24 + 24 + 8 + 4 + lst + 24         # q, p, 1/T, id, list | dp
+    if name.startswith("pass_c"):
+        return 24 + 24 + 8 + 4 + lst + 24 + 8 + (24 + 8 + 8)  # ... dp, eps | p, eps, 1/T
+    return None
+
+
+def cpu_baseline(W, n, steps, eos, dt, eps0):
+    import oracle as O
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, eps0=eps0, seed=20260101)
+    P = O.make_params(n, [L] * 3, dt=dt, eos=eos)
+    t0 = time.perf_counter()
+    S = O.State(P, q, p, e)
+    t_init = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rc, _ = S.step(steps)
+    dt_run = time.perf_counter() - t0
+    return {"value": n * steps / dt_run, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} full steps of the same N={n} system after oracle init "
+                      f"({t_init:.1f} s), single thread, {dt_run:.1f} s", "rc": rc}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--n", type=int, default=N_1M)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--mlp-iters", type=int, default=3000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU slab decomposition is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1507_06643_amd as dp
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    n = args.n
+    dt = 0.005
+    log(f"[bench] learned-EOS workload N={n}: init")
+    sysm, cfg, _, eps0 = make_system(dp, W, n, eos=dp.EOS_EINSTEIN, theta_mode=dp.THETA_MLP,
+                                     precision=dp.FP64, dt=dt)
+    t0 = time.perf_counter()
+    curve = sysm.mlp_train(nsamples=10**6, iters=args.mlp_iters, batch=4096, lr=3e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"[bench] surrogate trained in {t_train:.2f} s, final loss {curve[-1]:.3e}")
+    log(f"[bench] timing {args.steps} steps after {args.warmup} warm-up")
+    secs, hist = timed(sysm, args.steps, args.warmup)
+    value = n * args.steps / secs
+    ms_step = 1e3 * secs / args.steps
+    log(f"[bench] {value:.4e} particle-steps/s ({ms_step:.3f} ms/step)")
+    prof = kernel_profile(sysm, args.profile_steps)
+    nbar = mean_neighbours(sysm, n)
+    dom = max((k for k in prof if k.startswith("pass_")), key=lambda k: prof[k]["avg_ms"])
+    bpp = pair_kernel_bytes(dom, nbar)
+    achieved = bpp * n / (prof[dom]["avg_ms"] * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_particle": bpp, "mean_neighbours": nbar,
+            "avg_launch_ms": prof[dom]["avg_ms"]}
+    line = {
+        "metric": "particle-steps/s at N=1M",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "learned-EOS N=1,048,576 density 3, Einstein EOS (n=50, w=2, c0=10) "
+                               "via BF16 surrogate + Newton fallback, dt=0.005, FP64 pair terms",
+                   "n": n, "dt": dt, "precision": "fp64", "theta": "mlp+newton-fallback"},
+        "roofline": roof,
+        "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in prof.items()},
+        "energy_drift_per_1e4_steps": drift_per_1e4(hist),
+        "surrogate_train_s": t_train,
+    }
+    sysm.close()
+    if not args.no_variants:
+        variants = {}
+        for name, eos, tm, prec, vdt in [
+                ("plain_fp64_linear_eos", dp.EOS_LINEAR, dp.THETA_NEWTON, dp.FP64, 0.005),
+                ("fp32_pairs_learned_eos", dp.EOS_EINSTEIN, dp.THETA_MLP, dp.FP32, 0.005),
+                ("fp64_newton_learned_eos", dp.EOS_EINSTEIN, dp.THETA_NEWTON, dp.FP64, 0.005)]:
+            log(f"[bench] variant {name}")
+            s2, _, _, _ = make_system(dp, W, n, eos=eos, theta_mode=tm, precision=prec, dt=vdt)
+            if tm != dp.THETA_NEWTON:
+                s2.mlp_train(nsamples=10**6, iters=args.mlp_iters, batch=4096, lr=3e-3)
+            sec2, h2 = timed(s2, max(50, args.steps // 2), 10)
+            p2 = kernel_profile(s2, args.profile_steps)
+            variants[name] = {"value": n * max(50, args.steps // 2) / sec2,
+                              "ms_per_step": 1e3 * sec2 / max(50, args.steps // 2),
+                              "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in p2.items()},
+                              "energy_drift_per_1e4_steps": drift_per_1e4(h2)}
+            s2.close()
+        line["variants"] = variants
+    if not args.no_cpu:
+        log(f"[bench] CPU oracle: {args.cpu_steps} steps at N={n}")
+        line["cpu_baseline"] = cpu_baseline(W, n, args.cpu_steps, 1, dt, eps0)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

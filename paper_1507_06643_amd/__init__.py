@@ -1,0 +1,18 @@
+"""DPDE with energy conservation on MI355X: velocity-Verlet + SER pair-parallel
+fluctuation/dissipation (Homman, Maillet, Roussel, Stoltz, arXiv:1507.06643).
+
+The compute lives in libdpde.so (hand-written HIP for gfx950); this package is
+its Python binding.  Importing it loads the library and fails loudly when it
+has not been built.
+"""
+from . import _lib
+from ._lib import (DpdeError, EOS_EINSTEIN, EOS_LINEAR, FP32, FP64, SCHEME_SEM, SCHEME_SER,
+                   THETA_MLP, THETA_MLP_NEWTON, THETA_NEWTON)
+
+_lib.load()
+
+from .system import Config, System, debug_rng  # noqa: E402
+
+__all__ = ["Config", "System", "debug_rng", "DpdeError", "FP32", "FP64", "EOS_LINEAR",
+           "EOS_EINSTEIN", "THETA_NEWTON", "THETA_MLP", "THETA_MLP_NEWTON", "SCHEME_SER",
+           "SCHEME_SEM"]

@@ -1,0 +1,837 @@
+// libdpde.so: host side of the C ABI declared in include/dpde.h.
+//
+// One handle = one or more systems (replicas) stored back to back in
+// structure-of-arrays form, sorted by (replica, cell, id).  A step is a fixed
+// sequence of kernel launches on the handle's stream; the host only reads the
+// device status word once per dpde_step call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/dpde.h"
+#include "bin.h"
+#include "mlp.h"
+#include "pairs.h"
+
+using namespace dpde;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(DPDE_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                              \
+  } while (0)
+
+constexpr int kHistBytes = 64 << 20;
+constexpr int64_t kStatTile = 4096;
+
+struct ProfileRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct dpde_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t user_stream = nullptr;
+  Phys phys{};
+  int nrep = 1;
+  bool batch = false;
+  std::vector<Geo> geo_h;
+  std::vector<int64_t> offsets;
+  Geo* geo = nullptr;
+  int64_t n = 0;
+  int64_t ncells = 0;
+  int64_t step = 0;
+  int pair_block = 256;
+  int aux_block = 256;
+
+  PState cur{}, alt{};
+  double *Fx = nullptr, *Fy = nullptr, *Fz = nullptr;
+  double *dpx = nullptr, *dpy = nullptr, *dpz = nullptr, *deps = nullptr;
+  double* Ui = nullptr;
+  uint32_t *key = nullptr, *ticket = nullptr, *perm = nullptr;
+  uint32_t *cell_count = nullptr, *cell_start = nullptr, *scan_tmp = nullptr;
+  int scan_tiles = 0;
+  NList nl{};
+  uint32_t* status = nullptr;
+  uint64_t* d_step = nullptr;
+  int64_t* d_hist_count = nullptr;
+  int64_t* tile_begin = nullptr;
+  int32_t* rep_tile0 = nullptr;
+  int ntiles = 0;
+  double* partials = nullptr;
+  double* rec = nullptr;
+  double* hist = nullptr;
+  int64_t hist_cap = 0;
+  unsigned long long* counter = nullptr;
+
+  // surrogate network
+  MlpState mlp{};
+
+  // profiling
+  bool profiling = false;
+  std::vector<ProfileRec> prof;
+  std::vector<hipEvent_t> event_pool;
+
+  // graph cache
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int64_t graph_steps = 0;
+
+  std::vector<void*> allocations;
+};
+
+namespace {
+
+template <typename T>
+int dalloc(dpde_handle* h, T** p, size_t count) {
+  void* ptr = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+  if (e != hipSuccess)
+    return fail(DPDE_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                hipGetErrorString(e));
+  h->allocations.push_back(ptr);
+  *p = reinterpret_cast<T*>(ptr);
+  return DPDE_OK;
+}
+
+hipEvent_t get_event(dpde_handle* h) {
+  if (!h->event_pool.empty()) {
+    hipEvent_t e = h->event_pool.back();
+    h->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch with optional per-kernel event timing.
+template <typename... KArgs, typename... Args>
+void launch(dpde_handle* h, const char* name, void (*kernel)(KArgs...), dim3 grid, dim3 block,
+            Args... args) {
+  if (grid.x == 0) return;
+  if (h->profiling) {
+    ProfileRec r{name, get_event(h), get_event(h)};
+    (void)hipEventRecord(r.a, h->stream);
+    hipLaunchKernelGGL(kernel, grid, block, 0, h->stream, args...);
+    (void)hipEventRecord(r.b, h->stream);
+    h->prof.push_back(r);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, h->stream, args...);
+  }
+}
+
+inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+int check_params(const dpde_params* P, bool first) {
+  if (!P) return fail(DPDE_EINVAL, "params is NULL");
+  if (P->n < 2) return fail(DPDE_EINVAL, "n = %lld < 2", (long long)P->n);
+  if (P->n >= (int64_t)1 << 31) return fail(DPDE_EINVAL, "n = %lld too large", (long long)P->n);
+  for (int d = 0; d < 3; ++d) {
+    if (!(std::isfinite(P->box[d]) && P->box[d] > 0))
+      return fail(DPDE_EINVAL, "box[%d] must be finite and > 0", d);
+    if (P->periodic[d] != 0 && P->periodic[d] != 1)
+      return fail(DPDE_EINVAL, "periodic[%d] must be 0 or 1", d);
+  }
+  if (!first) return DPDE_OK;
+  if (!(std::isfinite(P->rc) && P->rc > 0)) return fail(DPDE_EINVAL, "rc must be > 0");
+  if (!(std::isfinite(P->mass) && P->mass > 0)) return fail(DPDE_EINVAL, "mass must be > 0");
+  if (!(std::isfinite(P->dt) && P->dt > 0)) return fail(DPDE_EINVAL, "dt must be > 0");
+  if (!(std::isfinite(P->kT_ref) && P->kT_ref > 0)) return fail(DPDE_EINVAL, "kT_ref must be > 0");
+  if (!(std::isfinite(P->gamma) && P->gamma >= 0)) return fail(DPDE_EINVAL, "gamma must be >= 0");
+  if (!(std::isfinite(P->a) && P->a >= 0)) return fail(DPDE_EINVAL, "a must be >= 0");
+  if (P->eos == DPDE_EOS_LINEAR) {
+    if (!(std::isfinite(P->cv) && P->cv > 0)) return fail(DPDE_EINVAL, "cv must be > 0");
+  } else if (P->eos == DPDE_EOS_EINSTEIN) {
+    if (!(P->eos_n >= 0 && P->eos_omega > 0 && P->eos_c0 > 0 && std::isfinite(P->eos_n) &&
+          std::isfinite(P->eos_omega) && std::isfinite(P->eos_c0)))
+      return fail(DPDE_EINVAL, "Einstein EOS needs eos_n >= 0, eos_omega > 0, eos_c0 > 0");
+  } else {
+    return fail(DPDE_EINVAL, "unknown eos %d", P->eos);
+  }
+  if (P->precision != DPDE_FP64 && P->precision != DPDE_FP32)
+    return fail(DPDE_EINVAL, "unknown precision %d", P->precision);
+  if (P->theta_mode < 0 || P->theta_mode > 2)
+    return fail(DPDE_EINVAL, "unknown theta_mode %d", P->theta_mode);
+  if (P->scheme != DPDE_SCHEME_SER && P->scheme != DPDE_SCHEME_SEM)
+    return fail(DPDE_EINVAL, "unknown scheme %d", P->scheme);
+  if (P->neighbor_cap < 0 || P->neighbor_cap > 1024)
+    return fail(DPDE_EINVAL, "neighbor_cap must be in [0, 1024]");
+  if (P->flags != 0) return fail(DPDE_EINVAL, "flags must be 0");
+  return DPDE_OK;
+}
+
+int geometry(const dpde_params* P, Geo& g) {
+  for (int d = 0; d < 3; ++d) {
+    const double ncd = std::floor(P->box[d] / P->rc);
+    if (ncd < 3.0)
+      return fail(DPDE_EBOX, "box[%d] = %g holds %g < 3 cells of side rc = %g", d, P->box[d], ncd,
+                  P->rc);
+    if (ncd > 1e6) return fail(DPDE_EINVAL, "box[%d]/rc too large", d);
+    g.nc[d] = (int32_t)ncd;
+    g.box[d] = P->box[d];
+    g.half_box[d] = 0.5 * P->box[d];
+    g.scale[d] = (double)g.nc[d] / P->box[d];
+    g.periodic[d] = P->periodic[d];
+  }
+  g.key0 = (uint32_t)P->seed;
+  g.key1 = (uint32_t)(P->seed >> 32) ^ P->replica;
+  return DPDE_OK;
+}
+
+void physics(const dpde_params* P, Phys& ph) {
+  ph.mass = P->mass;
+  ph.inv_mass = 1.0 / P->mass;
+  ph.inv_2m = 1.0 / (2.0 * P->mass);
+  ph.rc = P->rc;
+  ph.inv_rc = 1.0 / P->rc;
+  ph.rc2 = P->rc * P->rc;
+  ph.a = P->a;
+  ph.half_a_rc = 0.5 * P->a * P->rc;
+  ph.gkT_half = 0.5 * P->gamma * P->kT_ref;
+  ph.sigma = std::sqrt(2.0 * P->gamma * P->kT_ref);
+  ph.dt = P->dt;
+  ph.half_dt = 0.5 * P->dt;
+  ph.sqrt_dt = std::sqrt(P->dt);
+  ph.dsigma2_m = 3.0 * ph.sigma * ph.sigma / P->mass;
+  ph.cv = P->cv;
+  ph.eos_n = P->eos_n;
+  ph.eos_omega = P->eos_omega;
+  ph.eos_c0 = P->eos_c0;
+  ph.eos = P->eos;
+  ph.theta_mode = P->theta_mode;
+  ph.precision = P->precision;
+  ph.scheme = P->scheme;
+  ph.cap = P->neighbor_cap > 0 ? P->neighbor_cap : 64;
+}
+
+int alloc_pstate(dpde_handle* h, PState& s) {
+  int rc;
+  const int64_t n = h->n;
+  if ((rc = dalloc(h, &s.qx, n)) || (rc = dalloc(h, &s.qy, n)) || (rc = dalloc(h, &s.qz, n)) ||
+      (rc = dalloc(h, &s.px, n)) || (rc = dalloc(h, &s.py, n)) || (rc = dalloc(h, &s.pz, n)) ||
+      (rc = dalloc(h, &s.eps, n)) || (rc = dalloc(h, &s.invT, n)) || (rc = dalloc(h, &s.id, n)))
+    return rc;
+  s.rep = nullptr;
+  if (h->batch && (rc = dalloc(h, &s.rep, n))) return rc;
+  return DPDE_OK;
+}
+
+int allocate(dpde_handle* h) {
+  int rc;
+  const int64_t n = h->n;
+  if ((rc = alloc_pstate(h, h->cur)) || (rc = alloc_pstate(h, h->alt))) return rc;
+  if ((rc = dalloc(h, &h->Fx, n)) || (rc = dalloc(h, &h->Fy, n)) || (rc = dalloc(h, &h->Fz, n)) ||
+      (rc = dalloc(h, &h->dpx, n)) || (rc = dalloc(h, &h->dpy, n)) ||
+      (rc = dalloc(h, &h->dpz, n)) || (rc = dalloc(h, &h->deps, n)) || (rc = dalloc(h, &h->Ui, n)))
+    return rc;
+  if ((rc = dalloc(h, &h->key, n)) || (rc = dalloc(h, &h->ticket, n)) ||
+      (rc = dalloc(h, &h->perm, n)))
+    return rc;
+  if ((rc = dalloc(h, &h->cell_count, h->ncells)) || (rc = dalloc(h, &h->cell_start, h->ncells + 1)))
+    return rc;
+  h->scan_tiles = (int)((h->ncells + kScanTile - 1) / kScanTile);
+  if (h->scan_tiles > 1024 * 8) return fail(DPDE_EINVAL, "too many cells (%lld)", (long long)h->ncells);
+  if ((rc = dalloc(h, &h->scan_tmp, h->scan_tiles + 1))) return rc;
+  h->nl.stride = n;
+  if ((rc = dalloc(h, &h->nl.idx, (size_t)h->phys.cap * n)) || (rc = dalloc(h, &h->nl.count, n)))
+    return rc;
+  if ((rc = dalloc(h, &h->status, 4)) || (rc = dalloc(h, &h->d_step, 1)) ||
+      (rc = dalloc(h, &h->d_hist_count, 1)) || (rc = dalloc(h, &h->counter, 1)))
+    return rc;
+  // observable tiles: chunks of kStatTile inside each replica
+  std::vector<int64_t> tb;
+  std::vector<int32_t> rt;
+  for (int r = 0; r < h->nrep; ++r) {
+    rt.push_back((int32_t)tb.size());
+    for (int64_t b = h->offsets[r]; b < h->offsets[r + 1]; b += kStatTile) tb.push_back(b);
+  }
+  rt.push_back((int32_t)tb.size());
+  h->ntiles = (int)tb.size();
+  tb.push_back(n);
+  if ((rc = dalloc(h, &h->tile_begin, tb.size())) || (rc = dalloc(h, &h->rep_tile0, rt.size())) ||
+      (rc = dalloc(h, &h->partials, (size_t)h->ntiles * 8)) ||
+      (rc = dalloc(h, &h->rec, (size_t)h->nrep * 10)))
+    return rc;
+  HIPCHK(hipMemcpy(h->tile_begin, tb.data(), tb.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->rep_tile0, rt.data(), rt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  h->hist_cap = std::max<int64_t>(16, std::min<int64_t>(65536, kHistBytes / (h->nrep * 80)));
+  if ((rc = dalloc(h, &h->hist, (size_t)h->hist_cap * h->nrep * 10))) return rc;
+  if ((rc = dalloc(h, &h->geo, h->nrep))) return rc;
+  HIPCHK(hipMemcpy(h->geo, h->geo_h.data(), h->nrep * sizeof(Geo), hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(h->status, 0, 4 * sizeof(uint32_t)));
+  HIPCHK(hipMemset(h->cell_count, 0, h->ncells * sizeof(uint32_t)));
+  HIPCHK(hipMemset(h->d_hist_count, 0, sizeof(int64_t)));
+  return DPDE_OK;
+}
+
+int status_to_code(uint32_t st) {
+  if (st & ST_NONFINITE) return fail(DPDE_ENONFINITE, "non-finite value in the particle state");
+  if (st & ST_NEG_EINT)
+    return fail(DPDE_ENEG_EINT, "an internal energy (or temperature) became non-positive");
+  if (st & ST_EOS) return fail(DPDE_EEOS, "temperature inversion failed");
+  if (st & ST_OVERFLOW)
+    return fail(DPDE_EOVERFLOW, "a particle has more neighbours than the list capacity");
+  return DPDE_OK;
+}
+
+// ---- the launch sequence -----------------------------------------------------
+void enqueue_bin(dpde_handle* h, int kick) {
+  const int b = h->aux_block;
+  const int64_t n = h->n;
+  if (h->batch)
+    launch(h, "kick_drift_key", k_kick_drift_key<true>, blocks(n, b), b, h->cur, h->Fx, h->Fy,
+           h->Fz, n, h->geo, h->phys, kick, h->key, h->ticket, h->cell_count, h->status);
+  else
+    launch(h, "kick_drift_key", k_kick_drift_key<false>, blocks(n, b), b, h->cur, h->Fx, h->Fy,
+           h->Fz, n, h->geo, h->phys, kick, h->key, h->ticket, h->cell_count, h->status);
+  launch(h, "scan_tiles", k_scan_tiles, h->scan_tiles, kScanThreads, h->cell_count, h->ncells,
+         h->scan_tmp);
+  launch(h, "scan_tile_sums", k_scan_tile_sums, 1, 1024, h->scan_tmp, h->scan_tiles);
+  launch(h, "scan_apply", k_scan_apply, h->scan_tiles, kScanThreads, h->cell_count, h->ncells,
+         (const uint32_t*)h->scan_tmp, h->cell_start);
+  launch(h, "scatter", k_scatter, blocks(n, b), b, (const uint32_t*)h->key,
+         (const uint32_t*)h->ticket, (const uint32_t*)h->cell_start, n, h->perm,
+         (const uint32_t*)h->status);
+  launch(h, "cell_sort", k_cell_sort, blocks(h->ncells, b), b, (const uint32_t*)h->cell_start,
+         h->ncells, h->perm, (const uint32_t*)h->cur.id, (const uint32_t*)h->status);
+  launch(h, "gather", k_gather, blocks(n, b), b, h->cur, h->alt, (const uint32_t*)h->perm, n,
+         (const uint32_t*)h->status);
+  std::swap(h->cur, h->alt);
+}
+
+void enqueue_forces(dpde_handle* h, int mode) {
+  const int b = h->pair_block;
+  const int64_t n = h->n;
+  auto go = [&](auto kern) {
+    launch(h, "pass_a_forces", kern, blocks(n, b), b, h->cur, (const uint32_t*)h->cell_start, n,
+           (const Geo*)h->geo, h->phys, mode, h->Fx, h->Fy, h->Fz, h->Ui, h->nl, h->status);
+  };
+  if (h->batch) {
+    if (h->phys.precision == DPDE_FP32) go(k_pass_a<true, PREC_F32>);
+    else go(k_pass_a<true, PREC_F64>);
+  } else {
+    if (h->phys.precision == DPDE_FP32) go(k_pass_a<false, PREC_F32>);
+    else go(k_pass_a<false, PREC_F64>);
+  }
+}
+
+bool eos_inline(const dpde_handle* h) {
+  return h->phys.eos == DPDE_EOS_LINEAR || h->phys.theta_mode == DPDE_THETA_NEWTON;
+}
+
+template <bool B, int PR>
+void enqueue_fd_t(dpde_handle* h, uint64_t* d_step) {
+  const int b = h->pair_block;
+  const int64_t n = h->n;
+  (void)d_step;
+  const int inl = eos_inline(h) ? 1 : 0;
+  if (h->phys.scheme == DPDE_SCHEME_SEM) {
+    launch(h, "pass_b_sem", k_pass_b<B, PR, 1>, blocks(n, b), b, h->cur, h->nl, n,
+           (const Geo*)h->geo, h->phys, d_step, h->dpx, h->dpy, h->dpz, h->deps, h->status);
+    launch(h, "apply_sem", k_apply_sem, blocks(n, h->aux_block), h->aux_block, h->cur, n, h->phys,
+           (const double*)h->dpx, (const double*)h->dpy, (const double*)h->dpz,
+           (const double*)h->deps, inl, h->status);
+  } else {
+    launch(h, "pass_b_ser", k_pass_b<B, PR, 0>, blocks(n, b), b, h->cur, h->nl, n,
+           (const Geo*)h->geo, h->phys, d_step, h->dpx, h->dpy, h->dpz, h->deps, h->status);
+    launch(h, "pass_c_ser", k_pass_c<B, PR>, blocks(n, b), b, h->cur, h->nl, n,
+           (const Geo*)h->geo, h->phys, d_step, (const double*)h->dpx, (const double*)h->dpy,
+           (const double*)h->dpz, inl, h->alt.px, h->alt.py, h->alt.pz, h->alt.invT, h->status);
+    // the new momenta and temperatures live in the spare buffer's fields: swap
+    // them in (two steps restore the original pointer layout, which keeps
+    // even-length captured graphs replayable)
+    std::swap(h->cur.px, h->alt.px);
+    std::swap(h->cur.py, h->alt.py);
+    std::swap(h->cur.pz, h->alt.pz);
+    std::swap(h->cur.invT, h->alt.invT);
+  }
+  if (!inl) enqueue_theta_mlp(h->mlp, h->stream, h->cur.eps, h->cur.invT, n, h->phys, h->status);
+}
+
+void enqueue_fd(dpde_handle* h) {
+  if (h->batch) {
+    if (h->phys.precision == DPDE_FP32) enqueue_fd_t<true, PREC_F32>(h, h->d_step);
+    else enqueue_fd_t<true, PREC_F64>(h, h->d_step);
+  } else {
+    if (h->phys.precision == DPDE_FP32) enqueue_fd_t<false, PREC_F32>(h, h->d_step);
+    else enqueue_fd_t<false, PREC_F64>(h, h->d_step);
+  }
+}
+
+void enqueue_stats(dpde_handle* h, int advance) {
+  launch(h, "stats_tiles", k_stats_tiles, h->ntiles, kStatThreads, h->cur, (const double*)h->Ui,
+         (const int64_t*)h->tile_begin, h->phys, h->partials);
+  launch(h, "stats_final", k_stats_final, h->nrep, kStatThreads, (const double*)h->partials,
+         (const int32_t*)h->rep_tile0, (const Geo*)h->geo, (const uint64_t*)h->d_step, advance,
+         h->rec, h->hist, h->hist_cap, (const int64_t*)h->d_hist_count, h->nrep);
+  if (advance)
+    launch(h, "step_advance", k_step_advance, 1, 1, h->d_step, h->d_hist_count,
+           (const uint32_t*)h->status);
+}
+
+void enqueue_step(dpde_handle* h) {
+  enqueue_bin(h, 1);
+  enqueue_forces(h, 1);
+  enqueue_fd(h);
+  enqueue_stats(h, 1);
+}
+
+// Bin, forces, temperatures and observables of the current state.
+int prepare(dpde_handle* h) {
+  HIPCHK(hipMemcpyAsync(h->d_step, &h->step, sizeof(uint64_t), hipMemcpyHostToDevice, h->stream));
+  enqueue_bin(h, 0);
+  enqueue_forces(h, 0);
+  if (eos_inline(h)) {
+    launch(h, "inv_temperature", k_inv_temperature, blocks(h->n, h->aux_block), h->aux_block,
+           h->cur, h->n, h->phys, h->status);
+  } else {
+    enqueue_theta_mlp(h->mlp, h->stream, h->cur.eps, h->cur.invT, h->n, h->phys, h->status);
+  }
+  enqueue_stats(h, 0);
+  uint32_t st = 0;
+  HIPCHK(hipMemcpyAsync(&st, h->status, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  if (st) {
+    int rc = status_to_code(st);
+    HIPCHK(hipMemset(h->status, 0, sizeof(uint32_t)));
+    return rc;
+  }
+  return DPDE_OK;
+}
+
+int load(dpde_handle* h, const double* q, const double* p, const double* eps) {
+  if (!q || !p || !eps) return fail(DPDE_EINVAL, "q, p and eps must be device pointers");
+  HIPCHK(hipStreamSynchronize(h->user_stream));
+  HIPCHK(hipMemsetAsync(h->status, 0, sizeof(uint32_t), h->stream));
+  launch(h, "load_state", k_load_state, blocks(h->n, 256), 256, q, p, eps, (const Geo*)h->geo,
+         h->nrep, h->n, h->cur, h->status);
+  uint32_t st = 0;
+  HIPCHK(hipMemcpyAsync(&st, h->status, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  if (st & ST_NONFINITE) {
+    HIPCHK(hipMemset(h->status, 0, sizeof(uint32_t)));
+    return fail(DPDE_EINVAL, "non-finite value in the initial state");
+  }
+  if (st) {
+    HIPCHK(hipMemset(h->status, 0, sizeof(uint32_t)));
+    return status_to_code(st);
+  }
+  return DPDE_OK;
+}
+
+void release(dpde_handle* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  for (auto& r : h->prof) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : h->event_pool) (void)hipEventDestroy(e);
+  mlp_release(h->mlp);
+  for (void* p : h->allocations) (void)hipFree(p);
+  if (h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+int create(const dpde_params* params, int nrep, const int64_t* offsets, const double* q,
+           const double* p, const double* eps, void* stream, dpde_handle** out) {
+  if (!out) return fail(DPDE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nrep < 1) return fail(DPDE_EINVAL, "nrep must be >= 1");
+  int rc = check_params(params, true);
+  if (rc) return rc;
+  dpde_handle* h = new (std::nothrow) dpde_handle();
+  if (!h) return fail(DPDE_ENOMEM, "host allocation failed");
+  h->nrep = nrep;
+  h->batch = nrep > 1;
+  h->user_stream = (hipStream_t)stream;
+  physics(&params[0], h->phys);
+  h->step = params[0].step0;
+  h->offsets.assign(offsets, offsets + nrep + 1);
+  if (h->offsets[0] != 0) { release(h); return fail(DPDE_EINVAL, "offsets[0] must be 0"); }
+  int64_t cells = 0;
+  for (int r = 0; r < nrep; ++r) {
+    if ((rc = check_params(&params[r], r == 0))) { release(h); return rc; }
+    if (h->offsets[r + 1] - h->offsets[r] != params[r].n) {
+      release(h);
+      return fail(DPDE_EINVAL, "offsets[%d+1]-offsets[%d] != params[%d].n", r, r, r);
+    }
+    if (r > 0 && (params[r].mass != params[0].mass || params[r].rc != params[0].rc ||
+                  params[r].a != params[0].a || params[r].gamma != params[0].gamma ||
+                  params[r].kT_ref != params[0].kT_ref || params[r].dt != params[0].dt ||
+                  params[r].eos != params[0].eos || params[r].precision != params[0].precision ||
+                  params[r].scheme != params[0].scheme || params[r].step0 != params[0].step0)) {
+      release(h);
+      return fail(DPDE_EINVAL, "replica %d: physical parameters differ from replica 0", r);
+    }
+    Geo g{};
+    if ((rc = geometry(&params[r], g))) { release(h); return rc; }
+    g.cell_base = cells;
+    g.first = h->offsets[r];
+    g.n = params[r].n;
+    cells += (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+    h->geo_h.push_back(g);
+  }
+  h->n = h->offsets[nrep];
+  h->ncells = cells;
+  if (cells >= ((int64_t)1 << 31)) { release(h); return fail(DPDE_EINVAL, "too many cells"); }
+  if (hipGetDevice(&h->device) != hipSuccess) { release(h); return fail(DPDE_EHIP, "no HIP device"); }
+  if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+    release(h);
+    return fail(DPDE_EHIP, "hipStreamCreateWithFlags failed");
+  }
+  if ((rc = allocate(h))) { release(h); return rc; }
+  if ((rc = load(h, q, p, eps))) { release(h); return rc; }
+  if ((rc = prepare(h))) { release(h); return rc; }
+  *out = h;
+  return DPDE_OK;
+}
+
+int read_status(dpde_handle* h) {
+  uint32_t st = 0;
+  HIPCHK(hipMemcpyAsync(&st, h->status, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  if (st) return status_to_code(st);
+  return DPDE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dpde_last_error(void) { return g_last_error.c_str(); }
+
+int dpde_init(const dpde_params* params, const double* q, const double* p, const double* eps,
+              void* hip_stream, dpde_handle** out) {
+  if (!params) return fail(DPDE_EINVAL, "params is NULL");
+  const int64_t offs[2] = {0, params->n};
+  return create(params, 1, offs, q, p, eps, hip_stream, out);
+}
+
+int dpde_init_batch(const dpde_params* params, int32_t nrep, const int64_t* offsets,
+                    const double* q, const double* p, const double* eps, void* hip_stream,
+                    dpde_handle** out) {
+  if (!params || !offsets) return fail(DPDE_EINVAL, "params and offsets must not be NULL");
+  return create(params, nrep, offsets, q, p, eps, hip_stream, out);
+}
+
+int dpde_free(dpde_handle* h) {
+  release(h);
+  return DPDE_OK;
+}
+
+void* dpde_stream(dpde_handle* h) { return h ? (void*)h->stream : nullptr; }
+
+int dpde_step(dpde_handle* h, int64_t nsteps) {
+  if (!h) return fail(DPDE_EINVAL, "handle is NULL");
+  if (nsteps < 0) return fail(DPDE_EINVAL, "nsteps < 0");
+  for (int64_t s = 0; s < nsteps; ++s) enqueue_step(h);
+  HIPCHK(hipGetLastError());
+  int rc = read_status(h);
+  // device step counter is the truth (a failing step stops the counter)
+  uint64_t st = 0;
+  HIPCHK(hipMemcpy(&st, h->d_step, sizeof(uint64_t), hipMemcpyDeviceToHost));
+  h->step = (int64_t)st;
+  return rc;
+}
+
+int dpde_step_graph(dpde_handle* h, int64_t nsteps, int64_t reps) {
+  if (!h) return fail(DPDE_EINVAL, "handle is NULL");
+  if (nsteps <= 0 || (nsteps % 2) != 0 || reps < 0)
+    return fail(DPDE_EINVAL, "nsteps must be even and > 0, reps >= 0");
+  if (h->graph_exec == nullptr || h->graph_steps != nsteps) {
+    if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
+    if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+    const bool prof = h->profiling;
+    h->profiling = false;
+    HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    // each step swaps the two state buffers; an even count ends where it began,
+    // so every replay starts from the same buffers the capture saw
+    for (int64_t s = 0; s < nsteps; ++s) enqueue_step(h);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    h->profiling = prof;
+    if (e != hipSuccess) return fail(DPDE_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    h->graph = g;
+    HIPCHK(hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0));
+    h->graph_steps = nsteps;
+  }
+  for (int64_t r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(h->graph_exec, h->stream));
+  int rc = read_status(h);
+  uint64_t st = 0;
+  HIPCHK(hipMemcpy(&st, h->d_step, sizeof(uint64_t), hipMemcpyDeviceToHost));
+  h->step = (int64_t)st;
+  return rc;
+}
+
+int dpde_energies(dpde_handle* h, double out[10]) {
+  if (!h || !out) return fail(DPDE_EINVAL, "NULL argument");
+  HIPCHK(hipMemcpyAsync(out, h->rec, 10 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DPDE_OK;
+}
+
+int dpde_energies_batch(dpde_handle* h, double* out) {
+  if (!h || !out) return fail(DPDE_EINVAL, "NULL argument");
+  HIPCHK(hipMemcpyAsync(out, h->rec, (size_t)h->nrep * 10 * sizeof(double), hipMemcpyDeviceToHost,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DPDE_OK;
+}
+
+int dpde_history(dpde_handle* h, double* out, int64_t cap, int64_t* count) {
+  if (!h || !count) return fail(DPDE_EINVAL, "NULL argument");
+  int64_t total = 0;
+  HIPCHK(hipMemcpyAsync(&total, h->d_hist_count, sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const int64_t held = std::min(total, h->hist_cap);
+  const int64_t first = total - held;  // oldest record still held
+  const int64_t take = std::min(held, cap);
+  const size_t rec_doubles = (size_t)h->nrep * 10;
+  if (out && take > 0) {
+    std::vector<double> buf((size_t)h->hist_cap * rec_doubles);
+    HIPCHK(hipMemcpy(buf.data(), h->hist, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < take; ++k) {
+      const int64_t slot = (first + k) % h->hist_cap;
+      std::memcpy(out + k * rec_doubles, buf.data() + slot * rec_doubles,
+                  rec_doubles * sizeof(double));
+    }
+  }
+  *count = take;
+  HIPCHK(hipMemset(h->d_hist_count, 0, sizeof(int64_t)));
+  return DPDE_OK;
+}
+
+int dpde_get_state(dpde_handle* h, double* q, double* p, double* eps, int64_t* step) {
+  if (!h) return fail(DPDE_EINVAL, "handle is NULL");
+  if (q || p || eps) {
+    if (h->batch)
+      launch(h, "store_state", k_store_state<true>, blocks(h->n, 256), 256, h->cur,
+             (const Geo*)h->geo, h->n, q, p, eps);
+    else
+      launch(h, "store_state", k_store_state<false>, blocks(h->n, 256), 256, h->cur,
+             (const Geo*)h->geo, h->n, q, p, eps);
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  if (step) *step = h->step;
+  return DPDE_OK;
+}
+
+int dpde_set_state(dpde_handle* h, const double* q, const double* p, const double* eps,
+                   int64_t step) {
+  if (!h) return fail(DPDE_EINVAL, "handle is NULL");
+  int rc = load(h, q, p, eps);
+  if (rc) return rc;
+  h->step = step;
+  return prepare(h);
+}
+
+int dpde_forces(dpde_handle* h, double* F, double* U) {
+  if (!h || !F) return fail(DPDE_EINVAL, "NULL argument");
+  if (h->batch)
+    launch(h, "store_forces", k_store_vec3<true>, blocks(h->n, 256), 256, h->cur,
+           (const Geo*)h->geo, h->n, (const double*)h->Fx, (const double*)h->Fy,
+           (const double*)h->Fz, F);
+  else
+    launch(h, "store_forces", k_store_vec3<false>, blocks(h->n, 256), 256, h->cur,
+           (const Geo*)h->geo, h->n, (const double*)h->Fx, (const double*)h->Fy,
+           (const double*)h->Fz, F);
+  double rec[10];
+  HIPCHK(hipMemcpyAsync(rec, h->rec, sizeof(rec), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  if (U) *U = rec[0];
+  return DPDE_OK;
+}
+
+int dpde_set_tuning(dpde_handle* h, int32_t pair_block, int32_t aux_block) {
+  if (!h) return fail(DPDE_EINVAL, "handle is NULL");
+  auto ok = [](int b, int mx) { return b >= 64 && b <= mx && (b % 64) == 0; };
+  if (!ok(pair_block, kPairBlockMax) || !ok(aux_block, 1024))
+    return fail(DPDE_EINVAL, "block sizes must be multiples of 64 within the kernel limits");
+  h->pair_block = pair_block;
+  h->aux_block = aux_block;
+  if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
+  if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+  return DPDE_OK;
+}
+
+int dpde_profile_enable(dpde_handle* h, int32_t enable) {
+  if (!h) return fail(DPDE_EINVAL, "handle is NULL");
+  h->profiling = enable != 0;
+  return DPDE_OK;
+}
+
+int dpde_profile_read(dpde_handle* h, char* names, double* total_ms, int64_t* launches,
+                      int32_t nmax) {
+  if (!h) return fail(DPDE_EINVAL, "handle is NULL");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  std::vector<std::string> order;
+  std::map<std::string, std::pair<double, int64_t>> acc;
+  for (auto& r : h->prof) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    auto it = acc.find(r.name);
+    if (it == acc.end()) {
+      order.push_back(r.name);
+      acc[r.name] = {ms, 1};
+    } else {
+      it->second.first += ms;
+      it->second.second += 1;
+    }
+    h->event_pool.push_back(r.a);
+    h->event_pool.push_back(r.b);
+  }
+  h->prof.clear();
+  int k = 0;
+  for (auto& nm : order) {
+    if (k >= nmax) break;
+    if (names) {
+      std::memset(names + 32 * k, 0, 32);
+      std::strncpy(names + 32 * k, nm.c_str(), 31);
+    }
+    if (total_ms) total_ms[k] = acc[nm].first;
+    if (launches) launches[k] = acc[nm].second;
+    ++k;
+  }
+  return k;
+}
+
+int dpde_theta(dpde_handle* h, const double* eps, double* theta, int32_t* iters, int64_t n,
+               int32_t mode) {
+  if (!h || !eps || !theta) return fail(DPDE_EINVAL, "NULL argument");
+  if (n < 0 || mode < 0 || mode > 2) return fail(DPDE_EINVAL, "bad n or mode");
+  if (mode != DPDE_THETA_NEWTON && !h->mlp.trained)
+    return fail(DPDE_EINVAL, "the surrogate has not been trained or set");
+  launch_theta(h->mlp, h->stream, eps, theta, iters, n, h->phys, mode);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  return DPDE_OK;
+}
+
+int dpde_eos_energy(dpde_handle* h, const double* theta, double* eps, int64_t n) {
+  if (!h || !theta || !eps) return fail(DPDE_EINVAL, "NULL argument");
+  launch(h, "eos_energy", k_eos_energy, blocks(n, 256), 256, theta, eps, n, h->phys);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  return DPDE_OK;
+}
+
+int dpde_mlp_train(dpde_handle* h, const dpde_mlp_cfg* cfg, float* loss_curve) {
+  if (!h || !cfg) return fail(DPDE_EINVAL, "NULL argument");
+  if (h->phys.eos != DPDE_EOS_EINSTEIN)
+    return fail(DPDE_EINVAL, "the surrogate is for the nonlinear (Einstein) EOS");
+  std::string err;
+  int rc = mlp_train(h->mlp, h->stream, h->phys, *cfg, loss_curve, err);
+  if (rc) return fail(rc, "%s", err.c_str());
+  mlp_attach(h->mlp, h->phys);
+  return DPDE_OK;
+}
+
+int dpde_mlp_get(dpde_handle* h, float* weights, double* norm4) {
+  if (!h) return fail(DPDE_EINVAL, "NULL argument");
+  std::string err;
+  int rc = mlp_get(h->mlp, weights, norm4, err);
+  return rc ? fail(rc, "%s", err.c_str()) : DPDE_OK;
+}
+
+int dpde_mlp_set(dpde_handle* h, const float* weights, const double* norm4) {
+  if (!h || !weights || !norm4) return fail(DPDE_EINVAL, "NULL argument");
+  std::string err;
+  int rc = mlp_set(h->mlp, h->phys, weights, norm4, err);
+  if (rc) return fail(rc, "%s", err.c_str());
+  mlp_attach(h->mlp, h->phys);
+  return DPDE_OK;
+}
+
+int dpde_mlp_grad(dpde_handle* h, const float* x, const float* t, int64_t n, float* loss,
+                  float* grad) {
+  if (!h || !x || !t || !loss || !grad) return fail(DPDE_EINVAL, "NULL argument");
+  std::string err;
+  int rc = mlp_grad(h->mlp, h->stream, x, t, n, loss, grad, err);
+  return rc ? fail(rc, "%s", err.c_str()) : DPDE_OK;
+}
+
+int dpde_mlp_eval(dpde_handle* h, const float* x, float* y, int64_t n) {
+  if (!h || !x || !y) return fail(DPDE_EINVAL, "NULL argument");
+  std::string err;
+  int rc = mlp_eval(h->mlp, h->stream, x, y, n, err);
+  return rc ? fail(rc, "%s", err.c_str()) : DPDE_OK;
+}
+
+int dpde_debug_cells(dpde_handle* h, int32_t* cell_of_id) {
+  if (!h || !cell_of_id) return fail(DPDE_EINVAL, "NULL argument");
+  if (h->batch)
+    launch(h, "debug_cells", k_debug_cells<true>, blocks(h->n, 256), 256, h->cur, h->n,
+           (const Geo*)h->geo, cell_of_id);
+  else
+    launch(h, "debug_cells", k_debug_cells<false>, blocks(h->n, 256), 256, h->cur, h->n,
+           (const Geo*)h->geo, cell_of_id);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  return DPDE_OK;
+}
+
+int dpde_debug_pairs(dpde_handle* h, int32_t* lohi, int64_t cap, int64_t* npairs) {
+  if (!h || !npairs || (cap > 0 && !lohi)) return fail(DPDE_EINVAL, "NULL argument");
+  HIPCHK(hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream));
+  if (h->batch)
+    launch(h, "debug_pairs", k_debug_pairs<true>, blocks(h->n, 256), 256, h->cur, h->nl, h->n,
+           (const Geo*)h->geo, lohi, cap, h->counter);
+  else
+    launch(h, "debug_pairs", k_debug_pairs<false>, blocks(h->n, 256), 256, h->cur, h->nl, h->n,
+           (const Geo*)h->geo, lohi, cap, h->counter);
+  unsigned long long c = 0;
+  HIPCHK(hipMemcpyAsync(&c, h->counter, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  *npairs = (int64_t)c;
+  return DPDE_OK;
+}
+
+int dpde_debug_rng(uint64_t seed, uint32_t replica, int64_t step, const uint32_t* lo,
+                   const uint32_t* hi, int64_t n, uint32_t* raw, double* g, float* g32) {
+  if (!lo || !hi || n < 0) return fail(DPDE_EINVAL, "bad argument");
+  if (n == 0) return DPDE_OK;
+  hipLaunchKernelGGL(k_debug_rng, dim3(blocks(n, 256)), dim3(256), 0, nullptr, (uint32_t)seed,
+                     (uint32_t)(seed >> 32) ^ replica, (uint64_t)step, lo, hi, n, raw, g, g32);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipDeviceSynchronize());
+  return DPDE_OK;
+}
+
+}  // extern "C"

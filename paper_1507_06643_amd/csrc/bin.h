@@ -1,0 +1,260 @@
+// Cell binning: particles are kept sorted by the composite key (cell, id).
+//
+// Sort = two-level MSD radix sort.  Digit 1 is the whole cell index (one
+// counting pass: histogram of cells with integer atomics, exclusive scan to
+// cell offsets, scatter by offset + arrival ticket); digit 2 is the particle
+// identifier, finished inside each cell bucket by insertion sort (buckets
+// hold ~3 particles at density 3 with cells of side ~rc).  The resulting order
+// is a pure function of the positions, independent of the previous order and
+// of atomic arrival order, so trajectories are bit reproducible and a resumed
+// run continues exactly.
+#pragma once
+
+#include "common.h"
+
+namespace dpde {
+
+// Structure-of-arrays particle state in storage (cell-sorted) order.
+struct PState {
+  double *qx, *qy, *qz;
+  double *px, *py, *pz;
+  double *eps, *invT;
+  uint32_t* id;   // identifier inside the replica
+  uint32_t* rep;  // replica index (batched handles)
+};
+
+template <bool BATCH>
+__device__ __forceinline__ int rep_of(const PState& s, int64_t i) {
+  if constexpr (BATCH) return (int)s.rep[i];
+  return 0;
+}
+
+// ---- initial load: AoS rows in identifier order -> SoA ---------------------
+// Row k belongs to the replica r with geo[r].first <= k < geo[r].first + n.
+__global__ void k_load_state(const double* __restrict__ q, const double* __restrict__ p,
+                             const double* __restrict__ eps, const Geo* __restrict__ geo, int nrep,
+                             int64_t n, PState s, uint32_t* status) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int lo = 0, hi = nrep - 1;
+  while (lo < hi) {  // last replica whose first row <= k
+    const int mid = (lo + hi + 1) >> 1;
+    if (geo[mid].first <= k) lo = mid; else hi = mid - 1;
+  }
+  const double x = q[3 * k], y = q[3 * k + 1], z = q[3 * k + 2];
+  const double a = p[3 * k], b = p[3 * k + 1], c = p[3 * k + 2];
+  const double e = eps[k];
+  s.qx[k] = x; s.qy[k] = y; s.qz[k] = z;
+  s.px[k] = a; s.py[k] = b; s.pz[k] = c;
+  s.eps[k] = e;
+  s.invT[k] = 0.0;
+  s.id[k] = (uint32_t)(k - geo[lo].first);
+  if (s.rep) s.rep[k] = (uint32_t)lo;
+  const bool fin = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(a) && isfinite(b) &&
+                   isfinite(c) && isfinite(e);
+  if (!fin) atomicOr(status, ST_NONFINITE);
+  else if (!(e > 0.0)) atomicOr(status, ST_NEG_EINT);
+}
+
+// ---- state out: SoA storage order -> AoS rows in identifier order ------------
+template <bool BATCH>
+__global__ void k_store_state(PState s, const Geo* __restrict__ geo, int64_t n, double* q,
+                              double* p, double* eps) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t row = geo[rep_of<BATCH>(s, i)].first + (int64_t)s.id[i];
+  if (q) { q[3 * row] = s.qx[i]; q[3 * row + 1] = s.qy[i]; q[3 * row + 2] = s.qz[i]; }
+  if (p) { p[3 * row] = s.px[i]; p[3 * row + 1] = s.py[i]; p[3 * row + 2] = s.pz[i]; }
+  if (eps) eps[row] = s.eps[i];
+}
+
+template <bool BATCH>
+__global__ void k_store_vec3(PState s, const Geo* __restrict__ geo, int64_t n,
+                             const double* __restrict__ x, const double* __restrict__ y,
+                             const double* __restrict__ z, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t row = geo[rep_of<BATCH>(s, i)].first + (int64_t)s.id[i];
+  out[3 * row] = x[i]; out[3 * row + 1] = y[i]; out[3 * row + 2] = z[i];
+}
+
+// ---- digit 1: kick, drift, wrap, cell key, histogram ------------------------
+// With kick != 0 this is the first half of velocity-Verlet (Sec. 3.1):
+// p += dt/2 F, q += dt p / m, then periodic wrap into [0, L).
+template <bool BATCH>
+__global__ void k_kick_drift_key(PState s, const double* __restrict__ Fx,
+                                 const double* __restrict__ Fy, const double* __restrict__ Fz,
+                                 int64_t n, const Geo* __restrict__ geo, Phys P, int kick,
+                                 uint32_t* __restrict__ key, uint32_t* __restrict__ ticket,
+                                 uint32_t* __restrict__ count, uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (status_set(status)) return;
+  const Geo& g = geo[rep_of<BATCH>(s, i)];
+  double q[3] = {s.qx[i], s.qy[i], s.qz[i]};
+  if (kick) {
+    double p[3] = {s.px[i], s.py[i], s.pz[i]};
+    const double F[3] = {Fx[i], Fy[i], Fz[i]};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      p[d] = p[d] + P.half_dt * F[d];
+      q[d] = q[d] + P.dt * p[d] / P.mass;
+    }
+    s.px[i] = p[0]; s.py[i] = p[1]; s.pz[i] = p[2];
+    if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) atomicOr(status, ST_NONFINITE);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (g.periodic[d]) q[d] = wrap_coord(q[d], g.box[d]);
+  s.qx[i] = q[0]; s.qy[i] = q[1]; s.qz[i] = q[2];
+  if (!(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]))) atomicOr(status, ST_NONFINITE);
+  const int cx = cell_coord(q[0], g.scale[0], g.nc[0]);
+  const int cy = cell_coord(q[1], g.scale[1], g.nc[1]);
+  const int cz = cell_coord(q[2], g.scale[2], g.nc[2]);
+  const uint32_t c = (uint32_t)(g.cell_base + cx + (int64_t)g.nc[0] * (cy + (int64_t)g.nc[1] * cz));
+  key[i] = c;
+  ticket[i] = atomicAdd(&count[c], 1u);
+}
+
+// ---- exclusive scan of the cell histogram -> cell offsets --------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Exclusive scan of one value per thread across the block; returns the block
+// total through *total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* smem,
+                                                         uint32_t* total) {
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  if (lane == kWave - 1) smem[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < nw; ++w) {
+      const uint32_t t = smem[w];
+      smem[w] = run;
+      run += t;
+    }
+    smem[nw] = run;
+  }
+  __syncthreads();
+  const uint32_t excl = smem[wid] + x - v;
+  *total = smem[nw];
+  __syncthreads();
+  return excl;
+}
+
+__global__ void k_scan_tiles(const uint32_t* __restrict__ in, int64_t n,
+                             uint32_t* __restrict__ tile_sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += in[base + k];
+  __shared__ uint32_t smem[kScanThreads / kWave + 1];
+  uint32_t total;
+  block_exclusive_scan(s, smem, &total);
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// One block: exclusive scan of the tile sums in place (ntiles <= 1024*8);
+// the grand total goes to tile_sums[ntiles].
+__global__ void k_scan_tile_sums(uint32_t* tile_sums, int ntiles) {
+  const int per = (ntiles + blockDim.x - 1) / blockDim.x;
+  const int b = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int k = 0; k < per; ++k)
+    if (b + k < ntiles) s += tile_sums[b + k];
+  __shared__ uint32_t smem[1024 / kWave + 1];
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(s, smem, &total);
+  for (int k = 0; k < per; ++k)
+    if (b + k < ntiles) {
+      const uint32_t t = tile_sums[b + k];
+      tile_sums[b + k] = run;
+      run += t;
+    }
+  if (threadIdx.x == 0) tile_sums[ntiles] = total;
+}
+
+// out[c] = sum_{c' < c} in[c'] for c <= n; the histogram is cleared for the
+// next step.
+__global__ void k_scan_apply(uint32_t* __restrict__ in, int64_t n,
+                             const uint32_t* __restrict__ tile_sums, uint32_t* __restrict__ out) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0u;
+    s += v[k];
+  }
+  __shared__ uint32_t smem[kScanThreads / kWave + 1];
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(s, smem, &total) + tile_sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) {
+      out[base + k] = run;
+      in[base + k] = 0u;
+    }
+    run += v[k];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tile_sums[gridDim.x];
+}
+
+// perm[offset[key] + ticket] = old slot.
+__global__ void k_scatter(const uint32_t* __restrict__ key, const uint32_t* __restrict__ ticket,
+                          const uint32_t* __restrict__ start, int64_t n,
+                          uint32_t* __restrict__ perm, const uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (status_set(status)) return;
+  perm[start[key[i]] + ticket[i]] = (uint32_t)i;
+}
+
+// ---- digit 2: order each cell bucket by identifier ---------------------------
+__global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncells,
+                            uint32_t* __restrict__ perm, const uint32_t* __restrict__ id,
+                            const uint32_t* status) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  if (status_set(status)) return;
+  const uint32_t b = start[c], e = start[c + 1];
+  for (uint32_t k = b + 1; k < e; ++k) {
+    const uint32_t v = perm[k];
+    const uint32_t kv = id[v];
+    uint32_t m = k;
+    while (m > b) {
+      const uint32_t u = perm[m - 1];
+      if (id[u] <= kv) break;
+      perm[m] = u;
+      --m;
+    }
+    perm[m] = v;
+  }
+}
+
+// ---- gather into the new order -----------------------------------------------
+// After a device error the order is kept (identity copy), so the state of the
+// failing step survives the buffer swap.
+__global__ void k_gather(PState src, PState dst, const uint32_t* __restrict__ perm, int64_t n,
+                         const uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = status_set(status) ? (uint32_t)i : perm[i];
+  dst.qx[i] = src.qx[k]; dst.qy[i] = src.qy[k]; dst.qz[i] = src.qz[k];
+  dst.px[i] = src.px[k]; dst.py[i] = src.py[k]; dst.pz[i] = src.pz[k];
+  dst.eps[i] = src.eps[k];
+  dst.invT[i] = src.invT[k];
+  dst.id[i] = src.id[k];
+  if (dst.rep) dst.rep[i] = src.rep[k];
+}
+
+}  // namespace dpde

@@ -1,0 +1,187 @@
+// Device-side building blocks shared by the DPDE kernels: system descriptors,
+// the counter-based pair noise, box geometry and deterministic reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dpde {
+
+constexpr int kWave = 64;
+
+// Device status word bits (sticky for the rest of a dpde_step call).
+enum : uint32_t {
+  ST_NEG_EINT = 1u,   // eps_i <= 0 or T_i <= 0
+  ST_OVERFLOW = 2u,   // neighbour list capacity exceeded
+  ST_NONFINITE = 4u,  // NaN/Inf in positions or momenta
+  ST_EOS = 8u,        // temperature inversion failed
+};
+
+// Geometry and noise key of one system (replica).
+struct Geo {
+  double box[3];
+  double half_box[3];
+  double scale[3];     // cells per unit length: nc / box
+  int32_t nc[3];
+  int32_t periodic[3];
+  int64_t cell_base;   // global index of the replica's cell 0
+  int64_t first;       // first row (identifier space) of the replica
+  int64_t n;           // particles in the replica
+  uint32_t key0, key1; // Philox key: seed low word, seed high word ^ replica
+};
+
+// Physical parameters shared by all replicas of a handle.
+struct Phys {
+  double mass, inv_mass, inv_2m;
+  double rc, inv_rc, rc2;
+  double a, half_a_rc;      // force amplitude, potential prefactor a rc / 2
+  double gkT_half;          // gamma kT_ref / 2: gamma_ij = gkT_half (1/T_i + 1/T_j)
+  double sigma, dt, half_dt, sqrt_dt;
+  double dsigma2_m;         // d sigma^2 / m (SEM internal-energy drift)
+  double cv, eos_n, eos_omega, eos_c0;
+  double mlp_in_c, mlp_in_s, mlp_out_c, mlp_out_s, mlp_eps_lo, mlp_eps_hi;
+  int32_t eos, theta_mode, precision, scheme;
+  int32_t cap;              // neighbour list capacity per particle
+  int32_t pad_;
+};
+
+// -------------------------------------------------------------------------
+// Pair noise G_ij^n: Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// with counter (lo id, hi id, n_lo, n_hi) and the replica key, then
+// Box-Muller.  The noise is a pure function of (key, lo, hi, n), which is
+// what lets the second SER sweep regenerate the first sweep's increments
+// (Sec. 3.2.1).
+// -------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2,
+                                              uint32_t& x3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t m0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    const uint64_t m1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    const uint32_t y0 = (uint32_t)(m1 >> 32) ^ x1 ^ k0;
+    const uint32_t y2 = (uint32_t)(m0 >> 32) ^ x3 ^ k1;
+    x1 = (uint32_t)m1;
+    x3 = (uint32_t)m0;
+    x0 = y0;
+    x2 = y2;
+  }
+}
+
+__device__ __forceinline__ void pair_words(const Geo& g, uint32_t lo, uint32_t hi, uint64_t step,
+                                           uint32_t w[4]) {
+  w[0] = lo;
+  w[1] = hi;
+  w[2] = (uint32_t)step;
+  w[3] = (uint32_t)(step >> 32);
+  philox4x32_10(w[0], w[1], w[2], w[3], g.key0, g.key1);
+}
+
+// FP64 normals from the four words: u = (x + 1/2) 2^-32 in (0,1).
+__device__ __forceinline__ void box_muller_f64(const uint32_t w[4], double G[3]) {
+  const double s = 2.3283064365386963e-10;  // 2^-32
+  const double u0 = ((double)w[0] + 0.5) * s;
+  const double u1 = ((double)w[1] + 0.5) * s;
+  const double u2 = ((double)w[2] + 0.5) * s;
+  const double u3 = ((double)w[3] + 0.5) * s;
+  const double r1 = sqrt(-2.0 * log(u0));
+  const double r2 = sqrt(-2.0 * log(u2));
+  double sn, cs;
+  sincospi(2.0 * u1, &sn, &cs);
+  G[0] = r1 * cs;
+  G[1] = r1 * sn;
+  G[2] = r2 * cospi(2.0 * u3);
+}
+
+// FP32 normals from the same words: the top 24 bits give u in (0,1) exactly;
+// the hardware sine/cosine take their argument in turns, so sin(2 pi u) is
+// one instruction.
+__device__ __forceinline__ void box_muller_f32(const uint32_t w[4], float G[3]) {
+  const float s = 5.9604644775390625e-08f;  // 2^-24
+  const float h = 2.98023223876953125e-08f; // 2^-25
+  const float u0 = (float)(w[0] >> 8) * s + h;
+  const float u1 = (float)(w[1] >> 8) * s + h;
+  const float u2 = (float)(w[2] >> 8) * s + h;
+  const float u3 = (float)(w[3] >> 8) * s + h;
+  const float ln2x2 = -1.3862943611198906f;  // -2 ln 2: -2 ln u = -2 ln2 log2 u
+  const float r1 = __builtin_sqrtf(ln2x2 * __builtin_amdgcn_logf(u0));
+  const float r2 = __builtin_sqrtf(ln2x2 * __builtin_amdgcn_logf(u2));
+  G[0] = r1 * __builtin_amdgcn_cosf(u1);
+  G[1] = r1 * __builtin_amdgcn_sinf(u1);
+  G[2] = r2 * __builtin_amdgcn_cosf(u3);
+}
+
+// -------------------------------------------------------------------------
+// Geometry.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ double wrap_coord(double x, double L) {
+  if (x < 0.0 || x >= L) {
+    x = x - L * floor(x / L);
+    if (x >= L) x = 0.0;
+  }
+  return x;
+}
+
+__device__ __forceinline__ double min_image(double d, double L, double halfL) {
+  if (d > halfL) d -= L;
+  else if (d < -halfL) d += L;
+  return d;
+}
+
+// r^2 evaluated as (dx*dx + dy*dy) + dz*dz with no fused multiply-add, so the
+// pair predicate r^2 < rc^2 is an exact function of the positions.
+__device__ __forceinline__ double dist2(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  const double xx = dx * dx;
+  const double yy = dy * dy;
+  const double zz = dz * dz;
+  return (xx + yy) + zz;
+}
+
+__device__ __forceinline__ int cell_coord(double x, double scale, int nc) {
+  double c = floor(x * scale);
+  c = (c >= 0.0) ? c : 0.0;  // also maps NaN to 0 so indices stay in range
+  c = (c <= (double)(nc - 1)) ? c : (double)(nc - 1);
+  return (int)c;
+}
+
+// -------------------------------------------------------------------------
+// Deterministic reductions: xor-butterfly inside a wave (every lane ends with
+// the same bits), then waves combined in index order by one thread.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* smem /* NV * nwaves */) {
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) smem[k * nw + wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += smem[k * nw + w];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool status_set(const uint32_t* status) { return *status != 0u; }
+
+}  // namespace dpde

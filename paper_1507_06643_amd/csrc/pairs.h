@@ -1,0 +1,499 @@
+// Pair passes of one DPDE step over cell-sorted particles.
+//
+//   pass A  conservative forces at the new positions, neighbour list build,
+//           second half-kick of velocity-Verlet (Sec. 3.1);
+//   pass B  SER sweep 1: dp_i = sum_j dp_ij (eq. SER_p);
+//   pass C  SER sweep 2: regenerate dp_ij from the same counter-based noise,
+//           internal-energy reinjection (eq. SER_eint_discretization),
+//           p <- p + dp, eps <- eps + d eps, next 1/T_i.
+//
+// One lane per particle; each pair term is evaluated on both of its
+// particles' lanes in the canonical orientation (lower identifier first) and
+// negated on the higher one, so dp_ji = -dp_ij bit for bit and the particle
+// sums are plain gathers: no atomics, fixed summation order.
+#pragma once
+
+#include "bin.h"
+#include "eos.h"
+
+namespace dpde {
+
+constexpr int kPairBlockMax = 256;
+
+enum : int { PREC_F64 = 0, PREC_F32 = 1 };
+
+// Neighbour list: k-major (entry k of particle i at k*n + i), so the lanes of
+// a wave read consecutive words.
+struct NList {
+  uint32_t* idx;
+  uint32_t* count;
+  int64_t stride;  // n
+};
+
+// Up to two contiguous cell ranges along x for the stencil row (y, z).
+struct Row {
+  int a0, b0, a1, b1;  // inclusive cell x-ranges; a1 > b1 means "no second range"
+};
+
+__device__ __forceinline__ Row stencil_row(int cx, int nc, int periodic) {
+  Row r;
+  r.a1 = 1;
+  r.b1 = 0;
+  if (periodic) {
+    if (cx == 0) { r.a0 = 0; r.b0 = 1; r.a1 = nc - 1; r.b1 = nc - 1; }
+    else if (cx == nc - 1) { r.a0 = nc - 2; r.b0 = nc - 1; r.a1 = 0; r.b1 = 0; }
+    else { r.a0 = cx - 1; r.b0 = cx + 1; }
+  } else {
+    r.a0 = cx > 0 ? cx - 1 : 0;
+    r.b0 = cx < nc - 1 ? cx + 1 : nc - 1;
+  }
+  return r;
+}
+
+__device__ __forceinline__ bool wrap_cell(int& c, int nc, int periodic) {
+  if (c < 0) {
+    if (!periodic) return false;
+    c += nc;
+  } else if (c >= nc) {
+    if (!periodic) return false;
+    c -= nc;
+  }
+  return true;
+}
+
+// Visit every particle j of the 27 cells around (cx, cy, cz).
+template <typename F>
+__device__ __forceinline__ void for_each_candidate(const Geo& g, const uint32_t* __restrict__ start,
+                                                   int cx, int cy, int cz, F&& f) {
+  const Row row = stencil_row(cx, g.nc[0], g.periodic[0]);
+  for (int dz = -1; dz <= 1; ++dz) {
+    int z = cz + dz;
+    if (!wrap_cell(z, g.nc[2], g.periodic[2])) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      int y = cy + dy;
+      if (!wrap_cell(y, g.nc[1], g.periodic[1])) continue;
+      const int64_t base = g.cell_base + (int64_t)g.nc[0] * (y + (int64_t)g.nc[1] * z);
+      {
+        const uint32_t jb = start[base + row.a0], je = start[base + row.b0 + 1];
+        for (uint32_t j = jb; j < je; ++j) f(j);
+      }
+      if (row.a1 <= row.b1) {
+        const uint32_t jb = start[base + row.a1], je = start[base + row.b1 + 1];
+        for (uint32_t j = jb; j < je; ++j) f(j);
+      }
+    }
+  }
+}
+
+// Separation q_i - q_j with the minimum image along periodic dimensions.
+__device__ __forceinline__ void separation(const Geo& g, double xi, double yi, double zi,
+                                           double xj, double yj, double zj, double& dx,
+                                           double& dy, double& dz) {
+  dx = xi - xj;
+  dy = yi - yj;
+  dz = zi - zj;
+  if (g.periodic[0]) dx = min_image(dx, g.box[0], g.half_box[0]);
+  if (g.periodic[1]) dy = min_image(dy, g.box[1], g.half_box[1]);
+  if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Pass A: forces F_i = sum_j a (1 - r/rc) d_ij / r, U_i = 1/2 sum_j v(r_ij),
+// neighbour list; mode 1 also applies p += dt/2 F (end of velocity-Verlet).
+// ---------------------------------------------------------------------------
+template <bool BATCH, int PREC>
+__global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
+    PState s, const uint32_t* __restrict__ start, int64_t n, const Geo* __restrict__ geo, Phys P,
+    int mode, double* __restrict__ Fx, double* __restrict__ Fy, double* __restrict__ Fz,
+    double* __restrict__ Ui, NList nl, uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (status_set(status)) return;
+  const Geo& g = geo[rep_of<BATCH>(s, i)];
+  const double xi = s.qx[i], yi = s.qy[i], zi = s.qz[i];
+  const int cx = cell_coord(xi, g.scale[0], g.nc[0]);
+  const int cy = cell_coord(yi, g.scale[1], g.nc[1]);
+  const int cz = cell_coord(zi, g.scale[2], g.nc[2]);
+  const double* __restrict__ qx = s.qx;
+  const double* __restrict__ qy = s.qy;
+  const double* __restrict__ qz = s.qz;
+  double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0;
+  uint32_t nn = 0;
+  const uint32_t cap = (uint32_t)P.cap;
+  const float inv_rc_f = (float)P.inv_rc, a_f = (float)P.a;
+  for_each_candidate(g, start, cx, cy, cz, [&](uint32_t j) {
+    if (j == (uint32_t)i) return;
+    double dx, dy, dz;
+    separation(g, xi, yi, zi, qx[j], qy[j], qz[j], dx, dy, dz);
+    const double r2 = dist2(dx, dy, dz);
+    if (r2 < P.rc2) {
+      if (nn < cap) nl.idx[(int64_t)nn * nl.stride + i] = j;
+      ++nn;
+      if constexpr (PREC == PREC_F64) {
+        const double r = sqrt(r2);
+        const double w = 1.0 - r * P.inv_rc;
+        u += w * w;
+        if (r > 0.0) {
+          const double f = P.a * w / r;
+          fx += f * dx;
+          fy += f * dy;
+          fz += f * dz;
+        }
+      } else {
+        const float r = __builtin_sqrtf((float)r2);
+        const float w = 1.0f - r * inv_rc_f;
+        u += (double)(w * w);
+        if (r > 0.0f) {
+          const float f = a_f * w / r;
+          fx += (double)(f * (float)dx);
+          fy += (double)(f * (float)dy);
+          fz += (double)(f * (float)dz);
+        }
+      }
+    }
+  });
+  if (nn > cap) {
+    atomicOr(status, ST_OVERFLOW);
+    nn = cap;
+  }
+  nl.count[i] = nn;
+  Fx[i] = fx;
+  Fy[i] = fy;
+  Fz[i] = fz;
+  Ui[i] = 0.5 * P.half_a_rc * u;
+  if (mode) {
+    s.px[i] = s.px[i] + P.half_dt * fx;
+    s.py[i] = s.py[i] + P.half_dt * fy;
+    s.pz[i] = s.pz[i] + P.half_dt * fz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The SER momentum increment of one pair as seen by particle i (eq. SER_p):
+//   dp_ij = -gamma_ij chi v_ij dt + sigma sqrt(chi) G_ij sqrt(dt)
+// with chi = w^2, w = 1 - r/rc, gamma_ij = (gamma kT/2)(1/T_i + 1/T_j) and
+// G_ij = +G(lo,hi) for i = lo, -G(lo,hi) for i = hi.  Every factor is either
+// symmetric in (i,j) or flips sign exactly, so the result for (j,i) is the
+// exact negative.
+// ---------------------------------------------------------------------------
+struct PairOut {
+  double dp[3];
+  double gdotv;  // (sign G) . v_ij, for SEM
+  double chi;
+  double w;
+  double gij;
+};
+
+template <int PREC>
+__device__ __forceinline__ void ser_pair(const Phys& P, const Geo& g, double r2, double vx,
+                                         double vy, double vz, double invT_sum, uint32_t idi,
+                                         uint32_t idj, uint64_t step, PairOut& o) {
+  const bool i_lo = idi < idj;
+  uint32_t wd[4];
+  pair_words(g, i_lo ? idi : idj, i_lo ? idj : idi, step, wd);
+  if constexpr (PREC == PREC_F64) {
+    const double r = sqrt(r2);
+    const double w = 1.0 - r * P.inv_rc;
+    const double chi = w * w;
+    const double gij = P.gkT_half * invT_sum;
+    double G[3];
+    box_muller_f64(wd, G);
+    const double c1 = -gij * chi * P.dt;
+    const double c2 = (i_lo ? P.sigma : -P.sigma) * w * P.sqrt_dt;
+    o.dp[0] = c1 * vx + c2 * G[0];
+    o.dp[1] = c1 * vy + c2 * G[1];
+    o.dp[2] = c1 * vz + c2 * G[2];
+    o.gdotv = (i_lo ? 1.0 : -1.0) * (G[0] * vx + G[1] * vy + G[2] * vz);
+    o.chi = chi;
+    o.w = w;
+    o.gij = gij;
+  } else {
+    const float r = __builtin_sqrtf((float)r2);
+    const float w = 1.0f - r * (float)P.inv_rc;
+    const float chi = w * w;
+    const float gij = (float)(P.gkT_half * invT_sum);
+    float G[3];
+    box_muller_f32(wd, G);
+    const float c1 = -gij * chi * (float)P.dt;
+    const float c2 = (i_lo ? (float)P.sigma : -(float)P.sigma) * w * (float)P.sqrt_dt;
+    const float v0 = (float)vx, v1 = (float)vy, v2 = (float)vz;
+    o.dp[0] = (double)(c1 * v0 + c2 * G[0]);
+    o.dp[1] = (double)(c1 * v1 + c2 * G[1]);
+    o.dp[2] = (double)(c1 * v2 + c2 * G[2]);
+    o.gdotv = (double)((i_lo ? 1.0f : -1.0f) * (G[0] * v0 + G[1] * v1 + G[2] * v2));
+    o.chi = (double)chi;
+    o.w = (double)w;
+    o.gij = (double)gij;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass B (SER sweep 1, and the whole SEM update of eq. SEM_fd).
+// ---------------------------------------------------------------------------
+template <bool BATCH, int PREC, int SCHEME>
+__global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
+    PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
+    const uint64_t* __restrict__ d_step, double* __restrict__ dpx, double* __restrict__ dpy,
+    double* __restrict__ dpz, double* __restrict__ deps, uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (status_set(status)) return;
+  const uint64_t step = *d_step;
+  const Geo& g = geo[rep_of<BATCH>(s, i)];
+  const double xi = s.qx[i], yi = s.qy[i], zi = s.qz[i];
+  const double vxi = s.px[i] * P.inv_mass, vyi = s.py[i] * P.inv_mass, vzi = s.pz[i] * P.inv_mass;
+  const double iTi = s.invT[i];
+  const uint32_t idi = s.id[i];
+  const uint32_t nn = nl.count[i];
+  double ax = 0.0, ay = 0.0, az = 0.0, de = 0.0;
+  for (uint32_t k = 0; k < nn; ++k) {
+    const uint32_t j = nl.idx[(int64_t)k * nl.stride + i];
+    double dx, dy, dz;
+    separation(g, xi, yi, zi, s.qx[j], s.qy[j], s.qz[j], dx, dy, dz);
+    const double r2 = dist2(dx, dy, dz);
+    const double vx = vxi - s.px[j] * P.inv_mass;
+    const double vy = vyi - s.py[j] * P.inv_mass;
+    const double vz = vzi - s.pz[j] * P.inv_mass;
+    PairOut o;
+    ser_pair<PREC>(P, g, r2, vx, vy, vz, iTi + s.invT[j], idi, s.id[j], step, o);
+    ax += o.dp[0];
+    ay += o.dp[1];
+    az += o.dp[2];
+    if constexpr (SCHEME == 1) {
+      const double v2 = vx * vx + vy * vy + vz * vz;
+      de += 0.5 * (o.gij * v2 - P.dsigma2_m) * o.chi * P.dt -
+            0.5 * P.sigma * o.w * o.gdotv * P.sqrt_dt;
+    }
+  }
+  dpx[i] = ax;
+  dpy[i] = ay;
+  dpz[i] = az;
+  if constexpr (SCHEME == 1) deps[i] = de;
+}
+
+// ---------------------------------------------------------------------------
+// Inverse temperature of the updated internal energy.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double inv_temperature(const Phys& P, double eps, uint32_t* status) {
+  if (P.eos == 0) return P.cv / eps;
+  int it;
+  const double th = theta_newton_dev(P, eps, theta_start_dev(P, eps), it);
+  if (!(th > 0.0) || !isfinite(th)) atomicOr(status, ST_EOS);
+  return 1.0 / th;
+}
+
+// ---------------------------------------------------------------------------
+// Pass C (SER sweep 2): d eps_i = -1/2 sum_j dp_ij . (v_ij + (dp_i - dp_j)/(2m))
+// in FP64 for both precisions, then p <- p + dp, eps <- eps + d eps and the
+// next 1/T_i.  The updated momenta and 1/T are written to (pxo, pyo, pzo,
+// invTo), never over the arrays this pass gathers from.
+// ---------------------------------------------------------------------------
+template <bool BATCH, int PREC>
+__global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
+    PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
+    const uint64_t* __restrict__ d_step, const double* __restrict__ dpx,
+    const double* __restrict__ dpy, const double* __restrict__ dpz, int eos_inline,
+    double* __restrict__ pxo, double* __restrict__ pyo, double* __restrict__ pzo,
+    double* __restrict__ invTo, uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (status_set(status)) return;
+  const uint64_t step = *d_step;
+  const Geo& g = geo[rep_of<BATCH>(s, i)];
+  const double xi = s.qx[i], yi = s.qy[i], zi = s.qz[i];
+  const double pxi = s.px[i], pyi = s.py[i], pzi = s.pz[i];
+  const double vxi = pxi * P.inv_mass, vyi = pyi * P.inv_mass, vzi = pzi * P.inv_mass;
+  const double dxi = dpx[i], dyi = dpy[i], dzi = dpz[i];
+  const double iTi = s.invT[i];
+  const uint32_t idi = s.id[i];
+  const uint32_t nn = nl.count[i];
+  double de = 0.0;
+  for (uint32_t k = 0; k < nn; ++k) {
+    const uint32_t j = nl.idx[(int64_t)k * nl.stride + i];
+    double dx, dy, dz;
+    separation(g, xi, yi, zi, s.qx[j], s.qy[j], s.qz[j], dx, dy, dz);
+    const double r2 = dist2(dx, dy, dz);
+    const double vx = vxi - s.px[j] * P.inv_mass;
+    const double vy = vyi - s.py[j] * P.inv_mass;
+    const double vz = vzi - s.pz[j] * P.inv_mass;
+    PairOut o;
+    ser_pair<PREC>(P, g, r2, vx, vy, vz, iTi + s.invT[j], idi, s.id[j], step, o);
+    const double ux = vx + (dxi - dpx[j]) * P.inv_2m;
+    const double uy = vy + (dyi - dpy[j]) * P.inv_2m;
+    const double uz = vz + (dzi - dpz[j]) * P.inv_2m;
+    de += -0.5 * (o.dp[0] * ux + o.dp[1] * uy + o.dp[2] * uz);
+  }
+  // new momenta and 1/T go to separate arrays: other lanes are still reading
+  // p_j and 1/T_j of this particle for their own pair terms
+  pxo[i] = pxi + dxi;
+  pyo[i] = pyi + dyi;
+  pzo[i] = pzi + dzi;
+  const double e = s.eps[i] + de;
+  s.eps[i] = e;
+  if (!(e > 0.0)) {
+    atomicOr(status, ST_NEG_EINT);
+    invTo[i] = iTi;
+    return;
+  }
+  invTo[i] = eos_inline ? inv_temperature(P, e, status) : iTi;
+}
+
+// SEM: apply dp and d eps (both from pass B), then the next 1/T_i.
+__global__ void k_apply_sem(PState s, int64_t n, Phys P, const double* __restrict__ dpx,
+                            const double* __restrict__ dpy, const double* __restrict__ dpz,
+                            const double* __restrict__ deps, int eos_inline, uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (status_set(status)) return;
+  s.px[i] += dpx[i];
+  s.py[i] += dpy[i];
+  s.pz[i] += dpz[i];
+  const double e = s.eps[i] + deps[i];
+  s.eps[i] = e;
+  if (!(e > 0.0)) {
+    atomicOr(status, ST_NEG_EINT);
+    return;
+  }
+  if (eos_inline) s.invT[i] = inv_temperature(P, e, status);
+}
+
+// 1/T_i for every particle (initialisation and the separate-EOS path).
+__global__ void k_inv_temperature(PState s, int64_t n, Phys P, uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double e = s.eps[i];
+  if (!(e > 0.0)) {
+    atomicOr(status, ST_NEG_EINT);
+    return;
+  }
+  s.invT[i] = inv_temperature(P, e, status);
+}
+
+// ---------------------------------------------------------------------------
+// Observables: per-tile partial sums, then one block per replica in tile
+// order.  Record: U, K, sum eps, E, Px, Py, Pz, T_kin, T_int, step.
+// ---------------------------------------------------------------------------
+constexpr int kStatThreads = 256;
+
+__global__ __launch_bounds__(kStatThreads) void k_stats_tiles(
+    PState s, const double* __restrict__ Ui, const int64_t* __restrict__ tile_begin, Phys P,
+    double* __restrict__ partials) {
+  const int64_t b = tile_begin[blockIdx.x], e = tile_begin[blockIdx.x + 1];
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+    const double px = s.px[i], py = s.py[i], pz = s.pz[i];
+    const double p2 = px * px + py * py + pz * pz;
+    v[0] += Ui[i];
+    v[1] += p2 / (2.0 * P.mass);
+    v[2] += s.eps[i];
+    v[3] += px;
+    v[4] += py;
+    v[5] += pz;
+    v[6] += s.invT[i];
+  }
+  __shared__ double smem[7 * (kStatThreads / kWave)];
+  block_sum<7>(v, smem);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 7; ++k) partials[blockIdx.x * 8 + k] = v[k];
+}
+
+__global__ __launch_bounds__(kStatThreads) void k_stats_final(
+    const double* __restrict__ partials, const int32_t* __restrict__ rep_tile0,
+    const Geo* __restrict__ geo, const uint64_t* __restrict__ d_step, int advance,
+    double* __restrict__ rec, double* __restrict__ hist, int64_t hist_cap,
+    const int64_t* __restrict__ d_hist_count, int nrep) {
+  const int r = blockIdx.x;
+  const int t0 = rep_tile0[r], t1 = rep_tile0[r + 1];
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int t = t0 + threadIdx.x; t < t1; t += blockDim.x)
+    for (int k = 0; k < 7; ++k) v[k] += partials[t * 8 + k];
+  __shared__ double smem[7 * (kStatThreads / kWave)];
+  block_sum<7>(v, smem);
+  if (threadIdx.x == 0) {
+    const double N = (double)geo[r].n;
+    double o[10];
+    o[0] = v[0];
+    o[1] = v[1];
+    o[2] = v[2];
+    o[3] = v[0] + v[1] + v[2];
+    o[4] = v[3];
+    o[5] = v[4];
+    o[6] = v[5];
+    o[7] = 2.0 * v[1] / (3.0 * (N - 1.0));
+    o[8] = N / v[6];
+    o[9] = (double)(*d_step + (uint64_t)advance);
+    double* hrow = nullptr;
+    if (advance) hrow = hist + ((*d_hist_count % hist_cap) * nrep + r) * 10;
+    for (int k = 0; k < 10; ++k) {
+      rec[r * 10 + k] = o[k];
+      if (hrow) hrow[k] = o[k];
+    }
+  }
+}
+
+// End of a step: n <- n + 1, one more history record (not after an error).
+__global__ void k_step_advance(uint64_t* d_step, int64_t* d_hist_count, const uint32_t* status) {
+  if (status_set(status)) return;
+  *d_step += 1;
+  *d_hist_count += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Test hooks.
+// ---------------------------------------------------------------------------
+template <bool BATCH>
+__global__ void k_debug_cells(PState s, int64_t n, const Geo* __restrict__ geo, int32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Geo& g = geo[rep_of<BATCH>(s, i)];
+  const int cx = cell_coord(s.qx[i], g.scale[0], g.nc[0]);
+  const int cy = cell_coord(s.qy[i], g.scale[1], g.nc[1]);
+  const int cz = cell_coord(s.qz[i], g.scale[2], g.nc[2]);
+  out[g.first + s.id[i]] = cx + g.nc[0] * (cy + g.nc[1] * cz);
+}
+
+template <bool BATCH>
+__global__ void k_debug_pairs(PState s, NList nl, int64_t n, const Geo* __restrict__ geo,
+                              int32_t* out, int64_t cap, unsigned long long* counter) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Geo& g = geo[rep_of<BATCH>(s, i)];
+  const uint32_t idi = s.id[i];
+  for (uint32_t k = 0; k < nl.count[i]; ++k) {
+    const uint32_t j = nl.idx[(int64_t)k * nl.stride + i];
+    const uint32_t idj = s.id[j];
+    if (idi < idj) {
+      const unsigned long long slot = atomicAdd(counter, 1ull);
+      if ((int64_t)slot < cap) {
+        out[2 * slot] = (int32_t)(g.first + idi);
+        out[2 * slot + 1] = (int32_t)(g.first + idj);
+      }
+    }
+  }
+}
+
+__global__ void k_debug_rng(uint32_t key0, uint32_t key1, uint64_t step,
+                            const uint32_t* __restrict__ lo, const uint32_t* __restrict__ hi,
+                            int64_t n, uint32_t* raw, double* g, float* g32) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  Geo geo;
+  geo.key0 = key0;
+  geo.key1 = key1;
+  uint32_t w[4];
+  pair_words(geo, lo[k], hi[k], step, w);
+  if (raw)
+    for (int c = 0; c < 4; ++c) raw[4 * k + c] = w[c];
+  if (g) {
+    double G[3];
+    box_muller_f64(w, G);
+    for (int c = 0; c < 3; ++c) g[3 * k + c] = G[c];
+  }
+  if (g32) {
+    float G[3];
+    box_muller_f32(w, G);
+    for (int c = 0; c < 3; ++c) g32[3 * k + c] = G[c];
+  }
+}
+
+}  // namespace dpde

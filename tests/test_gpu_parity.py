@@ -1,0 +1,236 @@
+"""GPU path vs CPU oracle, through the C ABI.
+
+Integers (RNG words, cell indices, pair lists) must match bit for bit from
+identical inputs; FP64 state must match to 1e-12 relative per step with the
+scales L (positions, compared modulo L), sqrt(m kT) (momenta) and the mean
+internal energy (internal energies).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def dp():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1507_06643_amd as m
+    return m
+
+
+def _cfg(dp, n, box, **kw):
+    return dp.Config(n=n, box=list(box), **kw)
+
+
+def _oparams(n, box, **kw):
+    return O.make_params(n, box, **kw)
+
+
+def _state_errors(box, periodic, got, want, eps_scale):
+    qg, pg, eg = got
+    qo, po, eo = want
+    dq = qg - qo
+    for k in range(3):
+        if periodic[k]:
+            dq[:, k] -= box[k] * np.rint(dq[:, k] / box[k])
+    eq = np.abs(dq).max() / max(box)
+    ep = np.abs(pg - po).max()
+    ee = np.abs(eg - eo).max() / eps_scale
+    return eq, ep, ee
+
+
+def _gpu_state(sysm):
+    q, p, e, step = sysm.get_state()
+    return q.cpu().numpy(), p.cpu().numpy(), e.cpu().numpy(), step
+
+
+# ---------------------------------------------------------------------------
+# Counter-based RNG: words bit-exact, normals to rounding.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,replica,step", [(7, 0, 0), (2**64 - 1, 3, 12345),
+                                               (0xDEADBEEF12345678, 255, 2**33 + 7)])
+def test_rng_words_and_normals(dp, seed, replica, step):
+    lo, hi = W.random_pairs(2**31 - 1, 4099, seed=seed % 1000)
+    raw, g, g32 = dp.debug_rng(seed, replica, step, lo, hi)
+    for k in range(0, len(lo), 97):
+        assert list(raw[k]) == O.pair_words(seed, replica, step, int(lo[k]), int(hi[k]))
+        go = O.gauss3(seed, replica, step, int(lo[k]), int(hi[k]))
+        assert np.abs(g[k] - go).max() <= 1e-14 * max(1.0, np.abs(go).max())
+        assert np.abs(g32[k] - go).max() <= 2e-5 * max(1.0, np.abs(go).max())
+
+
+# ---------------------------------------------------------------------------
+# Cells and pairs: bit-exact from identical positions.
+# ---------------------------------------------------------------------------
+def _adversarial(n, box, seed):
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, dtype=float)
+    nc = np.floor(box).astype(int)
+    q = rng.random((n, 3)) * box
+    m = n // 5
+    for k in range(3):
+        q[:m, k] = rng.integers(0, nc[k], size=m) * (box[k] / nc[k])
+    q[m:m + 7, 0] = 0.0
+    q[m + 7:m + 14, 1] = np.nextafter(box[1], 0.0)
+    q[m + 14:m + 21, 2] = np.nextafter(box[2], 0.0)
+    base = q[m + 21].copy()
+    for t in range(4):
+        q[m + 21 + t] = base
+        q[m + 21 + t, 0] = (base[0] + t * 1.0) % box[0]
+    return q
+
+
+CASES = [
+    (1000, None, (1, 1, 1), 1),
+    (3001, None, (1, 1, 1), 2),        # ragged
+    (2400, (20.0, 6.5, 6.2), (0, 1, 1), 3),  # free boundaries along x
+    (5000, (12.3, 11.7, 11.9), (1, 1, 1), 4),
+]
+
+
+@pytest.mark.parametrize("n,box,periodic,seed", CASES)
+def test_cells_and_pairs_bit_exact(dp, n, box, periodic, seed):
+    if box is None:
+        L = W.cubic_side(n)
+        box = (L, L, L)
+    q = _adversarial(n, box, seed)
+    _, p, e = W.equilibrium_state(n, box, seed=seed)
+    sysm = dp.System(_cfg(dp, n, box, periodic=periodic), q, p, e)
+    P = _oparams(n, box, periodic=periodic)
+    cells = sysm.debug_cells().cpu().numpy()
+    assert np.array_equal(cells, O.cell_index(P, q))
+    got = sysm.debug_pairs()
+    want = O.pairs(P, q, "cells")
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+    sysm.close()
+
+
+def test_pairs_of_evolved_state_match_brute_force(dp):
+    n = 600
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=9)
+    sysm = dp.System(_cfg(dp, n, [L] * 3), q, p, e)
+    sysm.step(25)
+    qg, _, _, _ = _gpu_state(sysm)
+    P = _oparams(n, [L] * 3)
+    assert np.array_equal(sysm.debug_pairs(), O.pairs(P, qg, "brute"))
+    assert np.array_equal(sysm.debug_cells().cpu().numpy(), O.cell_index(P, qg))
+
+
+# ---------------------------------------------------------------------------
+# Forces and energies at initialisation.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1000, 20000])
+def test_forces_and_energies(dp, n):
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=n)
+    sysm = dp.System(_cfg(dp, n, [L] * 3), q, p, e)
+    F, U = sysm.forces()
+    Fo, Uo = O.forces(_oparams(n, [L] * 3), q)
+    assert np.abs(F.cpu().numpy() - Fo).max() <= TOL * max(1.0, np.abs(Fo).max())
+    assert abs(U - Uo) <= TOL * abs(Uo)
+    en = sysm.energies()
+    eo = O.energies(_oparams(n, [L] * 3), p, e, Uo)
+    assert np.allclose(en[[0, 1, 2, 3, 7, 8, 9]], eo[[0, 1, 2, 3, 7, 8, 9]], rtol=TOL, atol=0)
+    assert np.abs(en[4:7] - eo[4:7]).max() < 1e-10
+    sysm.close()
+
+
+# ---------------------------------------------------------------------------
+# One step from a GPU state, replayed by the oracle.
+# ---------------------------------------------------------------------------
+def _step_parity(dp, n, box, periodic=(1, 1, 1), nsteps_before=(0, 7), **kw):
+    q, p, e = W.equilibrium_state(n, box, seed=n + 1, eps0=kw.get("cv", 100.0))
+    sysm = dp.System(_cfg(dp, n, box, periodic=periodic, **kw), q, p, e)
+    worst = 0.0
+    done = 0
+    for nb in nsteps_before:
+        sysm.step(nb - done)
+        done = nb
+        qs, ps, es, step = _gpu_state(sysm)
+        P = _oparams(n, box, periodic=periodic, step=step, **kw)
+        S = O.State(P, qs, ps, es)
+        rc, _ = S.step(1)
+        assert rc == 0
+        sysm.step(1)
+        done += 1
+        qg, pg, eg, step1 = _gpu_state(sysm)
+        assert step1 == step + 1
+        errs = _state_errors(box, periodic, (qg, pg, eg), (S.q, S.p, S.eps), np.abs(S.eps).mean())
+        worst = max(worst, max(errs))
+        en = sysm.energies()
+        eo = S.energies()
+        assert abs(en[3] - eo[3]) <= 1e-12 * abs(eo[3])
+        assert abs(en[8] - eo[8]) <= 1e-12 * abs(eo[8])
+    sysm.close()
+    return worst
+
+
+def test_step_parity_config0(dp):
+    n = 1000
+    L = W.cubic_side(n)
+    assert _step_parity(dp, n, [L] * 3, dt=0.01) < TOL
+
+
+def test_step_parity_65536(dp):
+    n = 65536
+    L = W.cubic_side(n)
+    assert _step_parity(dp, n, [L] * 3, dt=0.005, nsteps_before=(0, 3)) < TOL
+
+
+def test_step_parity_free_x_boundaries(dp):
+    box = (24.0, 8.0, 8.0)
+    n = int(3 * np.prod(box))
+    assert _step_parity(dp, n, box, periodic=(0, 1, 1), dt=0.005) < TOL
+
+
+def test_step_parity_mass_and_ragged(dp):
+    box = (9.3, 8.1, 7.7)
+    n = 1733
+    assert _step_parity(dp, n, box, dt=0.004, mass=2.5, gamma=3.0, kT_ref=1.3, a=18.0) < TOL
+
+
+# ---------------------------------------------------------------------------
+# Conservation and determinism on the GPU.
+# ---------------------------------------------------------------------------
+def test_energy_conserved_without_conservative_force(dp):
+    n = 4000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=5)
+    sysm = dp.System(_cfg(dp, n, [L] * 3, a=0.0), q, p, e)
+    E0 = sysm.energies()[3]
+    sysm.step(500)
+    h = sysm.history()
+    assert h.shape[0] == 500
+    assert np.abs(h[:, 3] - E0).max() < 1e-12 * E0
+    assert np.abs(h[:, 4:7]).max() < 1e-10
+    sysm.close()
+
+
+def test_bit_reproducible_and_resumable(dp):
+    n = 3000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=6)
+    a = dp.System(_cfg(dp, n, [L] * 3), q, p, e)
+    a.step(20)
+    sa = _gpu_state(a)
+    b = dp.System(_cfg(dp, n, [L] * 3), q, p, e)
+    b.step(10)
+    qb, pb, eb, st = b.get_state()
+    c = dp.System(_cfg(dp, n, [L] * 3, step0=st), qb, pb, eb)
+    c.step(10)
+    sc = _gpu_state(c)
+    for x, y in zip(sa[:3], sc[:3]):
+        assert np.array_equal(x, y)
+    assert sa[3] == sc[3] == 20
+    for s in (a, b, c):
+        s.close()
