@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--mlp-iters", type=int, default=3000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -138,6 +140,18 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 3}))
+        return
+
     import paper_1507_06643_amd as dp
     import workloads as W
 

@@ -94,8 +94,15 @@ typedef struct dpde_params {
   int32_t scheme;       /* DPDE_SCHEME_*                                        */
   uint32_t replica;     /* folded into the noise key (seed_hi ^ replica)        */
   int32_t neighbor_cap; /* max neighbours per particle (0: default 64)          */
-  int32_t flags;        /* reserved, must be 0                                  */
+  int32_t flags;        /* DPDE_FLAG_* bits                                     */
 } dpde_params;
+
+/* flags: regenerate G_ij^n in the second SER sweep, as the paper does to avoid
+ * storing the increments (Sec. 3.2.1), instead of storing dp_ij per neighbour
+ * in the first sweep and reading it back (the default, which trades 24 bytes
+ * per neighbour of HBM traffic for the noise generation).  Results are
+ * identical bit for bit either way. */
+#define DPDE_FLAG_REGENERATE_NOISE 1
 
 typedef struct dpde_handle dpde_handle;
 

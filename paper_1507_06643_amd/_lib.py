@@ -18,6 +18,7 @@ FP64, FP32 = 0, 1
 EOS_LINEAR, EOS_EINSTEIN = 0, 1
 THETA_NEWTON, THETA_MLP, THETA_MLP_NEWTON = 0, 1, 2
 SCHEME_SER, SCHEME_SEM = 0, 1
+DPDE_FLAG_REGENERATE_NOISE = 1
 MLP_NPARAM = 1153
 
 ERROR_NAMES = {

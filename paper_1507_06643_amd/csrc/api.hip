@@ -71,8 +71,11 @@ struct dpde_handle {
   int aux_block = 256;
 
   PState cur{}, alt{};
+  bool regen = false;  // regenerate the noise in sweep 2 instead of storing dp_ij
   double *Fx = nullptr, *Fy = nullptr, *Fz = nullptr;
-  double *dpx = nullptr, *dpy = nullptr, *dpz = nullptr, *deps = nullptr;
+  PV* pv = nullptr;
+  double* deps = nullptr;
+  uint32_t* idk = nullptr;
   double* Ui = nullptr;
   uint32_t *key = nullptr, *ticket = nullptr, *perm = nullptr;
   uint32_t *cell_count = nullptr, *cell_start = nullptr, *scan_tmp = nullptr;
@@ -102,6 +105,7 @@ struct dpde_handle {
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   int64_t graph_steps = 0;
+  PState graph_cur{}, graph_alt{};  // buffer layout the graph was captured with
 
   std::vector<void*> allocations;
 };
@@ -184,7 +188,8 @@ int check_params(const dpde_params* P, bool first) {
     return fail(DPDE_EINVAL, "unknown scheme %d", P->scheme);
   if (P->neighbor_cap < 0 || P->neighbor_cap > 1024)
     return fail(DPDE_EINVAL, "neighbor_cap must be in [0, 1024]");
-  if (P->flags != 0) return fail(DPDE_EINVAL, "flags must be 0");
+  if ((P->flags & ~DPDE_FLAG_REGENERATE_NOISE) != 0)
+    return fail(DPDE_EINVAL, "unknown bits in flags");
   return DPDE_OK;
 }
 
@@ -234,13 +239,7 @@ void physics(const dpde_params* P, Phys& ph) {
 
 int alloc_pstate(dpde_handle* h, PState& s) {
   int rc;
-  const int64_t n = h->n;
-  if ((rc = dalloc(h, &s.qx, n)) || (rc = dalloc(h, &s.qy, n)) || (rc = dalloc(h, &s.qz, n)) ||
-      (rc = dalloc(h, &s.px, n)) || (rc = dalloc(h, &s.py, n)) || (rc = dalloc(h, &s.pz, n)) ||
-      (rc = dalloc(h, &s.eps, n)) || (rc = dalloc(h, &s.invT, n)) || (rc = dalloc(h, &s.id, n)))
-    return rc;
-  s.rep = nullptr;
-  if (h->batch && (rc = dalloc(h, &s.rep, n))) return rc;
+  if ((rc = dalloc(h, &s.r, h->n)) || (rc = dalloc(h, &s.eps, h->n))) return rc;
   return DPDE_OK;
 }
 
@@ -249,8 +248,8 @@ int allocate(dpde_handle* h) {
   const int64_t n = h->n;
   if ((rc = alloc_pstate(h, h->cur)) || (rc = alloc_pstate(h, h->alt))) return rc;
   if ((rc = dalloc(h, &h->Fx, n)) || (rc = dalloc(h, &h->Fy, n)) || (rc = dalloc(h, &h->Fz, n)) ||
-      (rc = dalloc(h, &h->dpx, n)) || (rc = dalloc(h, &h->dpy, n)) ||
-      (rc = dalloc(h, &h->dpz, n)) || (rc = dalloc(h, &h->deps, n)) || (rc = dalloc(h, &h->Ui, n)))
+      (rc = dalloc(h, &h->pv, n)) || (rc = dalloc(h, &h->deps, n)) || (rc = dalloc(h, &h->Ui, n)) ||
+      (rc = dalloc(h, &h->idk, n)))
     return rc;
   if ((rc = dalloc(h, &h->key, n)) || (rc = dalloc(h, &h->ticket, n)) ||
       (rc = dalloc(h, &h->perm, n)))
@@ -262,6 +261,11 @@ int allocate(dpde_handle* h) {
   if ((rc = dalloc(h, &h->scan_tmp, h->scan_tiles + 1))) return rc;
   h->nl.stride = n;
   if ((rc = dalloc(h, &h->nl.idx, (size_t)h->phys.cap * n)) || (rc = dalloc(h, &h->nl.count, n)))
+    return rc;
+  h->nl.dex = h->nl.dey = h->nl.dez = nullptr;
+  if (!h->regen && ((rc = dalloc(h, &h->nl.dex, (size_t)h->phys.cap * n)) ||
+                    (rc = dalloc(h, &h->nl.dey, (size_t)h->phys.cap * n)) ||
+                    (rc = dalloc(h, &h->nl.dez, (size_t)h->phys.cap * n))))
     return rc;
   if ((rc = dalloc(h, &h->status, 4)) || (rc = dalloc(h, &h->d_step, 1)) ||
       (rc = dalloc(h, &h->d_hist_count, 1)) || (rc = dalloc(h, &h->counter, 1)))
@@ -306,14 +310,12 @@ int status_to_code(uint32_t st) {
 void enqueue_bin(dpde_handle* h, int kick) {
   const int b = h->aux_block;
   const int64_t n = h->n;
-  if (h->batch)
-    launch(h, "kick_drift_key", k_kick_drift_key<true>, blocks(n, b), b, h->cur, h->Fx, h->Fy,
-           h->Fz, n, h->geo, h->phys, kick, h->key, h->ticket, h->cell_count, h->status);
-  else
-    launch(h, "kick_drift_key", k_kick_drift_key<false>, blocks(n, b), b, h->cur, h->Fx, h->Fy,
-           h->Fz, n, h->geo, h->phys, kick, h->key, h->ticket, h->cell_count, h->status);
-  launch(h, "scan_tiles", k_scan_tiles, h->scan_tiles, kScanThreads, h->cell_count, h->ncells,
-         h->scan_tmp);
+  auto kick_kernel = h->batch ? k_kick_drift_key<true> : k_kick_drift_key<false>;
+  launch(h, "kick_drift_key", kick_kernel, blocks(n, b), b, h->cur, (const double*)h->Fx,
+         (const double*)h->Fy, (const double*)h->Fz, n, (const Geo*)h->geo, h->phys, kick, h->key,
+         h->ticket, h->idk, h->cell_count, h->status);
+  launch(h, "scan_tiles", k_scan_tiles, h->scan_tiles, kScanThreads, (const uint32_t*)h->cell_count,
+         h->ncells, h->scan_tmp);
   launch(h, "scan_tile_sums", k_scan_tile_sums, 1, 1024, h->scan_tmp, h->scan_tiles);
   launch(h, "scan_apply", k_scan_apply, h->scan_tiles, kScanThreads, h->cell_count, h->ncells,
          (const uint32_t*)h->scan_tmp, h->cell_start);
@@ -321,7 +323,7 @@ void enqueue_bin(dpde_handle* h, int kick) {
          (const uint32_t*)h->ticket, (const uint32_t*)h->cell_start, n, h->perm,
          (const uint32_t*)h->status);
   launch(h, "cell_sort", k_cell_sort, blocks(h->ncells, b), b, (const uint32_t*)h->cell_start,
-         h->ncells, h->perm, (const uint32_t*)h->cur.id, (const uint32_t*)h->status);
+         h->ncells, h->perm, (const uint32_t*)h->idk, (const uint32_t*)h->status);
   launch(h, "gather", k_gather, blocks(n, b), b, h->cur, h->alt, (const uint32_t*)h->perm, n,
          (const uint32_t*)h->status);
   std::swap(h->cur, h->alt);
@@ -348,41 +350,43 @@ bool eos_inline(const dpde_handle* h) {
 }
 
 template <bool B, int PR>
-void enqueue_fd_t(dpde_handle* h, uint64_t* d_step) {
+void enqueue_fd_t(dpde_handle* h) {
   const int b = h->pair_block;
   const int64_t n = h->n;
-  (void)d_step;
   const int inl = eos_inline(h) ? 1 : 0;
+  const uint64_t* d_step = h->d_step;
+  const int store = h->regen ? 0 : 1;
   if (h->phys.scheme == DPDE_SCHEME_SEM) {
     launch(h, "pass_b_sem", k_pass_b<B, PR, 1>, blocks(n, b), b, h->cur, h->nl, n,
-           (const Geo*)h->geo, h->phys, d_step, h->dpx, h->dpy, h->dpz, h->deps, h->status);
+           (const Geo*)h->geo, h->phys, d_step, h->pv, h->deps, 0, h->status);
     launch(h, "apply_sem", k_apply_sem, blocks(n, h->aux_block), h->aux_block, h->cur, n, h->phys,
-           (const double*)h->dpx, (const double*)h->dpy, (const double*)h->dpz,
-           (const double*)h->deps, inl, h->status);
+           (const PV*)h->pv, (const double*)h->deps, inl, h->alt.r, h->status);
   } else {
     launch(h, "pass_b_ser", k_pass_b<B, PR, 0>, blocks(n, b), b, h->cur, h->nl, n,
-           (const Geo*)h->geo, h->phys, d_step, h->dpx, h->dpy, h->dpz, h->deps, h->status);
-    launch(h, "pass_c_ser", k_pass_c<B, PR>, blocks(n, b), b, h->cur, h->nl, n,
-           (const Geo*)h->geo, h->phys, d_step, (const double*)h->dpx, (const double*)h->dpy,
-           (const double*)h->dpz, inl, h->alt.px, h->alt.py, h->alt.pz, h->alt.invT, h->status);
-    // the new momenta and temperatures live in the spare buffer's fields: swap
-    // them in (two steps restore the original pointer layout, which keeps
-    // even-length captured graphs replayable)
-    std::swap(h->cur.px, h->alt.px);
-    std::swap(h->cur.py, h->alt.py);
-    std::swap(h->cur.pz, h->alt.pz);
-    std::swap(h->cur.invT, h->alt.invT);
+           (const Geo*)h->geo, h->phys, d_step, h->pv, h->deps, store, h->status);
+    if (h->regen)
+      launch(h, "pass_c_ser", k_pass_c<B, PR, 1>, blocks(n, b), b, h->cur, h->nl, n,
+             (const Geo*)h->geo, h->phys, d_step, (const PV*)h->pv, inl, h->alt.r, h->status);
+    else
+      launch(h, "pass_c_ser", k_pass_c<B, PR, 0>, blocks(n, b), b, h->cur, h->nl, n,
+             (const Geo*)h->geo, h->phys, d_step, (const PV*)h->pv, inl, h->alt.r, h->status);
   }
-  if (!inl) enqueue_theta_mlp(h->mlp, h->stream, h->cur.eps, h->cur.invT, n, h->phys, h->status);
+  // the updated records were written to the spare record array: swap them in
+  // (with the swap of the binning, each step swaps the records twice and the
+  // internal energies once; two steps restore the starting layout, which is
+  // what an even-length captured graph relies on)
+  std::swap(h->cur.r, h->alt.r);
+  if (!inl)
+    enqueue_theta_mlp(h->mlp, h->stream, h->cur.eps, &h->cur.r->invT, 8, n, h->phys, h->status);
 }
 
 void enqueue_fd(dpde_handle* h) {
   if (h->batch) {
-    if (h->phys.precision == DPDE_FP32) enqueue_fd_t<true, PREC_F32>(h, h->d_step);
-    else enqueue_fd_t<true, PREC_F64>(h, h->d_step);
+    if (h->phys.precision == DPDE_FP32) enqueue_fd_t<true, PREC_F32>(h);
+    else enqueue_fd_t<true, PREC_F64>(h);
   } else {
-    if (h->phys.precision == DPDE_FP32) enqueue_fd_t<false, PREC_F32>(h, h->d_step);
-    else enqueue_fd_t<false, PREC_F64>(h, h->d_step);
+    if (h->phys.precision == DPDE_FP32) enqueue_fd_t<false, PREC_F32>(h);
+    else enqueue_fd_t<false, PREC_F64>(h);
   }
 }
 
@@ -413,7 +417,7 @@ int prepare(dpde_handle* h) {
     launch(h, "inv_temperature", k_inv_temperature, blocks(h->n, h->aux_block), h->aux_block,
            h->cur, h->n, h->phys, h->status);
   } else {
-    enqueue_theta_mlp(h->mlp, h->stream, h->cur.eps, h->cur.invT, h->n, h->phys, h->status);
+    enqueue_theta_mlp(h->mlp, h->stream, h->cur.eps, &h->cur.r->invT, 8, h->n, h->phys, h->status);
   }
   enqueue_stats(h, 0);
   uint32_t st = 0;
@@ -478,6 +482,7 @@ int create(const dpde_params* params, int nrep, const int64_t* offsets, const do
   h->batch = nrep > 1;
   h->user_stream = (hipStream_t)stream;
   physics(&params[0], h->phys);
+  h->regen = (params[0].flags & DPDE_FLAG_REGENERATE_NOISE) != 0;
   h->step = params[0].step0;
   h->offsets.assign(offsets, offsets + nrep + 1);
   if (h->offsets[0] != 0) { release(h); return fail(DPDE_EINVAL, "offsets[0] must be 0"); }
@@ -572,7 +577,11 @@ int dpde_step_graph(dpde_handle* h, int64_t nsteps, int64_t reps) {
   if (!h) return fail(DPDE_EINVAL, "handle is NULL");
   if (nsteps <= 0 || (nsteps % 2) != 0 || reps < 0)
     return fail(DPDE_EINVAL, "nsteps must be even and > 0, reps >= 0");
-  if (h->graph_exec == nullptr || h->graph_steps != nsteps) {
+  // a graph bakes in the state buffer pointers; eager steps in between can
+  // leave the buffers in the other layout, then the graph is captured again
+  const bool same_layout = std::memcmp(&h->graph_cur, &h->cur, sizeof(PState)) == 0 &&
+                           std::memcmp(&h->graph_alt, &h->alt, sizeof(PState)) == 0;
+  if (h->graph_exec == nullptr || h->graph_steps != nsteps || !same_layout) {
     if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
     if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
     const bool prof = h->profiling;
@@ -580,6 +589,8 @@ int dpde_step_graph(dpde_handle* h, int64_t nsteps, int64_t reps) {
     HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     // each step swaps the two state buffers; an even count ends where it began,
     // so every replay starts from the same buffers the capture saw
+    h->graph_cur = h->cur;
+    h->graph_alt = h->alt;
     for (int64_t s = 0; s < nsteps; ++s) enqueue_step(h);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->stream, &g);
@@ -637,14 +648,9 @@ int dpde_history(dpde_handle* h, double* out, int64_t cap, int64_t* count) {
 
 int dpde_get_state(dpde_handle* h, double* q, double* p, double* eps, int64_t* step) {
   if (!h) return fail(DPDE_EINVAL, "handle is NULL");
-  if (q || p || eps) {
-    if (h->batch)
-      launch(h, "store_state", k_store_state<true>, blocks(h->n, 256), 256, h->cur,
-             (const Geo*)h->geo, h->n, q, p, eps);
-    else
-      launch(h, "store_state", k_store_state<false>, blocks(h->n, 256), 256, h->cur,
-             (const Geo*)h->geo, h->n, q, p, eps);
-  }
+  if (q || p || eps)
+    launch(h, "store_state", k_store_state, blocks(h->n, 256), 256, h->cur, (const Geo*)h->geo,
+           h->n, q, p, eps);
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipGetLastError());
   if (step) *step = h->step;
@@ -662,14 +668,8 @@ int dpde_set_state(dpde_handle* h, const double* q, const double* p, const doubl
 
 int dpde_forces(dpde_handle* h, double* F, double* U) {
   if (!h || !F) return fail(DPDE_EINVAL, "NULL argument");
-  if (h->batch)
-    launch(h, "store_forces", k_store_vec3<true>, blocks(h->n, 256), 256, h->cur,
-           (const Geo*)h->geo, h->n, (const double*)h->Fx, (const double*)h->Fy,
-           (const double*)h->Fz, F);
-  else
-    launch(h, "store_forces", k_store_vec3<false>, blocks(h->n, 256), 256, h->cur,
-           (const Geo*)h->geo, h->n, (const double*)h->Fx, (const double*)h->Fy,
-           (const double*)h->Fz, F);
+  launch(h, "store_forces", k_store_vec3, blocks(h->n, 256), 256, h->cur, (const Geo*)h->geo,
+         h->n, (const double*)h->Fx, (const double*)h->Fy, (const double*)h->Fz, F);
   double rec[10];
   HIPCHK(hipMemcpyAsync(rec, h->rec, sizeof(rec), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -795,12 +795,8 @@ int dpde_mlp_eval(dpde_handle* h, const float* x, float* y, int64_t n) {
 
 int dpde_debug_cells(dpde_handle* h, int32_t* cell_of_id) {
   if (!h || !cell_of_id) return fail(DPDE_EINVAL, "NULL argument");
-  if (h->batch)
-    launch(h, "debug_cells", k_debug_cells<true>, blocks(h->n, 256), 256, h->cur, h->n,
-           (const Geo*)h->geo, cell_of_id);
-  else
-    launch(h, "debug_cells", k_debug_cells<false>, blocks(h->n, 256), 256, h->cur, h->n,
-           (const Geo*)h->geo, cell_of_id);
+  launch(h, "debug_cells", k_debug_cells, blocks(h->n, 256), 256, h->cur, h->n,
+         (const Geo*)h->geo, cell_of_id);
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipGetLastError());
   return DPDE_OK;
@@ -809,12 +805,8 @@ int dpde_debug_cells(dpde_handle* h, int32_t* cell_of_id) {
 int dpde_debug_pairs(dpde_handle* h, int32_t* lohi, int64_t cap, int64_t* npairs) {
   if (!h || !npairs || (cap > 0 && !lohi)) return fail(DPDE_EINVAL, "NULL argument");
   HIPCHK(hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream));
-  if (h->batch)
-    launch(h, "debug_pairs", k_debug_pairs<true>, blocks(h->n, 256), 256, h->cur, h->nl, h->n,
-           (const Geo*)h->geo, lohi, cap, h->counter);
-  else
-    launch(h, "debug_pairs", k_debug_pairs<false>, blocks(h->n, 256), 256, h->cur, h->nl, h->n,
-           (const Geo*)h->geo, lohi, cap, h->counter);
+  launch(h, "debug_pairs", k_debug_pairs, blocks(h->n, 256), 256, h->cur, h->nl, h->n,
+         (const Geo*)h->geo, lohi, cap, h->counter);
   unsigned long long c = 0;
   HIPCHK(hipMemcpyAsync(&c, h->counter, sizeof(c), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));

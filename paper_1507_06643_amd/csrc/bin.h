@@ -1,6 +1,12 @@
-// Cell binning: particles are kept sorted by the composite key (cell, id).
+// Particle storage and cell binning.
 //
-// Sort = two-level MSD radix sort.  Digit 1 is the whole cell index (one
+// Storage: one 64-byte record per particle (position, momentum, 1/T, id,
+// replica), so that gathering a neighbour touches one cache line instead of
+// one line per array; the internal energy, read only by its own particle,
+// lives in a separate array.
+//
+// Order: particles are kept sorted by the composite key (cell, id).  The sort
+// is a two-level MSD radix sort: digit 1 is the whole cell index (one
 // counting pass: histogram of cells with integer atomics, exclusive scan to
 // cell offsets, scatter by offset + arrival ticket); digit 2 is the particle
 // identifier, finished inside each cell bucket by insertion sort (buckets
@@ -14,22 +20,35 @@
 
 namespace dpde {
 
-// Structure-of-arrays particle state in storage (cell-sorted) order.
+struct alignas(64) Rec {
+  double qx, qy, qz;
+  double px, py, pz;
+  double invT;
+  uint32_t id;   // identifier inside the replica
+  uint32_t rep;  // replica index
+};
+static_assert(sizeof(Rec) == 64, "particle record must be one 64-byte block");
+
 struct PState {
-  double *qx, *qy, *qz;
-  double *px, *py, *pz;
-  double *eps, *invT;
-  uint32_t* id;   // identifier inside the replica
-  uint32_t* rep;  // replica index (batched handles)
+  Rec* r;
+  double* eps;
 };
 
-template <bool BATCH>
-__device__ __forceinline__ int rep_of(const PState& s, int64_t i) {
-  if constexpr (BATCH) return (int)s.rep[i];
-  return 0;
+// XCD-aware tile order: the hardware deals workgroups round-robin over the 8
+// XCDs (each with its own L2); the remap makes XCD x work through one
+// contiguous share of the cell-sorted particles, a slab of the box whose
+// neighbour data stays in that XCD's L2.  It is a bijection on [0, nb).
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
+  constexpr unsigned kXcd = 8;
+  const unsigned q = nb / kXcd, r = nb % kXcd;
+  const unsigned x = b % kXcd, k = b / kXcd;
+  // workgroups b = x + 8k with k < q + (x < r) land on XCD x; give them the
+  // consecutive tiles first(x) .. first(x) + q + (x < r) - 1
+  const unsigned first = x * q + (x < r ? x : r);
+  return first + k;
 }
 
-// ---- initial load: AoS rows in identifier order -> SoA ---------------------
+// ---- initial load: AoS rows in identifier order -> records --------------------
 // Row k belongs to the replica r with geo[r].first <= k < geo[r].first + n.
 __global__ void k_load_state(const double* __restrict__ q, const double* __restrict__ p,
                              const double* __restrict__ eps, const Geo* __restrict__ geo, int nrep,
@@ -41,79 +60,111 @@ __global__ void k_load_state(const double* __restrict__ q, const double* __restr
     const int mid = (lo + hi + 1) >> 1;
     if (geo[mid].first <= k) lo = mid; else hi = mid - 1;
   }
-  const double x = q[3 * k], y = q[3 * k + 1], z = q[3 * k + 2];
-  const double a = p[3 * k], b = p[3 * k + 1], c = p[3 * k + 2];
+  Rec rc;
+  rc.qx = q[3 * k]; rc.qy = q[3 * k + 1]; rc.qz = q[3 * k + 2];
+  rc.px = p[3 * k]; rc.py = p[3 * k + 1]; rc.pz = p[3 * k + 2];
+  rc.invT = 0.0;
+  rc.id = (uint32_t)(k - geo[lo].first);
+  rc.rep = (uint32_t)lo;
   const double e = eps[k];
-  s.qx[k] = x; s.qy[k] = y; s.qz[k] = z;
-  s.px[k] = a; s.py[k] = b; s.pz[k] = c;
+  s.r[k] = rc;
   s.eps[k] = e;
-  s.invT[k] = 0.0;
-  s.id[k] = (uint32_t)(k - geo[lo].first);
-  if (s.rep) s.rep[k] = (uint32_t)lo;
-  const bool fin = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(a) && isfinite(b) &&
-                   isfinite(c) && isfinite(e);
+  const bool fin = isfinite(rc.qx) && isfinite(rc.qy) && isfinite(rc.qz) && isfinite(rc.px) &&
+                   isfinite(rc.py) && isfinite(rc.pz) && isfinite(e);
   if (!fin) atomicOr(status, ST_NONFINITE);
   else if (!(e > 0.0)) atomicOr(status, ST_NEG_EINT);
 }
 
-// ---- state out: SoA storage order -> AoS rows in identifier order ------------
-template <bool BATCH>
+// ---- state out: records -> AoS rows in identifier order -----------------------
 __global__ void k_store_state(PState s, const Geo* __restrict__ geo, int64_t n, double* q,
                               double* p, double* eps) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int64_t row = geo[rep_of<BATCH>(s, i)].first + (int64_t)s.id[i];
-  if (q) { q[3 * row] = s.qx[i]; q[3 * row + 1] = s.qy[i]; q[3 * row + 2] = s.qz[i]; }
-  if (p) { p[3 * row] = s.px[i]; p[3 * row + 1] = s.py[i]; p[3 * row + 2] = s.pz[i]; }
+  const Rec rc = s.r[i];
+  const int64_t row = geo[rc.rep].first + (int64_t)rc.id;
+  if (q) { q[3 * row] = rc.qx; q[3 * row + 1] = rc.qy; q[3 * row + 2] = rc.qz; }
+  if (p) { p[3 * row] = rc.px; p[3 * row + 1] = rc.py; p[3 * row + 2] = rc.pz; }
   if (eps) eps[row] = s.eps[i];
 }
 
-template <bool BATCH>
 __global__ void k_store_vec3(PState s, const Geo* __restrict__ geo, int64_t n,
                              const double* __restrict__ x, const double* __restrict__ y,
                              const double* __restrict__ z, double* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int64_t row = geo[rep_of<BATCH>(s, i)].first + (int64_t)s.id[i];
+  const Rec& rc = s.r[i];
+  const int64_t row = geo[rc.rep].first + (int64_t)rc.id;
   out[3 * row] = x[i]; out[3 * row + 1] = y[i]; out[3 * row + 2] = z[i];
 }
 
 // ---- digit 1: kick, drift, wrap, cell key, histogram ------------------------
 // With kick != 0 this is the first half of velocity-Verlet (Sec. 3.1):
 // p += dt/2 F, q += dt p / m, then periodic wrap into [0, L).
+// The identifier is also written to a compact array for the per-cell sort.
+// The histogram update is aggregated per run of equal keys inside a wave (the
+// particles are still nearly in cell order): one atomic per run, the run's
+// lanes take consecutive tickets.  Tiles follow the XCD-aware order, so each
+// XCD's atomics touch its own slab of counters.
 template <bool BATCH>
 __global__ void k_kick_drift_key(PState s, const double* __restrict__ Fx,
                                  const double* __restrict__ Fy, const double* __restrict__ Fz,
                                  int64_t n, const Geo* __restrict__ geo, Phys P, int kick,
                                  uint32_t* __restrict__ key, uint32_t* __restrict__ ticket,
-                                 uint32_t* __restrict__ count, uint32_t* status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (status_set(status)) return;
-  const Geo& g = geo[rep_of<BATCH>(s, i)];
-  double q[3] = {s.qx[i], s.qy[i], s.qz[i]};
-  if (kick) {
-    double p[3] = {s.px[i], s.py[i], s.pz[i]};
-    const double F[3] = {Fx[i], Fy[i], Fz[i]};
+                                 uint32_t* __restrict__ idk, uint32_t* __restrict__ count,
+                                 uint32_t* status) {
+  const int64_t i = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (status_set(status)) return;  // uniform: the whole grid leaves together
+  const bool live = i < n;
+  uint32_t c = 0xFFFFFFFFu;
+  if (live) {
+    Rec rc = s.r[i];
+    const Geo& g = geo[BATCH ? rc.rep : 0u];
+    double q[3] = {rc.qx, rc.qy, rc.qz};
+    if (kick) {
+      double p[3] = {rc.px, rc.py, rc.pz};
+      const double F[3] = {Fx[i], Fy[i], Fz[i]};
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      p[d] = p[d] + P.half_dt * F[d];
-      q[d] = q[d] + P.dt * p[d] / P.mass;
+      for (int d = 0; d < 3; ++d) {
+        p[d] = p[d] + P.half_dt * F[d];
+        q[d] = q[d] + P.dt * p[d] / P.mass;
+      }
+      rc.px = p[0]; rc.py = p[1]; rc.pz = p[2];
+      if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) atomicOr(status, ST_NONFINITE);
     }
-    s.px[i] = p[0]; s.py[i] = p[1]; s.pz[i] = p[2];
-    if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) atomicOr(status, ST_NONFINITE);
-  }
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
-    if (g.periodic[d]) q[d] = wrap_coord(q[d], g.box[d]);
-  s.qx[i] = q[0]; s.qy[i] = q[1]; s.qz[i] = q[2];
-  if (!(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]))) atomicOr(status, ST_NONFINITE);
-  const int cx = cell_coord(q[0], g.scale[0], g.nc[0]);
-  const int cy = cell_coord(q[1], g.scale[1], g.nc[1]);
-  const int cz = cell_coord(q[2], g.scale[2], g.nc[2]);
-  const uint32_t c = (uint32_t)(g.cell_base + cx + (int64_t)g.nc[0] * (cy + (int64_t)g.nc[1] * cz));
-  key[i] = c;
-  ticket[i] = atomicAdd(&count[c], 1u);
+    for (int d = 0; d < 3; ++d)
+      if (g.periodic[d]) q[d] = wrap_coord(q[d], g.box[d]);
+    rc.qx = q[0]; rc.qy = q[1]; rc.qz = q[2];
+    s.r[i] = rc;
+    if (!(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]))) atomicOr(status, ST_NONFINITE);
+    const int cx = cell_coord(q[0], g.scale[0], g.nc[0]);
+    const int cy = cell_coord(q[1], g.scale[1], g.nc[1]);
+    const int cz = cell_coord(q[2], g.scale[2], g.nc[2]);
+    c = (uint32_t)(g.cell_base + cx + (int64_t)g.nc[0] * (cy + (int64_t)g.nc[1] * cz));
+    key[i] = c;
+    idk[i] = rc.id;
+  }
+  // runs of equal keys among consecutive lanes
+  const int lane = threadIdx.x % kWave;
+  const uint32_t prev = __shfl_up(c, 1, kWave);
+  const bool head = live && (lane == 0 || prev != c);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long below = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+  const int my_head = 63 - __clzll(heads & below);  // last head at or below this lane
+  const unsigned long long above = heads & ~below;   // heads strictly above
+  const int next_head = above ? __ffsll((long long)above) - 1 : kWave;
+  // the run of a head ends before the next head or at the first dead lane
+  const unsigned long long alive = __ballot(live);
+  int run_end = next_head;
+  const unsigned long long dead_above = ~alive & ~below;
+  if (dead_above) {
+    const int first_dead = __ffsll((long long)dead_above) - 1;
+    if (first_dead < run_end) run_end = first_dead;
+  }
+  uint32_t base = 0;
+  if (head) base = atomicAdd(&count[c], (uint32_t)(run_end - lane));
+  base = __shfl(base, my_head, kWave);
+  if (live) ticket[i] = base + (uint32_t)(lane - my_head);
 }
 
 // ---- exclusive scan of the cell histogram -> cell offsets --------------------
@@ -221,7 +272,7 @@ __global__ void k_scatter(const uint32_t* __restrict__ key, const uint32_t* __re
 
 // ---- digit 2: order each cell bucket by identifier ---------------------------
 __global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncells,
-                            uint32_t* __restrict__ perm, const uint32_t* __restrict__ id,
+                            uint32_t* __restrict__ perm, const uint32_t* __restrict__ idk,
                             const uint32_t* status) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
@@ -229,11 +280,11 @@ __global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncells,
   const uint32_t b = start[c], e = start[c + 1];
   for (uint32_t k = b + 1; k < e; ++k) {
     const uint32_t v = perm[k];
-    const uint32_t kv = id[v];
+    const uint32_t kv = idk[v];
     uint32_t m = k;
     while (m > b) {
       const uint32_t u = perm[m - 1];
-      if (id[u] <= kv) break;
+      if (idk[u] <= kv) break;
       perm[m] = u;
       --m;
     }
@@ -249,12 +300,8 @@ __global__ void k_gather(PState src, PState dst, const uint32_t* __restrict__ pe
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t k = status_set(status) ? (uint32_t)i : perm[i];
-  dst.qx[i] = src.qx[k]; dst.qy[i] = src.qy[k]; dst.qz[i] = src.qz[k];
-  dst.px[i] = src.px[k]; dst.py[i] = src.py[k]; dst.pz[i] = src.pz[k];
+  dst.r[i] = src.r[k];
   dst.eps[i] = src.eps[k];
-  dst.invT[i] = src.invT[k];
-  dst.id[i] = src.id[k];
-  if (dst.rep) dst.rep[i] = src.rep[k];
 }
 
 }  // namespace dpde

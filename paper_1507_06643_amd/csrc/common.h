@@ -97,19 +97,28 @@ __device__ __forceinline__ void box_muller_f64(const uint32_t w[4], double G[3])
   G[2] = r2 * cospi(2.0 * u3);
 }
 
-// FP32 normals from the same words: the top 24 bits give u in (0,1) exactly;
-// the hardware sine/cosine take their argument in turns, so sin(2 pi u) is
-// one instruction.
+// ln u for u = (x + 1/2) 2^-32 in FP32.  Far from 1 the float of x keeps 24
+// significant bits at every magnitude (the tails keep full relative
+// precision); within 2^-8 of 1, ln u = ln(1 - v) is summed as a series in the
+// complement v = (~x + 1/2) 2^-32, which the float grid below 1 cannot resolve.
+__device__ __forceinline__ float ln_uniform_f32(uint32_t x) {
+  const float two_m32 = 2.3283064365386963e-10f;
+  if (x >= 0xFF000000u) {
+    const float v = ((float)(~x) + 0.5f) * two_m32;
+    return -v * (1.0f + v * (0.5f + v * 0.33333334f));
+  }
+  const float u = ((float)x + 0.5f) * two_m32;
+  return 0.6931471805599453f * __builtin_amdgcn_logf(u);  // ln 2 * log2 u
+}
+
+// FP32 normals from the same words; the hardware sine/cosine take their
+// argument in turns, so sin(2 pi u) is one instruction.
 __device__ __forceinline__ void box_muller_f32(const uint32_t w[4], float G[3]) {
-  const float s = 5.9604644775390625e-08f;  // 2^-24
-  const float h = 2.98023223876953125e-08f; // 2^-25
-  const float u0 = (float)(w[0] >> 8) * s + h;
-  const float u1 = (float)(w[1] >> 8) * s + h;
-  const float u2 = (float)(w[2] >> 8) * s + h;
-  const float u3 = (float)(w[3] >> 8) * s + h;
-  const float ln2x2 = -1.3862943611198906f;  // -2 ln 2: -2 ln u = -2 ln2 log2 u
-  const float r1 = __builtin_sqrtf(ln2x2 * __builtin_amdgcn_logf(u0));
-  const float r2 = __builtin_sqrtf(ln2x2 * __builtin_amdgcn_logf(u2));
+  const float two_m32 = 2.3283064365386963e-10f;
+  const float r1 = __builtin_sqrtf(-2.0f * ln_uniform_f32(w[0]));
+  const float r2 = __builtin_sqrtf(-2.0f * ln_uniform_f32(w[2]));
+  const float u1 = (float)w[1] * two_m32;
+  const float u3 = (float)w[3] * two_m32;
   G[0] = r1 * __builtin_amdgcn_cosf(u1);
   G[1] = r1 * __builtin_amdgcn_sinf(u1);
   G[2] = r2 * __builtin_amdgcn_cosf(u3);

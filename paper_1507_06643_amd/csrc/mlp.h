@@ -125,8 +125,9 @@ struct MlpDev {
 // Newton alone.  No lane leaves before the matrix-core step.
 template <int OUT_INV>
 __global__ __launch_bounds__(256) void k_theta(const double* __restrict__ eps, double* __restrict__ out,
-                                               int32_t* __restrict__ iters, int64_t n, Phys P,
-                                               MlpDev m, int mode, uint32_t* status) {
+                                               int64_t ostride, int32_t* __restrict__ iters,
+                                               int64_t n, Phys P, MlpDev m, int mode,
+                                               uint32_t* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < n;
   const double e = valid ? eps[i] : 1.0;
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(256) void k_theta(const double* __restrict__ eps, d
   if (!(th > 0.0) || !isfinite(th)) {
     if (status) atomicOr(status, ST_EOS);
   }
-  out[i] = OUT_INV ? 1.0 / th : th;
+  out[i * ostride] = OUT_INV ? 1.0 / th : th;
   if (iters) iters[i] = it;
 }
 
@@ -381,19 +382,20 @@ inline void mlp_attach(MlpState& s, Phys& P) {
   P.mlp_eps_hi = s.eps_hi;
 }
 
-// 1/theta of the state's internal energies with the handle's theta mode.
+// 1/theta of the state's internal energies with the handle's theta mode,
+// written with a stride (in doubles) into the particle records.
 inline void enqueue_theta_mlp(MlpState& s, hipStream_t st, const double* eps, double* invT,
-                              int64_t n, const Phys& P, uint32_t* status) {
+                              int64_t stride, int64_t n, const Phys& P, uint32_t* status) {
   const int mode = s.trained ? P.theta_mode : 0;
   hipLaunchKernelGGL(k_theta<1>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, eps, invT,
-                     (int32_t*)nullptr, n, P, mlp_dev(s), mode, status);
+                     stride, (int32_t*)nullptr, n, P, mlp_dev(s), mode, status);
 }
 
 inline void launch_theta(MlpState& s, hipStream_t st, const double* eps, double* theta,
                          int32_t* iters, int64_t n, const Phys& P, int mode) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_theta<0>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, eps, theta,
-                     iters, n, P, mlp_dev(s), mode, (uint32_t*)nullptr);
+                     (int64_t)1, iters, n, P, mlp_dev(s), mode, (uint32_t*)nullptr);
 }
 
 inline int mlp_set(MlpState& s, const Phys& P, const float* w, const double* norm4,

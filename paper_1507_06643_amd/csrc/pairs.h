@@ -2,15 +2,21 @@
 //
 //   pass A  conservative forces at the new positions, neighbour list build,
 //           second half-kick of velocity-Verlet (Sec. 3.1);
-//   pass B  SER sweep 1: dp_i = sum_j dp_ij (eq. SER_p);
-//   pass C  SER sweep 2: regenerate dp_ij from the same counter-based noise,
-//           internal-energy reinjection (eq. SER_eint_discretization),
-//           p <- p + dp, eps <- eps + d eps, next 1/T_i.
+//   pass B  SER sweep 1: dp_ij and dp_i = sum_j dp_ij (eq. SER_p);
+//   pass C  SER sweep 2: internal-energy reinjection
+//           (eq. SER_eint_discretization), p <- p + dp, eps <- eps + d eps,
+//           next 1/T_i.
 //
 // One lane per particle; each pair term is evaluated on both of its
 // particles' lanes in the canonical orientation (lower identifier first) and
 // negated on the higher one, so dp_ji = -dp_ij bit for bit and the particle
 // sums are plain gathers: no atomics, fixed summation order.
+//
+// Sweep 2 needs the same dp_ij as sweep 1.  The paper regenerates the noise
+// from (i, j, n) to avoid storing the increments; with HBM to spare, sweep 1
+// here stores dp_ij per neighbour-list entry and sweep 2 reads it back, which
+// removes the random-number generation and the pair geometry from sweep 2.
+// The regenerating form is kept (Phys::regen) and gives identical bits.
 #pragma once
 
 #include "bin.h"
@@ -22,12 +28,25 @@ constexpr int kPairBlockMax = 256;
 
 enum : int { PREC_F64 = 0, PREC_F32 = 1 };
 
+struct alignas(32) DP {
+  double x, y, z, pad;
+};
+
+// Momentum after the conservative half-kick and the sweep-1 increment of one
+// particle, packed so that sweep 2 gathers one line per neighbour.
+struct alignas(64) PV {
+  double px, py, pz;
+  double dx, dy, dz;
+  double pad0, pad1;
+};
+
 // Neighbour list: k-major (entry k of particle i at k*n + i), so the lanes of
-// a wave read consecutive words.
+// a wave read and write consecutive words for a given k.
 struct NList {
   uint32_t* idx;
   uint32_t* count;
-  int64_t stride;  // n
+  double *dex, *dey, *dez;  // dp_ij per entry (stored-increment form), same layout
+  int64_t stride;           // n
 };
 
 // Up to two contiguous cell ranges along x for the stencil row (y, z).
@@ -97,64 +116,131 @@ __device__ __forceinline__ void separation(const Geo& g, double xi, double yi, d
   if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
 }
 
+__device__ __forceinline__ int64_t tile_index() {
+  return (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+
 // ---------------------------------------------------------------------------
 // Pass A: forces F_i = sum_j a (1 - r/rc) d_ij / r, U_i = 1/2 sum_j v(r_ij),
 // neighbour list; mode 1 also applies p += dt/2 F (end of velocity-Verlet).
+//
+// Each lane finds its neighbours at its own pace; the list is staged in LDS
+// (k-major per block) and written to HBM at the end, one coalesced store per
+// k, instead of scattered partial-line stores during the search.  A wave whose
+// particles all sit in interior cells (no periodic image reachable through the
+// stencil) skips the minimum-image test, which is then the identity.
 // ---------------------------------------------------------------------------
+constexpr int kListLds = 32;
+
+// Phase 1 of pass A: visit the 27-cell stencil and hand every neighbour with
+// r^2 < rc^2 to `sink`.  Only the pair predicate is evaluated here, so the
+// divergent candidate loop stays short; the force arithmetic runs afterwards
+// over the compact list.
+template <bool MI, typename Sink>
+__device__ __forceinline__ void scan_candidates(const Geo& g, const uint32_t* __restrict__ start,
+                                                const Rec* __restrict__ R, int64_t i, double xi,
+                                                double yi, double zi, int cx, int cy, int cz,
+                                                double rc2, Sink&& sink) {
+  auto test = [&](uint32_t j, double xj, double yj, double zj) {
+    double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+    if constexpr (MI) {
+      if (g.periodic[0]) dx = min_image(dx, g.box[0], g.half_box[0]);
+      if (g.periodic[1]) dy = min_image(dy, g.box[1], g.half_box[1]);
+      if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
+    }
+    if (dist2(dx, dy, dz) < rc2 && j != (uint32_t)i) sink(j);
+  };
+  auto range = [&](uint32_t jb, uint32_t je) {
+    uint32_t j = jb;
+    // two candidates per trip: both position loads are in flight together
+    for (; j + 1 < je; j += 2) {
+      const double x0 = R[j].qx, y0 = R[j].qy, z0 = R[j].qz;
+      const double x1 = R[j + 1].qx, y1 = R[j + 1].qy, z1 = R[j + 1].qz;
+      test(j, x0, y0, z0);
+      test(j + 1, x1, y1, z1);
+    }
+    if (j < je) test(j, R[j].qx, R[j].qy, R[j].qz);
+  };
+  const Row row = stencil_row(cx, g.nc[0], g.periodic[0]);
+  for (int dz = -1; dz <= 1; ++dz) {
+    int z = cz + dz;
+    if (!wrap_cell(z, g.nc[2], g.periodic[2])) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      int y = cy + dy;
+      if (!wrap_cell(y, g.nc[1], g.periodic[1])) continue;
+      const int64_t base = g.cell_base + (int64_t)g.nc[0] * (y + (int64_t)g.nc[1] * z);
+      range(start[base + row.a0], start[base + row.b0 + 1]);
+      if (row.a1 <= row.b1) range(start[base + row.a1], start[base + row.b1 + 1]);
+    }
+  }
+}
+
+__device__ __forceinline__ bool interior_dim(int c, int nc, int periodic) {
+  // cells c-1..c+1 exist without wrapping and are closer than half a box
+  return !periodic || (nc >= 4 && c >= 1 && c <= nc - 2);
+}
+
 template <bool BATCH, int PREC>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
     PState s, const uint32_t* __restrict__ start, int64_t n, const Geo* __restrict__ geo, Phys P,
     int mode, double* __restrict__ Fx, double* __restrict__ Fy, double* __restrict__ Fz,
     double* __restrict__ Ui, NList nl, uint32_t* status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ uint32_t lst[kListLds * kPairBlockMax];
+  const int64_t i = tile_index();
   if (i >= n) return;
   if (status_set(status)) return;
-  const Geo& g = geo[rep_of<BATCH>(s, i)];
-  const double xi = s.qx[i], yi = s.qy[i], zi = s.qz[i];
+  const int tid = threadIdx.x, bd = blockDim.x;
+  const Rec* __restrict__ R = s.r;
+  const double xi = R[i].qx, yi = R[i].qy, zi = R[i].qz;
+  const Geo& g = geo[BATCH ? R[i].rep : 0u];
   const int cx = cell_coord(xi, g.scale[0], g.nc[0]);
   const int cy = cell_coord(yi, g.scale[1], g.nc[1]);
   const int cz = cell_coord(zi, g.scale[2], g.nc[2]);
-  const double* __restrict__ qx = s.qx;
-  const double* __restrict__ qy = s.qy;
-  const double* __restrict__ qz = s.qz;
-  double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0;
   uint32_t nn = 0;
   const uint32_t cap = (uint32_t)P.cap;
-  const float inv_rc_f = (float)P.inv_rc, a_f = (float)P.a;
-  for_each_candidate(g, start, cx, cy, cz, [&](uint32_t j) {
-    if (j == (uint32_t)i) return;
-    double dx, dy, dz;
-    separation(g, xi, yi, zi, qx[j], qy[j], qz[j], dx, dy, dz);
-    const double r2 = dist2(dx, dy, dz);
-    if (r2 < P.rc2) {
-      if (nn < cap) nl.idx[(int64_t)nn * nl.stride + i] = j;
-      ++nn;
-      if constexpr (PREC == PREC_F64) {
-        const double r = sqrt(r2);
-        const double w = 1.0 - r * P.inv_rc;
-        u += w * w;
-        if (r > 0.0) {
-          const double f = P.a * w / r;
-          fx += f * dx;
-          fy += f * dy;
-          fz += f * dz;
-        }
-      } else {
-        const float r = __builtin_sqrtf((float)r2);
-        const float w = 1.0f - r * inv_rc_f;
-        u += (double)(w * w);
-        if (r > 0.0f) {
-          const float f = a_f * w / r;
-          fx += (double)(f * (float)dx);
-          fy += (double)(f * (float)dy);
-          fz += (double)(f * (float)dz);
-        }
-      }
-    }
-  });
+  // phase 1: neighbour list (staged in LDS, k-major per block)
+  auto sink = [&](uint32_t j) {
+    if (nn < (uint32_t)kListLds) lst[nn * bd + tid] = j;
+    else if (nn < cap) nl.idx[(int64_t)nn * nl.stride + i] = j;
+    ++nn;
+  };
+  const bool interior = interior_dim(cx, g.nc[0], g.periodic[0]) &&
+                        interior_dim(cy, g.nc[1], g.periodic[1]) &&
+                        interior_dim(cz, g.nc[2], g.periodic[2]);
+  if (__all(interior))
+    scan_candidates<false>(g, start, R, i, xi, yi, zi, cx, cy, cz, P.rc2, sink);
+  else
+    scan_candidates<true>(g, start, R, i, xi, yi, zi, cx, cy, cz, P.rc2, sink);
   if (nn > cap) {
     atomicOr(status, ST_OVERFLOW);
     nn = cap;
+  }
+  // phase 2: forces over the compact list, in list order
+  double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0;
+  const float inv_rc_f = (float)P.inv_rc, a_f = (float)P.a;
+  for (uint32_t k = 0; k < nn; ++k) {
+    const uint32_t j = k < (uint32_t)kListLds ? lst[k * bd + tid] : nl.idx[(int64_t)k * nl.stride + i];
+    if (k < (uint32_t)kListLds) nl.idx[(int64_t)k * nl.stride + i] = j;
+    double dx, dy, dz;
+    separation(g, xi, yi, zi, R[j].qx, R[j].qy, R[j].qz, dx, dy, dz);
+    const double r2 = dist2(dx, dy, dz);
+    if constexpr (PREC == PREC_F64) {
+      const double r = sqrt(r2);
+      const double w = 1.0 - r * P.inv_rc;
+      u += w * w;
+      const double f = r > 0.0 ? P.a * w / r : 0.0;
+      fx += f * dx;
+      fy += f * dy;
+      fz += f * dz;
+    } else {
+      const float r = __builtin_sqrtf((float)r2);
+      const float w = 1.0f - r * inv_rc_f;
+      u += (double)(w * w);
+      const float f = r > 0.0f ? a_f * w / r : 0.0f;
+      fx += (double)(f * (float)dx);
+      fy += (double)(f * (float)dy);
+      fz += (double)(f * (float)dz);
+    }
   }
   nl.count[i] = nn;
   Fx[i] = fx;
@@ -162,9 +248,10 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
   Fz[i] = fz;
   Ui[i] = 0.5 * P.half_a_rc * u;
   if (mode) {
-    s.px[i] = s.px[i] + P.half_dt * fx;
-    s.py[i] = s.py[i] + P.half_dt * fy;
-    s.pz[i] = s.pz[i] + P.half_dt * fz;
+    Rec* W = s.r;
+    W[i].px = W[i].px + P.half_dt * fx;
+    W[i].py = W[i].py + P.half_dt * fy;
+    W[i].pz = W[i].pz + P.half_dt * fz;
   }
 }
 
@@ -227,47 +314,63 @@ __device__ __forceinline__ void ser_pair(const Phys& P, const Geo& g, double r2,
   }
 }
 
+// dp_ij of neighbour j seen from the record of particle i.
+template <int PREC>
+__device__ __forceinline__ void pair_from_records(const Phys& P, const Geo& g, const Rec& a,
+                                                  const Rec& b, uint64_t step, double& vx,
+                                                  double& vy, double& vz, PairOut& o) {
+  double dx, dy, dz;
+  separation(g, a.qx, a.qy, a.qz, b.qx, b.qy, b.qz, dx, dy, dz);
+  const double r2 = dist2(dx, dy, dz);
+  vx = a.px * P.inv_mass - b.px * P.inv_mass;
+  vy = a.py * P.inv_mass - b.py * P.inv_mass;
+  vz = a.pz * P.inv_mass - b.pz * P.inv_mass;
+  ser_pair<PREC>(P, g, r2, vx, vy, vz, a.invT + b.invT, a.id, b.id, step, o);
+}
+
 // ---------------------------------------------------------------------------
 // Pass B (SER sweep 1, and the whole SEM update of eq. SEM_fd).
 // ---------------------------------------------------------------------------
 template <bool BATCH, int PREC, int SCHEME>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
-    const uint64_t* __restrict__ d_step, double* __restrict__ dpx, double* __restrict__ dpy,
-    double* __restrict__ dpz, double* __restrict__ deps, uint32_t* status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t* __restrict__ d_step, PV* __restrict__ pv, double* __restrict__ deps,
+    int store, uint32_t* status) {
+  const int64_t i = tile_index();
   if (i >= n) return;
   if (status_set(status)) return;
   const uint64_t step = *d_step;
-  const Geo& g = geo[rep_of<BATCH>(s, i)];
-  const double xi = s.qx[i], yi = s.qy[i], zi = s.qz[i];
-  const double vxi = s.px[i] * P.inv_mass, vyi = s.py[i] * P.inv_mass, vzi = s.pz[i] * P.inv_mass;
-  const double iTi = s.invT[i];
-  const uint32_t idi = s.id[i];
+  const Rec* __restrict__ R = s.r;
+  const Rec a = R[i];
+  const Geo& g = geo[BATCH ? a.rep : 0u];
   const uint32_t nn = nl.count[i];
   double ax = 0.0, ay = 0.0, az = 0.0, de = 0.0;
+  // software pipeline: the record of neighbour k+1 is requested before the
+  // pair term of neighbour k is computed
+  Rec nb;
+  if (nn > 0) nb = R[nl.idx[i]];
   for (uint32_t k = 0; k < nn; ++k) {
-    const uint32_t j = nl.idx[(int64_t)k * nl.stride + i];
-    double dx, dy, dz;
-    separation(g, xi, yi, zi, s.qx[j], s.qy[j], s.qz[j], dx, dy, dz);
-    const double r2 = dist2(dx, dy, dz);
-    const double vx = vxi - s.px[j] * P.inv_mass;
-    const double vy = vyi - s.py[j] * P.inv_mass;
-    const double vz = vzi - s.pz[j] * P.inv_mass;
+    const int64_t e = (int64_t)k * nl.stride + i;
+    const Rec b = nb;
+    if (k + 1 < nn) nb = R[nl.idx[e + nl.stride]];
+    double vx, vy, vz;
     PairOut o;
-    ser_pair<PREC>(P, g, r2, vx, vy, vz, iTi + s.invT[j], idi, s.id[j], step, o);
+    pair_from_records<PREC>(P, g, a, b, step, vx, vy, vz, o);
     ax += o.dp[0];
     ay += o.dp[1];
     az += o.dp[2];
+    if (store) {
+      nl.dex[e] = o.dp[0];
+      nl.dey[e] = o.dp[1];
+      nl.dez[e] = o.dp[2];
+    }
     if constexpr (SCHEME == 1) {
       const double v2 = vx * vx + vy * vy + vz * vz;
       de += 0.5 * (o.gij * v2 - P.dsigma2_m) * o.chi * P.dt -
             0.5 * P.sigma * o.w * o.gdotv * P.sqrt_dt;
     }
   }
-  dpx[i] = ax;
-  dpy[i] = ay;
-  dpz[i] = az;
+  pv[i] = PV{a.px, a.py, a.pz, ax, ay, az, 0.0, 0.0};
   if constexpr (SCHEME == 1) deps[i] = de;
 }
 
@@ -285,76 +388,91 @@ __device__ __forceinline__ double inv_temperature(const Phys& P, double eps, uin
 // ---------------------------------------------------------------------------
 // Pass C (SER sweep 2): d eps_i = -1/2 sum_j dp_ij . (v_ij + (dp_i - dp_j)/(2m))
 // in FP64 for both precisions, then p <- p + dp, eps <- eps + d eps and the
-// next 1/T_i.  The updated momenta and 1/T are written to (pxo, pyo, pzo,
-// invTo), never over the arrays this pass gathers from.
+// next 1/T_i.  The new records go to `out`, never over the records this pass
+// gathers from.
 // ---------------------------------------------------------------------------
-template <bool BATCH, int PREC>
+template <bool BATCH, int PREC, int REGEN>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
-    const uint64_t* __restrict__ d_step, const double* __restrict__ dpx,
-    const double* __restrict__ dpy, const double* __restrict__ dpz, int eos_inline,
-    double* __restrict__ pxo, double* __restrict__ pyo, double* __restrict__ pzo,
-    double* __restrict__ invTo, uint32_t* status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t* __restrict__ d_step, const PV* __restrict__ pv, int eos_inline,
+    Rec* __restrict__ out, uint32_t* status) {
+  const int64_t i = tile_index();
   if (i >= n) return;
   if (status_set(status)) return;
   const uint64_t step = *d_step;
-  const Geo& g = geo[rep_of<BATCH>(s, i)];
-  const double xi = s.qx[i], yi = s.qy[i], zi = s.qz[i];
-  const double pxi = s.px[i], pyi = s.py[i], pzi = s.pz[i];
-  const double vxi = pxi * P.inv_mass, vyi = pyi * P.inv_mass, vzi = pzi * P.inv_mass;
-  const double dxi = dpx[i], dyi = dpy[i], dzi = dpz[i];
-  const double iTi = s.invT[i];
-  const uint32_t idi = s.id[i];
+  const Rec* __restrict__ R = s.r;
+  const Rec a = R[i];
+  const Geo& g = geo[BATCH ? a.rep : 0u];
+  const PV di = pv[i];
+  const double vxi = a.px * P.inv_mass, vyi = a.py * P.inv_mass, vzi = a.pz * P.inv_mass;
   const uint32_t nn = nl.count[i];
   double de = 0.0;
+  uint32_t jn = nn > 0 ? nl.idx[i] : 0u;
+  PV nv;
+  if (nn > 0) nv = pv[jn];
   for (uint32_t k = 0; k < nn; ++k) {
-    const uint32_t j = nl.idx[(int64_t)k * nl.stride + i];
-    double dx, dy, dz;
-    separation(g, xi, yi, zi, s.qx[j], s.qy[j], s.qz[j], dx, dy, dz);
-    const double r2 = dist2(dx, dy, dz);
-    const double vx = vxi - s.px[j] * P.inv_mass;
-    const double vy = vyi - s.py[j] * P.inv_mass;
-    const double vz = vzi - s.pz[j] * P.inv_mass;
-    PairOut o;
-    ser_pair<PREC>(P, g, r2, vx, vy, vz, iTi + s.invT[j], idi, s.id[j], step, o);
-    const double ux = vx + (dxi - dpx[j]) * P.inv_2m;
-    const double uy = vy + (dyi - dpy[j]) * P.inv_2m;
-    const double uz = vz + (dzi - dpz[j]) * P.inv_2m;
-    de += -0.5 * (o.dp[0] * ux + o.dp[1] * uy + o.dp[2] * uz);
+    const int64_t e = (int64_t)k * nl.stride + i;
+    const uint32_t j = jn;
+    const PV dj = nv;
+    if (k + 1 < nn) {
+      jn = nl.idx[e + nl.stride];
+      nv = pv[jn];
+    }
+    double ex, ey, ez, vx, vy, vz;
+    if constexpr (REGEN) {
+      const Rec b = R[j];
+      PairOut o;
+      pair_from_records<PREC>(P, g, a, b, step, vx, vy, vz, o);
+      ex = o.dp[0];
+      ey = o.dp[1];
+      ez = o.dp[2];
+    } else {
+      ex = nl.dex[e];
+      ey = nl.dey[e];
+      ez = nl.dez[e];
+      vx = vxi - dj.px * P.inv_mass;
+      vy = vyi - dj.py * P.inv_mass;
+      vz = vzi - dj.pz * P.inv_mass;
+    }
+    const double ux = vx + (di.dx - dj.dx) * P.inv_2m;
+    const double uy = vy + (di.dy - dj.dy) * P.inv_2m;
+    const double uz = vz + (di.dz - dj.dz) * P.inv_2m;
+    de += -0.5 * (ex * ux + ey * uy + ez * uz);
   }
-  // new momenta and 1/T go to separate arrays: other lanes are still reading
-  // p_j and 1/T_j of this particle for their own pair terms
-  pxo[i] = pxi + dxi;
-  pyo[i] = pyi + dyi;
-  pzo[i] = pzi + dzi;
+  Rec o = a;
+  o.px = a.px + di.dx;
+  o.py = a.py + di.dy;
+  o.pz = a.pz + di.dz;
   const double e = s.eps[i] + de;
   s.eps[i] = e;
   if (!(e > 0.0)) {
     atomicOr(status, ST_NEG_EINT);
-    invTo[i] = iTi;
-    return;
+  } else if (eos_inline) {
+    o.invT = inv_temperature(P, e, status);
   }
-  invTo[i] = eos_inline ? inv_temperature(P, e, status) : iTi;
+  out[i] = o;
 }
 
 // SEM: apply dp and d eps (both from pass B), then the next 1/T_i.
-__global__ void k_apply_sem(PState s, int64_t n, Phys P, const double* __restrict__ dpx,
-                            const double* __restrict__ dpy, const double* __restrict__ dpz,
-                            const double* __restrict__ deps, int eos_inline, uint32_t* status) {
+__global__ void k_apply_sem(PState s, int64_t n, Phys P, const PV* __restrict__ pv,
+                            const double* __restrict__ deps, int eos_inline,
+                            Rec* __restrict__ out, uint32_t* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (status_set(status)) return;
-  s.px[i] += dpx[i];
-  s.py[i] += dpy[i];
-  s.pz[i] += dpz[i];
+  Rec o = s.r[i];
+  const PV d = pv[i];
+  o.px += d.dx;
+  o.py += d.dy;
+  o.pz += d.dz;
   const double e = s.eps[i] + deps[i];
   s.eps[i] = e;
   if (!(e > 0.0)) {
     atomicOr(status, ST_NEG_EINT);
-    return;
+  } else if (eos_inline) {
+    o.invT = inv_temperature(P, e, status);
   }
-  if (eos_inline) s.invT[i] = inv_temperature(P, e, status);
+  out[i] = o;
 }
 
 // 1/T_i for every particle (initialisation and the separate-EOS path).
@@ -366,7 +484,7 @@ __global__ void k_inv_temperature(PState s, int64_t n, Phys P, uint32_t* status)
     atomicOr(status, ST_NEG_EINT);
     return;
   }
-  s.invT[i] = inv_temperature(P, e, status);
+  s.r[i].invT = inv_temperature(P, e, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -381,7 +499,8 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_tiles(
   const int64_t b = tile_begin[blockIdx.x], e = tile_begin[blockIdx.x + 1];
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
-    const double px = s.px[i], py = s.py[i], pz = s.pz[i];
+    const Rec& rc = s.r[i];
+    const double px = rc.px, py = rc.py, pz = rc.pz;
     const double p2 = px * px + py * py + pz * pz;
     v[0] += Ui[i];
     v[1] += p2 / (2.0 * P.mass);
@@ -389,7 +508,7 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_tiles(
     v[3] += px;
     v[4] += py;
     v[5] += pz;
-    v[6] += s.invT[i];
+    v[6] += rc.invT;
   }
   __shared__ double smem[7 * (kStatThreads / kWave)];
   block_sum<7>(v, smem);
@@ -441,31 +560,30 @@ __global__ void k_step_advance(uint64_t* d_step, int64_t* d_hist_count, const ui
 // ---------------------------------------------------------------------------
 // Test hooks.
 // ---------------------------------------------------------------------------
-template <bool BATCH>
 __global__ void k_debug_cells(PState s, int64_t n, const Geo* __restrict__ geo, int32_t* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const Geo& g = geo[rep_of<BATCH>(s, i)];
-  const int cx = cell_coord(s.qx[i], g.scale[0], g.nc[0]);
-  const int cy = cell_coord(s.qy[i], g.scale[1], g.nc[1]);
-  const int cz = cell_coord(s.qz[i], g.scale[2], g.nc[2]);
-  out[g.first + s.id[i]] = cx + g.nc[0] * (cy + g.nc[1] * cz);
+  const Rec& rc = s.r[i];
+  const Geo& g = geo[rc.rep];
+  const int cx = cell_coord(rc.qx, g.scale[0], g.nc[0]);
+  const int cy = cell_coord(rc.qy, g.scale[1], g.nc[1]);
+  const int cz = cell_coord(rc.qz, g.scale[2], g.nc[2]);
+  out[g.first + rc.id] = cx + g.nc[0] * (cy + g.nc[1] * cz);
 }
 
-template <bool BATCH>
 __global__ void k_debug_pairs(PState s, NList nl, int64_t n, const Geo* __restrict__ geo,
                               int32_t* out, int64_t cap, unsigned long long* counter) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const Geo& g = geo[rep_of<BATCH>(s, i)];
-  const uint32_t idi = s.id[i];
+  const Rec& a = s.r[i];
+  const Geo& g = geo[a.rep];
   for (uint32_t k = 0; k < nl.count[i]; ++k) {
     const uint32_t j = nl.idx[(int64_t)k * nl.stride + i];
-    const uint32_t idj = s.id[j];
-    if (idi < idj) {
+    const uint32_t idj = s.r[j].id;
+    if (a.id < idj) {
       const unsigned long long slot = atomicAdd(counter, 1ull);
       if ((int64_t)slot < cap) {
-        out[2 * slot] = (int32_t)(g.first + idi);
+        out[2 * slot] = (int32_t)(g.first + a.id);
         out[2 * slot + 1] = (int32_t)(g.first + idj);
       }
     }

@@ -1,0 +1,336 @@
+"""GPU tests of the variants around the plain FP64 path: FP32 pair terms,
+nonlinear EOS, the surrogate network, batched replicas, graph replay, SEM,
+failure codes, and the full 1M-particle size."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dp():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1507_06643_amd as m
+    return m
+
+
+def _gpu_state(s):
+    q, p, e, st = s.get_state()
+    return q.cpu().numpy(), p.cpu().numpy(), e.cpu().numpy(), st
+
+
+def _one_step_vs_oracle(dp, n, box, periodic=(1, 1, 1), prime=3, **kw):
+    """Advance `prime` steps on the GPU, then compare one more GPU step with
+    the oracle's step from the same state; returns the max errors (q/L, p,
+    eps/mean eps) and the energy records."""
+    okw = {k: v for k, v in kw.items() if k not in ("precision", "theta_mode")}
+    eps0 = kw.pop("eps0", 100.0)
+    okw.pop("eps0", None)
+    q, p, e = W.equilibrium_state(n, box, seed=n + 7, eps0=eps0)
+    s = dp.System(dp.Config(n=n, box=list(box), periodic=periodic, **kw), q, p, e)
+    s.step(prime)
+    qs, ps, es, st = _gpu_state(s)
+    S = O.State(O.make_params(n, box, periodic=periodic, step=st, **okw), qs, ps, es)
+    rc, _ = S.step(1)
+    assert rc == 0
+    s.step(1)
+    qg, pg, eg, _ = _gpu_state(s)
+    dq = qg - S.q
+    for k in range(3):
+        if periodic[k]:
+            dq[:, k] -= box[k] * np.rint(dq[:, k] / box[k])
+    errs = (np.abs(dq).max() / max(box), np.abs(pg - S.p).max(),
+            np.abs(eg - S.eps).max() / np.abs(S.eps).mean())
+    en, eo = s.energies(), S.energies()
+    s.close()
+    return errs, en, eo
+
+
+# ---------------------------------------------------------------------------
+# FP32 pair terms: per-step error against the FP64 oracle is stated here.
+# FP32 carries ~6e-8 relative rounding per pair term; a momentum change of
+# ~N_nb * |dp_ij| ~ 1 gives ~1e-6 absolute per step.
+# ---------------------------------------------------------------------------
+FP32_TOL = {"q": 1e-9, "p": 2e-5, "eps": 2e-7}
+
+
+def test_fp32_step_error_vs_fp64_oracle(dp):
+    n = 20000
+    L = W.cubic_side(n)
+    (eq, ep, ee), en, eo = _one_step_vs_oracle(dp, n, [L] * 3, precision=dp.FP32, dt=0.005)
+    assert eq < FP32_TOL["q"] and ep < FP32_TOL["p"] and ee < FP32_TOL["eps"], (eq, ep, ee)
+    # the conserved sums stay FP64-exact in structure: energy/momentum agree closely
+    assert abs(en[3] - eo[3]) < 1e-9 * abs(eo[3])
+
+
+def test_fp32_conserves_energy_without_conservative_force(dp):
+    n = 4000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=51)
+    s = dp.System(dp.Config(n=n, box=[L] * 3, a=0.0, precision=dp.FP32), q, p, e)
+    E0 = s.energies()[3]
+    s.step(300)
+    h = s.history()
+    assert np.abs(h[:, 3] - E0).max() < 1e-12 * E0
+    assert np.abs(h[:, 4:7]).max() < 1e-10
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# Nonlinear (Einstein) EOS with Newton inversion.
+# ---------------------------------------------------------------------------
+def test_theta_newton_matches_oracle(dp):
+    n = 200
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=3, eps0=25.0)
+    s = dp.System(dp.Config(n=n, box=[L] * 3, eos=dp.EOS_EINSTEIN), q, p, e)
+    P = O.make_params(n, [L] * 3, eos=1)
+    th = np.exp(np.linspace(np.log(0.05), np.log(100.0), 3001))
+    eps = O.eos_energy(P, th)
+    got_eps = s.eos_energy(th).cpu().numpy()
+    assert np.abs(got_eps / eps - 1).max() < 4e-15
+    got, its = s.theta(eps, mode=dp.THETA_NEWTON)
+    want, oits = O.theta_newton(P, eps)
+    assert np.abs(got.cpu().numpy() / want - 1).max() < 1e-13
+    assert its.cpu().numpy().max() < 60
+    s.close()
+
+
+def test_step_parity_einstein_eos(dp):
+    n = 3000
+    L = W.cubic_side(n)
+    P = O.make_params(10, [5, 5, 5], eos=1)
+    eps1 = float(O.eos_energy(P, 1.0)[0])
+    (eq, ep, ee), en, eo = _one_step_vs_oracle(dp, n, [L] * 3, eos=dp.EOS_EINSTEIN, dt=0.005,
+                                               eps0=eps1)
+    assert max(eq, ep, ee) < 1e-12, (eq, ep, ee)
+    assert abs(en[8] - eo[8]) < 1e-12 * eo[8]
+
+
+# ---------------------------------------------------------------------------
+# Surrogate network: GPU gradients vs the oracle's FP64 backprop, BF16
+# inference vs the oracle forward on the BF16-rounded weights, training, and
+# the error of the surrogate temperature judged by Newton.
+# ---------------------------------------------------------------------------
+def _bf16_round(w):
+    w = np.asarray(w, dtype=np.float32)
+    u = w.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def eos_system(dp):
+    n = 200
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=4, eps0=25.0)
+    s = dp.System(dp.Config(n=n, box=[L] * 3, eos=dp.EOS_EINSTEIN, theta_mode=dp.THETA_MLP), q, p, e)
+    yield s
+    s.close()
+
+
+def test_mlp_gradients_match_oracle(dp, eos_system):
+    rng = np.random.default_rng(8)
+    w = rng.normal(0, 0.5, 1153).astype(np.float32)
+    eos_system.mlp_set(w, np.array([3.0, 3.0, 0.0, 2.3]))
+    x = rng.uniform(-1, 1, 3000).astype(np.float32)
+    t = rng.uniform(-1, 1, 3000).astype(np.float32)
+    loss, g = eos_system.mlp_grad(x, t)
+    lo, go = O.mlp_loss_grad(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    assert loss == pytest.approx(lo, rel=1e-5)
+    scale = np.abs(go).max()
+    assert np.abs(g - go).max() < 2e-5 * scale
+
+
+def test_mlp_bf16_inference_matches_oracle_forward(dp, eos_system):
+    rng = np.random.default_rng(9)
+    w = rng.normal(0, 0.5, 1153).astype(np.float32)
+    eos_system.mlp_set(w, np.array([3.0, 3.0, 0.0, 2.3]))
+    x = np.concatenate([rng.uniform(-1, 1, 1000), [-1.0, 1.0, 0.0]]).astype(np.float32)
+    y = eos_system.mlp_eval(x).cpu().numpy()
+    # oracle forward with BF16 weights (activations stay FP64: the BF16
+    # rounding of the hidden activations on the GPU bounds the difference)
+    yo = O.mlp_forward(_bf16_round(w), x.astype(np.float64))
+    assert np.abs(y - yo).max() < 0.02 * max(1.0, np.abs(yo).max())
+    # operand-layout check: the same weights with W2 transposed (a swapped
+    # A/B operand) or with the hidden units permuted give a much larger error
+    wt = _bf16_round(w)
+    w2 = wt[64:64 + 1024].reshape(32, 32)
+    wt_T = wt.copy()
+    wt_T[64:64 + 1024] = w2.T.reshape(-1)
+    err = np.abs(y - yo).mean()
+    assert err < 0.2 * np.abs(y - O.mlp_forward(wt_T, x.astype(np.float64))).mean()
+
+
+def test_mlp_training_and_surrogate_accuracy(dp, eos_system):
+    curve = eos_system.mlp_train(nsamples=200000, iters=3000, batch=4096, lr=3e-3, seed=5)
+    assert curve[-1] < 0.05 * curve[0]
+    assert curve[-1] < 2e-3
+    P = O.make_params(10, [5, 5, 5], eos=1)
+    th = np.exp(np.linspace(np.log(0.2), np.log(20.0), 2001))
+    eps = O.eos_energy(P, th)
+    net, _ = eos_system.theta(eps, mode=dp.THETA_MLP)
+    rel = np.abs(net.cpu().numpy() / th - 1)
+    assert rel.max() < 0.05, rel.max()
+    polished, its = eos_system.theta(eps, mode=dp.THETA_MLP_NEWTON)
+    assert np.abs(polished.cpu().numpy() / th - 1).max() < 1e-13
+    newton, its0 = eos_system.theta(eps, mode=dp.THETA_NEWTON)
+    # the network start saves Newton iterations
+    assert its.cpu().numpy().mean() < its0.cpu().numpy().mean()
+    # outside the training range the surrogate mode falls back to Newton
+    out = np.array([0.5, 5000.0])
+    got, it_out = eos_system.theta(out, mode=dp.THETA_MLP)
+    want, _ = O.theta_newton(P, out)
+    assert np.abs(got.cpu().numpy() / want - 1).max() < 1e-13
+    assert it_out.cpu().numpy().min() > 0
+
+
+# ---------------------------------------------------------------------------
+# Batched replicas: each replica equals the single system built from its own
+# parameters, bit for bit; graph replay equals eager stepping bit for bit.
+# ---------------------------------------------------------------------------
+def test_batched_replicas_match_single_systems(dp):
+    sizes, seeds = W.replica_sizes(6, 500, 3000, seed=77)
+    cfgs, qs, ps, es = [], [], [], []
+    for r, (nr, sd) in enumerate(zip(sizes, seeds)):
+        L = W.cubic_side(int(nr))
+        q, p, e = W.equilibrium_state(int(nr), [L] * 3, seed=1000 + r)
+        cfgs.append(dp.Config(n=int(nr), box=[L] * 3, seed=int(sd), replica=r))
+        qs.append(q); ps.append(p); es.append(e)
+    b = dp.System(cfgs, np.concatenate(qs), np.concatenate(ps), np.concatenate(es))
+    b.step(15)
+    qb, pb, eb, st = _gpu_state(b)
+    enb = b.energies()
+    for r in range(len(cfgs)):
+        s = dp.System(cfgs[r], qs[r], ps[r], es[r])
+        s.step(15)
+        q1, p1, e1, _ = _gpu_state(s)
+        lo, hi = b.offsets[r], b.offsets[r + 1]
+        assert np.array_equal(qb[lo:hi], q1)
+        assert np.array_equal(pb[lo:hi], p1)
+        assert np.array_equal(eb[lo:hi], e1)
+        assert np.array_equal(enb[r], s.energies())
+        s.close()
+    b.close()
+
+
+def test_graph_replay_equals_eager(dp):
+    n = 5000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=61)
+    a = dp.System(dp.Config(n=n, box=[L] * 3), q, p, e)
+    g = dp.System(dp.Config(n=n, box=[L] * 3), q, p, e)
+    a.step(12)
+    g.step_graph(4, 3)
+    sa, sg = _gpu_state(a), _gpu_state(g)
+    for x, y in zip(sa[:3], sg[:3]):
+        assert np.array_equal(x, y)
+    assert sa[3] == sg[3] == 12
+    # eager work between replays, then more replays
+    g.step(2)
+    g.step_graph(4, 2)
+    a.step(10)
+    sa, sg = _gpu_state(a), _gpu_state(g)
+    for x, y in zip(sa[:3], sg[:3]):
+        assert np.array_equal(x, y)
+    ha = a.history()
+    hg = g.history()
+    assert np.array_equal(ha[-10:], hg[-10:])
+    a.close()
+    g.close()
+
+
+def test_batched_graph_replay(dp):
+    sizes, seeds = W.replica_sizes(16, 500, 8000, seed=78)
+    cfgs, qs, ps, es = [], [], [], []
+    for r, (nr, sd) in enumerate(zip(sizes, seeds)):
+        L = W.cubic_side(int(nr))
+        q, p, e = W.equilibrium_state(int(nr), [L] * 3, seed=2000 + r)
+        cfgs.append(dp.Config(n=int(nr), box=[L] * 3, seed=int(sd), replica=r))
+        qs.append(q); ps.append(p); es.append(e)
+    Q, Pm, E = np.concatenate(qs), np.concatenate(ps), np.concatenate(es)
+    a = dp.System(cfgs, Q, Pm, E)
+    g = dp.System(cfgs, Q, Pm, E)
+    a.step(8)
+    g.step_graph(2, 4)
+    assert np.array_equal(a.energies(), g.energies())
+    h = g.history()
+    assert h.shape == (8, 16, 10)
+    a.close()
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# SEM (Sec. 3.1.1): one step against the oracle's SEM.
+# ---------------------------------------------------------------------------
+def test_sem_step_parity(dp):
+    n = 3000
+    L = W.cubic_side(n)
+    (eq, ep, ee), en, eo = _one_step_vs_oracle(dp, n, [L] * 3, scheme=dp.SCHEME_SEM, dt=0.005)
+    assert max(eq, ep, ee) < 1e-12, (eq, ep, ee)
+
+
+# ---------------------------------------------------------------------------
+# Failure paths: codes, state kept at the failing step.
+# ---------------------------------------------------------------------------
+def test_negative_internal_energy_reported(dp):
+    """Tiny heat capacity and a large noise: the reinjection drives some eps
+    below zero (Sec. 4.4.2); the step returns DPDE_ENEG_EINT."""
+    n = 2000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=71, eps0=0.05)
+    s = dp.System(dp.Config(n=n, box=[L] * 3, cv=0.05, gamma=40.0, dt=0.02), q, p, e)
+    rc = s.step_raw(50)
+    assert rc == dp._lib.DPDE_ENEG_EINT
+    q1, p1, e1, st = s.get_state()
+    assert st < 50
+    # the state is readable and finite
+    assert np.isfinite(q1.cpu().numpy()).all()
+    s.close()
+
+
+def test_invalid_inputs_rejected(dp):
+    n = 300
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=72)
+    bad = q.copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(dp.DpdeError) as ex:
+        dp.System(dp.Config(n=n, box=[L] * 3), bad, p, e)
+    assert ex.value.code == dp._lib.DPDE_EINVAL
+    e2 = e.copy()
+    e2[3] = -1.0
+    with pytest.raises(dp.DpdeError) as ex:
+        dp.System(dp.Config(n=n, box=[L] * 3), q, p, e2)
+    assert ex.value.code == dp._lib.DPDE_ENEG_EINT
+    with pytest.raises(dp.DpdeError) as ex:
+        dp.System(dp.Config(n=n, box=[2.9, L, L]), q, p, e)
+    assert ex.value.code == dp._lib.DPDE_EBOX
+
+
+def test_neighbour_overflow_reported(dp):
+    n = 3000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=73)
+    with pytest.raises(dp.DpdeError) as ex:
+        dp.System(dp.Config(n=n, box=[L] * 3, neighbor_cap=4), q, p, e)
+    assert ex.value.code == dp._lib.DPDE_EOVERFLOW
+
+
+# ---------------------------------------------------------------------------
+# Full size: N = 1,048,576 in the launch configuration the benchmark times.
+# The oracle replays one step from the GPU state (a few seconds on one core).
+# ---------------------------------------------------------------------------
+def test_full_size_one_step_parity(dp):
+    n = 1_048_576
+    L = W.cubic_side(n)
+    (eq, ep, ee), en, eo = _one_step_vs_oracle(dp, n, [L] * 3, prime=2, dt=0.005)
+    assert max(eq, ep, ee) < 1e-12, (eq, ep, ee)
+    assert abs(en[3] - eo[3]) < 1e-12 * abs(eo[3])
+    assert abs(en[8] - eo[8]) < 1e-12 * abs(eo[8])

@@ -234,3 +234,39 @@ def test_bit_reproducible_and_resumable(dp):
     assert sa[3] == sc[3] == 20
     for s in (a, b, c):
         s.close()
+
+
+def test_stored_increments_equal_regenerated_noise(dp):
+    """Sweep 2 reading back the stored dp_ij and sweep 2 regenerating G_ij^n
+    from (ids, n) as the paper does give the same trajectory bit for bit."""
+    from paper_1507_06643_amd import _lib as L
+    n = 4000
+    L_ = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L_] * 3, seed=81)
+    for prec in (dp.FP64, dp.FP32):
+        a = dp.System(_cfg(dp, n, [L_] * 3, precision=prec), q, p, e)
+        cfg = _cfg(dp, n, [L_] * 3, precision=prec)
+        P = cfg.to_c()
+        P.flags = L.DPDE_FLAG_REGENERATE_NOISE
+        import ctypes as C
+        import torch
+        h = C.c_void_p()
+        qd = torch.as_tensor(q, device="cuda").contiguous()
+        pd = torch.as_tensor(p, device="cuda").contiguous()
+        ed = torch.as_tensor(e, device="cuda").contiguous()
+        torch.cuda.synchronize()
+        lib = L.load()
+        L.check(lib.dpde_init(C.byref(P), C.c_void_p(qd.data_ptr()), C.c_void_p(pd.data_ptr()),
+                              C.c_void_p(ed.data_ptr()), None, C.byref(h)))
+        a.step(12)
+        L.check(lib.dpde_step(h, 12))
+        qo = torch.empty_like(qd); po = torch.empty_like(pd); eo = torch.empty_like(ed)
+        st = C.c_int64(0)
+        L.check(lib.dpde_get_state(h, C.c_void_p(qo.data_ptr()), C.c_void_p(po.data_ptr()),
+                                   C.c_void_p(eo.data_ptr()), C.byref(st)))
+        sa = _gpu_state(a)
+        assert np.array_equal(sa[0], qo.cpu().numpy())
+        assert np.array_equal(sa[1], po.cpu().numpy())
+        assert np.array_equal(sa[2], eo.cpu().numpy())
+        lib.dpde_free(h)
+        a.close()
