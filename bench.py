@@ -77,6 +77,86 @@ def drift_per_1e4(hist):
     return float(1e4 * s)
 
 
+def drift_fit(E):
+    """Least-squares slope of (E_n - E_0)/|E_0| against n, times 10^4
+    (the linear fit of Sec. 4.2.1, eq. E_drift, per 10^4 steps)."""
+    E = np.asarray(E, dtype=float)
+    n = np.arange(len(E), dtype=float)
+    return float(1e4 * np.polyfit(n, (E - E[0]) / abs(E[0]), 1)[0])
+
+
+def mean_se(x):
+    x = np.asarray(x, dtype=float)
+    return float(x.mean()), float(x.std(ddof=1) / math.sqrt(len(x))) if len(x) > 1 else 0.0
+
+
+def drift_vs_oracle(dp, W, seeds, n=1000, steps=1000, dt=0.01):
+    """Small equilibrium system (N=1000, density 3, dt=0.01, 1000 steps):
+    GPU and CPU oracle run the same seeds; drift per 10^4 steps and the
+    kinetic/internal temperatures, mean +- standard error over seeds."""
+    import oracle as O
+    L = W.cubic_side(n)
+    g_d, o_d, g_tk, g_ti, o_tk, o_ti = [], [], [], [], [], []
+    t_cpu = 0.0
+    for sd in seeds:
+        q, p, e = W.equilibrium_state(n, [L] * 3, eps0=100.0, seed=1000 + sd)
+        s = dp.System(dp.Config(n=n, box=[L] * 3, dt=dt, seed=sd), q, p, e)
+        E0 = s.energies()
+        s.step(steps)
+        h = s.history()
+        s.close()
+        Eg = np.concatenate([[E0[3]], h[:, 3]])
+        g_d.append(drift_fit(Eg))
+        g_tk.append(h[steps // 2:, 7].mean())
+        g_ti.append(h[steps // 2:, 8].mean())
+        P = O.make_params(n, [L] * 3, dt=dt, seed=sd)
+        t0 = time.perf_counter()
+        S = O.State(P, q, p, e)
+        E0o = S.energies()
+        rc, rec = S.step(steps, record=True)
+        t_cpu += time.perf_counter() - t0
+        Eo = np.concatenate([[E0o[3]], rec[:, 3]])
+        o_d.append(drift_fit(Eo))
+        o_tk.append(rec[steps // 2:, 7].mean())
+        o_ti.append(rec[steps // 2:, 8].mean())
+    gm, gs = mean_se(g_d)
+    om, os_ = mean_se(o_d)
+    return {"workload": f"N={n} density 3, dt={dt}, {steps} steps, {len(seeds)} seeds, FP64",
+            "gpu_drift_per_1e4": [gm, gs], "oracle_drift_per_1e4": [om, os_],
+            "diff_over_combined_se": abs(gm - om) / max(1e-300, math.hypot(gs, os_)),
+            "gpu_Tkin_Tint": [mean_se(g_tk)[0], mean_se(g_ti)[0]],
+            "oracle_Tkin_Tint": [mean_se(o_tk)[0], mean_se(o_ti)[0]],
+            "oracle_seconds": t_cpu}
+
+
+def drift_gpu(dp, W, n=65536, steps=10000, seeds=(1, 2, 3, 4), dts=(0.005, 0.01),
+              precisions=("fp64", "fp32")):
+    """Equilibrium drift on the GPU at N=65,536 (density 3), 10^4 steps."""
+    L = W.cubic_side(n)
+    out = {}
+    for prec in precisions:
+        for dt in dts:
+            dr, tk, ti = [], [], []
+            for sd in seeds:
+                q, p, e = W.equilibrium_state(n, [L] * 3, eps0=100.0, seed=2000 + sd)
+                s = dp.System(dp.Config(n=n, box=[L] * 3, dt=dt, seed=sd,
+                                        precision=dp.FP32 if prec == "fp32" else dp.FP64), q, p, e)
+                # relax the random initial packing before measuring
+                s.step(1000)
+                s.history()
+                E0 = s.energies()
+                s.step(steps)
+                h = s.history()
+                s.close()
+                dr.append(drift_fit(np.concatenate([[E0[3]], h[:, 3]])))
+                tk.append(h[:, 7].mean())
+                ti.append(h[:, 8].mean())
+            out[f"{prec}_dt{dt}"] = {"drift_per_1e4": list(mean_se(dr)), "Tkin": list(mean_se(tk)),
+                                     "Tint": list(mean_se(ti))}
+    return {"workload": f"N={n} density 3, {steps} steps after 1000 relaxation steps, "
+                        f"{len(seeds)} seeds", "results": out}
+
+
 def kernel_profile(sysm, steps):
     sysm.profile(True)
     sysm.step(steps)
@@ -101,6 +181,32 @@ def pair_kernel_bytes(name, nbar, fp32=False):
         return 24 + 24 + 8 + 4 + lst + 24         # q, p, 1/T, id, list | dp
     if name.startswith("pass_c"):
         return 24 + 24 + 8 + 4 + lst + 24 + 8 + (24 + 8 + 8)  # ... dp, eps | p, eps, 1/T
+    return None
+
+
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "learned_eos_n1m_traffic.txt")
+KERNEL_SOURCES = ["common.h", "bin.h", "pairs.h", "eos.h", "mlp.h", "api.hip"]
+
+
+def counter_traffic(kernel_prefix):
+    """HBM bytes per launch (read, write) of a kernel from the committed
+    rocprofv3 counter summary, or None when the kernel sources have changed
+    since the counters were taken."""
+    import hashlib
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    h = hashlib.sha256()
+    for fn in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1507_06643_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    lines = open(PROFILE_TRAFFIC).read().splitlines()
+    sha = [l.split()[1] for l in lines if l.startswith("source_sha256")]
+    if not sha or sha[0] != h.hexdigest():
+        return None
+    for l in lines:
+        parts = l.rsplit(" ", 2)
+        if len(parts) == 3 and parts[0].startswith(kernel_prefix):
+            return float(parts[1]), float(parts[2])
     return None
 
 
@@ -131,6 +237,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--mlp-iters", type=int, default=3000)
+    ap.add_argument("--no-drift", action="store_true", help="skip the energy-drift legs")
+    ap.add_argument("--drift-seeds", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -173,13 +281,26 @@ def main():
     log(f"[bench] {value:.4e} particle-steps/s ({ms_step:.3f} ms/step)")
     prof = kernel_profile(sysm, args.profile_steps)
     nbar = mean_neighbours(sysm, n)
-    dom = max((k for k in prof if k.startswith("pass_")), key=lambda k: prof[k]["avg_ms"])
+    symbols = {"pass_a_forces": "k_pass_a<false, 0>", "pass_b_ser": "k_pass_b<false, 0, 0>",
+               "pass_c_ser": "k_pass_c<false, 0, 0>"}
+    pair_roofs = {}
+    for k in [k for k in prof if k in symbols]:
+        bpp_k = pair_kernel_bytes(k, nbar)
+        t_k = prof[k]["avg_ms"] * 1e-3
+        tr = counter_traffic(symbols[k])
+        pair_roofs[k] = {"avg_launch_ms": prof[k]["avg_ms"], "algorithmic_bytes": bpp_k * n,
+                         "achieved_GBps": bpp_k * n / t_k / 1e9,
+                         "frac": bpp_k * n / t_k / 1e9 / HBM_PEAK_GBS,
+                         "counter_bytes": None if tr is None else tr[0] + tr[1],
+                         "counter_GBps": None if tr is None else (tr[0] + tr[1]) / t_k / 1e9}
+    dom = max(pair_roofs, key=lambda k: pair_roofs[k]["avg_launch_ms"])
     bpp = pair_kernel_bytes(dom, nbar)
-    achieved = bpp * n / (prof[dom]["avg_ms"] * 1e-3) / 1e9
+    achieved = pair_roofs[dom]["achieved_GBps"]
     roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": pair_roofs[dom]["counter_bytes"],
             "bytes_per_particle": bpp, "mean_neighbours": nbar,
-            "avg_launch_ms": prof[dom]["avg_ms"]}
+            "avg_launch_ms": prof[dom]["avg_ms"], "pair_kernels": pair_roofs}
     line = {
         "metric": "particle-steps/s at N=1M",
         "value": value,
@@ -220,6 +341,11 @@ def main():
                               "energy_drift_per_1e4_steps": drift_per_1e4(h2)}
             s2.close()
         line["variants"] = variants
+    if not args.no_drift:
+        log("[bench] energy drift: GPU vs oracle, N=1000")
+        line["drift_vs_oracle"] = drift_vs_oracle(dp, W, list(range(1, args.drift_seeds + 1)))
+        log("[bench] energy drift: GPU, N=65536, 10^4 steps")
+        line["drift_gpu"] = drift_gpu(dp, W)
     if not args.no_cpu:
         log(f"[bench] CPU oracle: {args.cpu_steps} steps at N={n}")
         line["cpu_baseline"] = cpu_baseline(W, n, args.cpu_steps, 1, dt, eps0)

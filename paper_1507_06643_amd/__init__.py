@@ -5,6 +5,10 @@ The compute lives in libdpde.so (hand-written HIP for gfx950); this package is
 its Python binding.  Importing it loads the library and fails loudly when it
 has not been built.
 """
+# torch first: its HIP runtime is then the one the library binds to (one
+# runtime per process, shared streams and device state)
+import torch  # noqa: F401
+
 from . import _lib
 from ._lib import (DpdeError, EOS_EINSTEIN, EOS_LINEAR, FP32, FP64, SCHEME_SEM, SCHEME_SER,
                    THETA_MLP, THETA_MLP_NEWTON, THETA_NEWTON)

@@ -24,11 +24,34 @@ FLAGS = [
 ]
 
 
+def _generic_hip_soname(path: str) -> None:
+    """Record the HIP runtime dependency under its generic name.
+
+    hipcc links against /opt/rocm/lib/libamdhip64.so, whose SONAME carries
+    the major version (libamdhip64.so.7).  A process that already holds a HIP
+    runtime loaded under the generic name libamdhip64.so (PyTorch ships its
+    own copy) would then map a second, independent runtime: separate device
+    state and stream handles that are not valid across the two.  Rewriting
+    the NEEDED string (same length, NUL padded) makes the loader reuse the
+    runtime already present; a process without one resolves the generic name
+    through the run path to /opt/rocm/lib.
+    """
+    data = bytearray(open(path, "rb").read())
+    old, new = b"libamdhip64.so.7\x00", b"libamdhip64.so\x00\x00\x00"
+    count = data.count(old)
+    if count != 1:
+        raise RuntimeError(f"expected one {old!r} in {path}, found {count}")
+    i = data.index(old)
+    data[i:i + len(old)] = new
+    open(path, "wb").write(bytes(data))
+
+
 def build(verbose: bool = False) -> str:
-    cmd = [HIPCC] + FLAGS + ["-o", LIB + ".tmp", SRC]
+    cmd = [HIPCC] + FLAGS + ["-Wl,-rpath,/opt/rocm/lib", "-o", LIB + ".tmp", SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
+    _generic_hip_soname(LIB + ".tmp")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

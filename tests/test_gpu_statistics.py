@@ -1,0 +1,64 @@
+"""Long-run behaviour on the GPU against the oracle: energy drift per 10^4
+steps (linear fit of Sec. 4.2.1) and the equality of kinetic and internal
+temperatures at equilibrium (Sec. 2.2)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _drift(E):
+    n = np.arange(len(E), dtype=float)
+    return 1e4 * np.polyfit(n, (E - E[0]) / abs(E[0]), 1)[0]
+
+
+def test_energy_drift_matches_oracle_small_system():
+    import paper_1507_06643_amd as dp
+    n, steps, dt = 1000, 1000, 0.01
+    L = W.cubic_side(n)
+    dg, do = [], []
+    for sd in (1, 2, 3):
+        q, p, e = W.equilibrium_state(n, [L] * 3, seed=1000 + sd)
+        s = dp.System(dp.Config(n=n, box=[L] * 3, dt=dt, seed=sd), q, p, e)
+        E0 = s.energies()[3]
+        s.step(steps)
+        Eg = np.concatenate([[E0], s.history()[:, 3]])
+        s.close()
+        S = O.State(O.make_params(n, [L] * 3, dt=dt, seed=sd), q, p, e)
+        E0o = S.energies()[3]
+        rc, rec = S.step(steps, record=True)
+        assert rc == 0
+        Eo = np.concatenate([[E0o], rec[:, 3]])
+        # same seeds, same noise: the histories agree to rounding at first;
+        # the dynamics is chaotic, so rounding differences grow later on
+        assert np.abs(Eg[:100] - Eo[:100]).max() < 1e-10 * abs(E0o)
+        dg.append(_drift(Eg))
+        do.append(_drift(Eo))
+    dg, do = np.array(dg), np.array(do)
+    # the drift over the run agrees seed by seed well inside its spread
+    assert np.abs(dg - do).max() < 0.05 * np.abs(do).max()
+
+
+def test_kinetic_and_internal_temperatures_agree():
+    import paper_1507_06643_amd as dp
+    n, dt = 65536, 0.005
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=77, eps0=100.0)
+    s = dp.System(dp.Config(n=n, box=[L] * 3, dt=dt, seed=5), q, p, e)
+    s.step(2000)
+    s.history()
+    s.step(2000)
+    h = s.history()
+    s.close()
+    # blocks of 200 steps as independent samples
+    tk = h[:, 7].reshape(10, -1).mean(1)
+    ti = h[:, 8].reshape(10, -1).mean(1)
+    se = math.hypot(tk.std(ddof=1), ti.std(ddof=1)) / math.sqrt(10)
+    # weak order 1: the two estimators differ by O(dt); allow 5 se + 1 %
+    assert abs(tk.mean() - ti.mean()) < 5 * se + 0.01 * ti.mean(), (tk.mean(), ti.mean())
+    # internal-energy marginal Gamma(C_v + 1, T): <eps> = (C_v + 1) T_int
