@@ -170,13 +170,15 @@ def mean_neighbours(sysm, n):
     return 2.0 * len(pr) / n
 
 
-def pair_kernel_bytes(name, nbar, fp32=False):
+def pair_kernel_bytes(name, nbar, nskin=None, fp32=False):
     """Algorithmic HBM bytes per particle of the pair kernels: every
     per-particle array read or written once, neighbour-list words 4 B each;
-    neighbour gathers are re-reads served on chip and not counted."""
+    neighbour gathers are re-reads served on chip and not counted.  Pass A
+    reads the skin list (nskin entries) and writes the exact list."""
     lst = 4.0 + 4.0 * nbar  # count + entries
     if name.startswith("pass_a"):
-        return 24 + 24 + 4 + (24 + 24 + 8) + lst  # q, p, cell offsets ~4 | F, p, U | list
+        skin = 4.0 + 4.0 * (nskin if nskin is not None else nbar)
+        return 24 + 24 + (24 + 24 + 8) + skin + lst  # q, p, skin list | F, p, U, list
     if name.startswith("pass_b"):
         return 24 + 24 + 8 + 4 + lst + 24         # q, p, 1/T, id, list | dp
     if name.startswith("pass_c"):
@@ -281,11 +283,16 @@ def main():
     log(f"[bench] {value:.4e} particle-steps/s ({ms_step:.3f} ms/step)")
     prof = kernel_profile(sysm, args.profile_steps)
     nbar = mean_neighbours(sysm, n)
+    # skin-list length from the density of the uniform fluid: pairs within rc + skin
+    nskin = nbar * ((cfg.rc + cfg.skin) / cfg.rc) ** 3
+    b0 = sysm.list_builds()
+    sysm.step(100)
+    builds_per_step = (sysm.list_builds() - b0) / 100.0
     symbols = {"pass_a_forces": "k_pass_a<false, 0>", "pass_b_ser": "k_pass_b<false, 0, 0>",
                "pass_c_ser": "k_pass_c<false, 0, 0>"}
     pair_roofs = {}
     for k in [k for k in prof if k in symbols]:
-        bpp_k = pair_kernel_bytes(k, nbar)
+        bpp_k = pair_kernel_bytes(k, nbar, nskin)
         t_k = prof[k]["avg_ms"] * 1e-3
         tr = counter_traffic(symbols[k])
         pair_roofs[k] = {"avg_launch_ms": prof[k]["avg_ms"], "algorithmic_bytes": bpp_k * n,
@@ -294,12 +301,12 @@ def main():
                          "counter_bytes": None if tr is None else tr[0] + tr[1],
                          "counter_GBps": None if tr is None else (tr[0] + tr[1]) / t_k / 1e9}
     dom = max(pair_roofs, key=lambda k: pair_roofs[k]["avg_launch_ms"])
-    bpp = pair_kernel_bytes(dom, nbar)
+    bpp = pair_kernel_bytes(dom, nbar, nskin)
     achieved = pair_roofs[dom]["achieved_GBps"]
     roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": pair_roofs[dom]["counter_bytes"],
-            "bytes_per_particle": bpp, "mean_neighbours": nbar,
+            "bytes_per_particle": bpp, "mean_neighbours": nbar, "skin_list_estimate": nskin,
             "avg_launch_ms": prof[dom]["avg_ms"], "pair_kernels": pair_roofs}
     line = {
         "metric": "particle-steps/s at N=1M",
@@ -316,7 +323,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "learned-EOS N=1,048,576 density 3, Einstein EOS (n=50, w=2, c0=10) "
                                "via BF16 surrogate + Newton fallback, dt=0.005, FP64 pair terms",
-                   "n": n, "dt": dt, "precision": "fp64", "theta": "mlp+newton-fallback"},
+                   "n": n, "dt": dt, "precision": "fp64", "theta": "mlp+newton-fallback",
+                   "skin": cfg.skin, "list_builds_per_step": builds_per_step},
         "roofline": roof,
         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in prof.items()},
         "energy_drift_per_1e4_steps": drift_per_1e4(hist),

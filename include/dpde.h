@@ -85,6 +85,10 @@ typedef struct dpde_params {
   double dt;            /* timestep > 0                                         */
   double cv;            /* heat capacity of the linear EOS                      */
   double eos_n, eos_omega, eos_c0; /* Einstein EOS parameters                   */
+  double skin;          /* neighbour-list skin >= 0: lists hold pairs within    */
+                        /* rc + skin and are rebuilt once some particle has     */
+                        /* moved more than skin/2 since the last build; the     */
+                        /* trajectory does not depend on it (0: every step)     */
   uint64_t seed;        /* 64-bit noise seed                                    */
   int64_t step0;        /* initial value of the step counter n                  */
   int32_t periodic[3];  /* 1 = periodic, 0 = free                               */
@@ -93,7 +97,7 @@ typedef struct dpde_params {
   int32_t theta_mode;   /* DPDE_THETA_*                                         */
   int32_t scheme;       /* DPDE_SCHEME_*                                        */
   uint32_t replica;     /* folded into the noise key (seed_hi ^ replica)        */
-  int32_t neighbor_cap; /* max neighbours per particle (0: default 64)          */
+  int32_t neighbor_cap; /* list capacity per particle (0: 64, or 96 with skin)  */
   int32_t flags;        /* DPDE_FLAG_* bits                                     */
 } dpde_params;
 
@@ -163,6 +167,9 @@ int dpde_forces(dpde_handle* h, double* F, double* U);
 
 /* Release every resource of the handle (NULL is accepted). */
 int dpde_free(dpde_handle* h);
+
+/* Number of neighbour-list builds so far (host *builds). */
+int dpde_list_builds(dpde_handle* h, int64_t* builds);
 
 /* Thread-local description of the last failure ("" if none). */
 const char* dpde_last_error(void);

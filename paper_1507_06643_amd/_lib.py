@@ -36,6 +36,7 @@ class Params(C.Structure):
         ("mass", C.c_double), ("rc", C.c_double), ("a", C.c_double), ("gamma", C.c_double),
         ("kT_ref", C.c_double), ("dt", C.c_double), ("cv", C.c_double),
         ("eos_n", C.c_double), ("eos_omega", C.c_double), ("eos_c0", C.c_double),
+        ("skin", C.c_double),
         ("seed", C.c_uint64), ("step0", C.c_int64),
         ("periodic", C.c_int32 * 3),
         ("eos", C.c_int32), ("precision", C.c_int32), ("theta_mode", C.c_int32),
@@ -74,6 +75,7 @@ SIGNATURES = [
     ("dpde_set_state", C.c_int, [_vp, _vp, _vp, _vp, _i64]),
     ("dpde_forces", C.c_int, [_vp, _vp, _dp]),
     ("dpde_free", C.c_int, [_vp]),
+    ("dpde_list_builds", C.c_int, [_vp, C.POINTER(_i64)]),
     ("dpde_last_error", C.c_char_p, []),
     ("dpde_stream", _vp, [_vp]),
     ("dpde_init_batch", C.c_int, [C.POINTER(Params), _i32, C.POINTER(_i64), _vp, _vp, _vp, _vp,

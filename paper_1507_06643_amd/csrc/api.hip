@@ -71,6 +71,12 @@ struct dpde_handle {
   int aux_block = 256;
 
   PState cur{}, alt{};
+  double half_skin2 = 0.0, rs2 = 0.0;
+  QRef* qref = nullptr;
+  uint32_t* slot = nullptr;  // memory index of each identifier row
+  BuildCtl* ctl = nullptr;
+  unsigned long long* builds = nullptr;
+  SkinList skin{};
   bool regen = false;  // regenerate the noise in sweep 2 instead of storing dp_ij
   double *Fx = nullptr, *Fy = nullptr, *Fz = nullptr;
   PV* pv = nullptr;
@@ -87,7 +93,7 @@ struct dpde_handle {
   int64_t* tile_begin = nullptr;
   int32_t* rep_tile0 = nullptr;
   int ntiles = 0;
-  double* partials = nullptr;
+  Fix* partials = nullptr;
   double* rec = nullptr;
   double* hist = nullptr;
   int64_t hist_cap = 0;
@@ -171,6 +177,8 @@ int check_params(const dpde_params* P, bool first) {
   if (!(std::isfinite(P->kT_ref) && P->kT_ref > 0)) return fail(DPDE_EINVAL, "kT_ref must be > 0");
   if (!(std::isfinite(P->gamma) && P->gamma >= 0)) return fail(DPDE_EINVAL, "gamma must be >= 0");
   if (!(std::isfinite(P->a) && P->a >= 0)) return fail(DPDE_EINVAL, "a must be >= 0");
+  if (!(std::isfinite(P->skin) && P->skin >= 0 && P->skin <= P->rc))
+    return fail(DPDE_EINVAL, "skin must be in [0, rc]");
   if (P->eos == DPDE_EOS_LINEAR) {
     if (!(std::isfinite(P->cv) && P->cv > 0)) return fail(DPDE_EINVAL, "cv must be > 0");
   } else if (P->eos == DPDE_EOS_EINSTEIN) {
@@ -195,10 +203,10 @@ int check_params(const dpde_params* P, bool first) {
 
 int geometry(const dpde_params* P, Geo& g) {
   for (int d = 0; d < 3; ++d) {
-    const double ncd = std::floor(P->box[d] / P->rc);
+    const double ncd = std::floor(P->box[d] / (P->rc + P->skin));
     if (ncd < 3.0)
-      return fail(DPDE_EBOX, "box[%d] = %g holds %g < 3 cells of side rc = %g", d, P->box[d], ncd,
-                  P->rc);
+      return fail(DPDE_EBOX, "box[%d] = %g holds %g < 3 cells of side rc + skin = %g", d,
+                  P->box[d], ncd, P->rc + P->skin);
     if (ncd > 1e6) return fail(DPDE_EINVAL, "box[%d]/rc too large", d);
     g.nc[d] = (int32_t)ncd;
     g.box[d] = P->box[d];
@@ -234,7 +242,7 @@ void physics(const dpde_params* P, Phys& ph) {
   ph.theta_mode = P->theta_mode;
   ph.precision = P->precision;
   ph.scheme = P->scheme;
-  ph.cap = P->neighbor_cap > 0 ? P->neighbor_cap : 64;
+  ph.cap = P->neighbor_cap > 0 ? P->neighbor_cap : (P->skin > 0 ? 96 : 64);
 }
 
 int alloc_pstate(dpde_handle* h, PState& s) {
@@ -262,6 +270,17 @@ int allocate(dpde_handle* h) {
   h->nl.stride = n;
   if ((rc = dalloc(h, &h->nl.idx, (size_t)h->phys.cap * n)) || (rc = dalloc(h, &h->nl.count, n)))
     return rc;
+  if ((rc = dalloc(h, &h->qref, n)) || (rc = dalloc(h, &h->ctl, 1)) ||
+      (rc = dalloc(h, &h->builds, 1)) ||
+      (rc = dalloc(h, &h->skin.idx, (size_t)h->phys.cap * n)) ||
+      (rc = dalloc(h, &h->slot, n)) ||
+      (rc = dalloc(h, &h->skin.count, n)))
+    return rc;
+  h->skin.stride = n;
+  h->skin.cap = h->phys.cap;
+  HIPCHK(hipMemset(h->qref, 0, n * sizeof(QRef)));
+  HIPCHK(hipMemset(h->ctl, 0, sizeof(BuildCtl)));
+  HIPCHK(hipMemset(h->builds, 0, sizeof(unsigned long long)));
   h->nl.dex = h->nl.dey = h->nl.dez = nullptr;
   if (!h->regen && ((rc = dalloc(h, &h->nl.dex, (size_t)h->phys.cap * n)) ||
                     (rc = dalloc(h, &h->nl.dey, (size_t)h->phys.cap * n)) ||
@@ -281,7 +300,7 @@ int allocate(dpde_handle* h) {
   h->ntiles = (int)tb.size();
   tb.push_back(n);
   if ((rc = dalloc(h, &h->tile_begin, tb.size())) || (rc = dalloc(h, &h->rep_tile0, rt.size())) ||
-      (rc = dalloc(h, &h->partials, (size_t)h->ntiles * 8)) ||
+      (rc = dalloc(h, &h->partials, (size_t)h->ntiles * kStatVals)) ||
       (rc = dalloc(h, &h->rec, (size_t)h->nrep * 10)))
     return rc;
   HIPCHK(hipMemcpy(h->tile_begin, tb.data(), tb.size() * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -307,34 +326,47 @@ int status_to_code(uint32_t st) {
 }
 
 // ---- the launch sequence -----------------------------------------------------
+// Kick and drift; on list-build steps (decided on the device) the binning,
+// the reorder and the skin lists.  Buffer roles are the same either way.
 void enqueue_bin(dpde_handle* h, int kick) {
   const int b = h->aux_block;
   const int64_t n = h->n;
-  auto kick_kernel = h->batch ? k_kick_drift_key<true> : k_kick_drift_key<false>;
-  launch(h, "kick_drift_key", kick_kernel, blocks(n, b), b, h->cur, (const double*)h->Fx,
-         (const double*)h->Fy, (const double*)h->Fz, n, (const Geo*)h->geo, h->phys, kick, h->key,
-         h->ticket, h->idk, h->cell_count, h->status);
+  const double hs2 = h->half_skin2;
+  const BuildCtl* ctl = h->ctl;
+  launch(h, "kick", h->batch ? k_kick<true> : k_kick<false>, blocks(n, b), b, h->cur,
+         (const double*)h->Fx, (const double*)h->Fy, (const double*)h->Fz, n, (const Geo*)h->geo,
+         h->phys, kick, (const QRef*)h->qref, h->ctl, h->status);
+  launch(h, "bin_key", h->batch ? k_bin_key<true> : k_bin_key<false>, blocks(n, b), b, h->cur, n,
+         (const Geo*)h->geo, h->key, h->ticket, h->idk, h->cell_count, ctl, hs2, h->status);
   launch(h, "scan_tiles", k_scan_tiles, h->scan_tiles, kScanThreads, (const uint32_t*)h->cell_count,
-         h->ncells, h->scan_tmp);
-  launch(h, "scan_tile_sums", k_scan_tile_sums, 1, 1024, h->scan_tmp, h->scan_tiles);
+         h->ncells, h->scan_tmp, ctl, hs2);
+  launch(h, "scan_tile_sums", k_scan_tile_sums, 1, 1024, h->scan_tmp, h->scan_tiles, ctl, hs2);
   launch(h, "scan_apply", k_scan_apply, h->scan_tiles, kScanThreads, h->cell_count, h->ncells,
-         (const uint32_t*)h->scan_tmp, h->cell_start);
+         (const uint32_t*)h->scan_tmp, h->cell_start, ctl, hs2);
   launch(h, "scatter", k_scatter, blocks(n, b), b, (const uint32_t*)h->key,
-         (const uint32_t*)h->ticket, (const uint32_t*)h->cell_start, n, h->perm,
+         (const uint32_t*)h->ticket, (const uint32_t*)h->cell_start, n, h->perm, ctl, hs2,
          (const uint32_t*)h->status);
   launch(h, "cell_sort", k_cell_sort, blocks(h->ncells, b), b, (const uint32_t*)h->cell_start,
-         h->ncells, h->perm, (const uint32_t*)h->idk, (const uint32_t*)h->status);
-  launch(h, "gather", k_gather, blocks(n, b), b, h->cur, h->alt, (const uint32_t*)h->perm, n,
+         h->ncells, h->perm, (const uint32_t*)h->idk, ctl, hs2, (const uint32_t*)h->status);
+  launch(h, "gather", h->batch ? k_gather<true> : k_gather<false>, blocks(n, b), b, h->cur, h->alt,
+         (const uint32_t*)h->perm, n, (const Geo*)h->geo, h->qref, h->slot, ctl, hs2,
          (const uint32_t*)h->status);
-  std::swap(h->cur, h->alt);
+  launch(h, "copy_back", k_copy_back, blocks(n, b), b, h->alt, h->cur, n, ctl, hs2,
+         (const uint32_t*)h->status);
+  const int pb = h->pair_block;
+  launch(h, "build_skin", h->batch ? k_build_skin<true> : k_build_skin<false>, blocks(n, pb), pb,
+         h->cur, (const uint32_t*)h->cell_start, n, (const Geo*)h->geo, h->rs2, h->skin, ctl, hs2,
+         h->status);
+  launch(h, "sort_skin", k_sort_skin, blocks(n, 256), 256, n, h->skin, (const uint32_t*)h->slot,
+         ctl, hs2, (const uint32_t*)h->status);
 }
 
 void enqueue_forces(dpde_handle* h, int mode) {
   const int b = h->pair_block;
   const int64_t n = h->n;
   auto go = [&](auto kern) {
-    launch(h, "pass_a_forces", kern, blocks(n, b), b, h->cur, (const uint32_t*)h->cell_start, n,
-           (const Geo*)h->geo, h->phys, mode, h->Fx, h->Fy, h->Fz, h->Ui, h->nl, h->status);
+    launch(h, "pass_a_forces", kern, blocks(n, b), b, h->cur, n, (const Geo*)h->geo, h->phys, mode,
+           h->Fx, h->Fy, h->Fz, h->Ui, h->skin, h->nl, h->status);
   };
   if (h->batch) {
     if (h->phys.precision == DPDE_FP32) go(k_pass_a<true, PREC_F32>);
@@ -372,8 +404,7 @@ void enqueue_fd_t(dpde_handle* h) {
              (const Geo*)h->geo, h->phys, d_step, (const PV*)h->pv, inl, h->alt.r, h->status);
   }
   // the updated records were written to the spare record array: swap them in
-  // (with the swap of the binning, each step swaps the records twice and the
-  // internal energies once; two steps restore the starting layout, which is
+  // (one swap per step, so two steps restore the starting layout, which is
   // what an even-length captured graph relies on)
   std::swap(h->cur.r, h->alt.r);
   if (!inl)
@@ -393,12 +424,11 @@ void enqueue_fd(dpde_handle* h) {
 void enqueue_stats(dpde_handle* h, int advance) {
   launch(h, "stats_tiles", k_stats_tiles, h->ntiles, kStatThreads, h->cur, (const double*)h->Ui,
          (const int64_t*)h->tile_begin, h->phys, h->partials);
-  launch(h, "stats_final", k_stats_final, h->nrep, kStatThreads, (const double*)h->partials,
+  launch(h, "stats_final", k_stats_final, h->nrep, kStatThreads, (const Fix*)h->partials,
          (const int32_t*)h->rep_tile0, (const Geo*)h->geo, (const uint64_t*)h->d_step, advance,
          h->rec, h->hist, h->hist_cap, (const int64_t*)h->d_hist_count, h->nrep);
-  if (advance)
-    launch(h, "step_advance", k_step_advance, 1, 1, h->d_step, h->d_hist_count,
-           (const uint32_t*)h->status);
+  launch(h, "step_end", k_step_end, 1, 1, h->d_step, h->d_hist_count, h->ctl, h->builds,
+         h->half_skin2, advance, (const uint32_t*)h->status);
 }
 
 void enqueue_step(dpde_handle* h) {
@@ -411,6 +441,8 @@ void enqueue_step(dpde_handle* h) {
 // Bin, forces, temperatures and observables of the current state.
 int prepare(dpde_handle* h) {
   HIPCHK(hipMemcpyAsync(h->d_step, &h->step, sizeof(uint64_t), hipMemcpyHostToDevice, h->stream));
+  static const BuildCtl forced{0ull, 1u, 0u};
+  HIPCHK(hipMemcpyAsync(h->ctl, &forced, sizeof(BuildCtl), hipMemcpyHostToDevice, h->stream));
   enqueue_bin(h, 0);
   enqueue_forces(h, 0);
   if (eos_inline(h)) {
@@ -483,6 +515,8 @@ int create(const dpde_params* params, int nrep, const int64_t* offsets, const do
   h->user_stream = (hipStream_t)stream;
   physics(&params[0], h->phys);
   h->regen = (params[0].flags & DPDE_FLAG_REGENERATE_NOISE) != 0;
+  h->half_skin2 = 0.25 * params[0].skin * params[0].skin;
+  h->rs2 = (params[0].rc + params[0].skin) * (params[0].rc + params[0].skin);
   h->step = params[0].step0;
   h->offsets.assign(offsets, offsets + nrep + 1);
   if (h->offsets[0] != 0) { release(h); return fail(DPDE_EINVAL, "offsets[0] must be 0"); }
@@ -497,7 +531,8 @@ int create(const dpde_params* params, int nrep, const int64_t* offsets, const do
                   params[r].a != params[0].a || params[r].gamma != params[0].gamma ||
                   params[r].kT_ref != params[0].kT_ref || params[r].dt != params[0].dt ||
                   params[r].eos != params[0].eos || params[r].precision != params[0].precision ||
-                  params[r].scheme != params[0].scheme || params[r].step0 != params[0].step0)) {
+                  params[r].scheme != params[0].scheme || params[r].step0 != params[0].step0 ||
+                  params[r].skin != params[0].skin)) {
       release(h);
       return fail(DPDE_EINVAL, "replica %d: physical parameters differ from replica 0", r);
     }
@@ -559,6 +594,15 @@ int dpde_free(dpde_handle* h) {
 }
 
 void* dpde_stream(dpde_handle* h) { return h ? (void*)h->stream : nullptr; }
+
+int dpde_list_builds(dpde_handle* h, int64_t* builds) {
+  if (!h || !builds) return fail(DPDE_EINVAL, "NULL argument");
+  unsigned long long b = 0;
+  HIPCHK(hipMemcpyAsync(&b, h->builds, sizeof(b), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  *builds = (int64_t)b;
+  return DPDE_OK;
+}
 
 int dpde_step(dpde_handle* h, int64_t nsteps) {
   if (!h) return fail(DPDE_EINVAL, "handle is NULL");
@@ -681,7 +725,7 @@ int dpde_forces(dpde_handle* h, double* F, double* U) {
 int dpde_set_tuning(dpde_handle* h, int32_t pair_block, int32_t aux_block) {
   if (!h) return fail(DPDE_EINVAL, "handle is NULL");
   auto ok = [](int b, int mx) { return b >= 64 && b <= mx && (b % 64) == 0; };
-  if (!ok(pair_block, kPairBlockMax) || !ok(aux_block, 1024))
+  if (!ok(pair_block, kPairBlockMax) || !ok(aux_block, kAuxMaxThreads))
     return fail(DPDE_EINVAL, "block sizes must be multiples of 64 within the kernel limits");
   h->pair_block = pair_block;
   h->aux_block = aux_block;

@@ -34,6 +34,26 @@ struct PState {
   double* eps;
 };
 
+// Neighbour-list build control for one step.  The kick kernel raises dmax to
+// the largest squared displacement since the last build (bit pattern of a
+// non-negative double, so integer max is float max); the binning and list
+// build kernels run when force is set or dmax exceeds (skin/2)^2, and do
+// nothing otherwise.  The decision is read from device memory by every
+// kernel, so a captured graph replays it faithfully.
+struct BuildCtl {
+  unsigned long long dmax_bits;
+  uint32_t force;
+  uint32_t pad;
+};
+
+__device__ __forceinline__ bool rebuild_now(const BuildCtl* c, double half_skin2) {
+  return c->force != 0u || __longlong_as_double((long long)c->dmax_bits) > half_skin2;
+}
+
+struct alignas(32) QRef {
+  double x, y, z, pad;
+};
+
 // XCD-aware tile order: the hardware deals workgroups round-robin over the 8
 // XCDs (each with its own L2); the remap makes XCD x work through one
 // contiguous share of the cell-sorted particles, a slab of the box whose
@@ -97,26 +117,22 @@ __global__ void k_store_vec3(PState s, const Geo* __restrict__ geo, int64_t n,
   out[3 * row] = x[i]; out[3 * row + 1] = y[i]; out[3 * row + 2] = z[i];
 }
 
-// ---- digit 1: kick, drift, wrap, cell key, histogram ------------------------
-// With kick != 0 this is the first half of velocity-Verlet (Sec. 3.1):
-// p += dt/2 F, q += dt p / m, then periodic wrap into [0, L).
-// The identifier is also written to a compact array for the per-cell sort.
-// The histogram update is aggregated per run of equal keys inside a wave (the
-// particles are still nearly in cell order): one atomic per run, the run's
-// lanes take consecutive tickets.  Tiles follow the XCD-aware order, so each
-// XCD's atomics touch its own slab of counters.
+constexpr int kAuxMaxThreads = 1024;  // largest block of the per-particle kernels
+
+// First half of velocity-Verlet (Sec. 3.1): p += dt/2 F, q += dt p / m, then
+// the periodic wrap into [0, L); with kick == 0 only the wrap.  Each wave also
+// reports its largest squared displacement since the last list build.
 template <bool BATCH>
-__global__ void k_kick_drift_key(PState s, const double* __restrict__ Fx,
-                                 const double* __restrict__ Fy, const double* __restrict__ Fz,
-                                 int64_t n, const Geo* __restrict__ geo, Phys P, int kick,
-                                 uint32_t* __restrict__ key, uint32_t* __restrict__ ticket,
-                                 uint32_t* __restrict__ idk, uint32_t* __restrict__ count,
-                                 uint32_t* status) {
-  const int64_t i = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (status_set(status)) return;  // uniform: the whole grid leaves together
-  const bool live = i < n;
-  uint32_t c = 0xFFFFFFFFu;
-  if (live) {
+__global__ void k_kick(PState s, const double* __restrict__ Fx, const double* __restrict__ Fy,
+                       const double* __restrict__ Fz, int64_t n, const Geo* __restrict__ geo,
+                       Phys P, int kick, const QRef* __restrict__ qref, BuildCtl* ctl,
+                       uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // no early return: every thread reaches the block barrier below (another
+  // block may raise the status while this one runs)
+  const bool run = !status_set(status);
+  double d2 = 0.0;
+  if (run && i < n) {
     Rec rc = s.r[i];
     const Geo& g = geo[BATCH ? rc.rep : 0u];
     double q[3] = {rc.qx, rc.qy, rc.qz};
@@ -136,10 +152,56 @@ __global__ void k_kick_drift_key(PState s, const double* __restrict__ Fx,
       if (g.periodic[d]) q[d] = wrap_coord(q[d], g.box[d]);
     rc.qx = q[0]; rc.qy = q[1]; rc.qz = q[2];
     s.r[i] = rc;
-    if (!(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]))) atomicOr(status, ST_NONFINITE);
-    const int cx = cell_coord(q[0], g.scale[0], g.nc[0]);
-    const int cy = cell_coord(q[1], g.scale[1], g.nc[1]);
-    const int cz = cell_coord(q[2], g.scale[2], g.nc[2]);
+    if (!(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]))) {
+      atomicOr(status, ST_NONFINITE);
+    } else {
+      const QRef r0 = qref[i];
+      double dx = q[0] - r0.x, dy = q[1] - r0.y, dz = q[2] - r0.z;
+      if (g.periodic[0]) dx = min_image(dx, g.box[0], g.half_box[0]);
+      if (g.periodic[1]) dy = min_image(dy, g.box[1], g.half_box[1]);
+      if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
+      d2 = dx * dx + dy * dy + dz * dz;
+    }
+  }
+  // block maximum, then one atomic per block and only when it raises the
+  // running maximum (non-negative doubles order like their bit patterns; a
+  // stale read can only be smaller than the true value, never skip a raise)
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) d2 = fmax(d2, __shfl_xor(d2, off, kWave));
+  __shared__ double wmax[kAuxMaxThreads / kWave];
+  const int nw = blockDim.x / kWave;
+  if ((threadIdx.x % kWave) == 0) wmax[threadIdx.x / kWave] = d2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < nw; ++w) d2 = fmax(d2, wmax[w]);
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(d2);
+    const unsigned long long cur =
+        __hip_atomic_load(&ctl->dmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (run && bits > cur) atomicMax(&ctl->dmax_bits, bits);
+  }
+}
+
+// Cell key of every particle and the cell histogram (list-build steps only).
+// The identifier is also written to a compact array for the per-cell sort.
+// The histogram update is aggregated per run of equal keys inside a wave (the
+// particles are still nearly in cell order): one atomic per run, the run's
+// lanes take consecutive tickets.  Tiles follow the XCD-aware order, so each
+// XCD's atomics touch its own slab of counters.
+template <bool BATCH>
+__global__ void k_bin_key(PState s, int64_t n, const Geo* __restrict__ geo,
+                          uint32_t* __restrict__ key, uint32_t* __restrict__ ticket,
+                          uint32_t* __restrict__ idk, uint32_t* __restrict__ count,
+                          const BuildCtl* ctl, double half_skin2, uint32_t* status) {
+  if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;  // uniform
+  const int64_t i = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const bool live = i < n;
+  uint32_t c = 0xFFFFFFFFu;
+  if (live) {
+    const Rec& rc = s.r[i];
+    const Geo& g = geo[BATCH ? rc.rep : 0u];
+    const int cx = cell_coord(rc.qx, g.scale[0], g.nc[0]);
+    const int cy = cell_coord(rc.qy, g.scale[1], g.nc[1]);
+    const int cz = cell_coord(rc.qz, g.scale[2], g.nc[2]);
     c = (uint32_t)(g.cell_base + cx + (int64_t)g.nc[0] * (cy + (int64_t)g.nc[1] * cz));
     key[i] = c;
     idk[i] = rc.id;
@@ -202,7 +264,9 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 }
 
 __global__ void k_scan_tiles(const uint32_t* __restrict__ in, int64_t n,
-                             uint32_t* __restrict__ tile_sums) {
+                             uint32_t* __restrict__ tile_sums, const BuildCtl* ctl,
+                             double half_skin2) {
+  if (!rebuild_now(ctl, half_skin2)) return;
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t s = 0;
 #pragma unroll
@@ -216,7 +280,9 @@ __global__ void k_scan_tiles(const uint32_t* __restrict__ in, int64_t n,
 
 // One block: exclusive scan of the tile sums in place (ntiles <= 1024*8);
 // the grand total goes to tile_sums[ntiles].
-__global__ void k_scan_tile_sums(uint32_t* tile_sums, int ntiles) {
+__global__ void k_scan_tile_sums(uint32_t* tile_sums, int ntiles, const BuildCtl* ctl,
+                                 double half_skin2) {
+  if (!rebuild_now(ctl, half_skin2)) return;
   const int per = (ntiles + blockDim.x - 1) / blockDim.x;
   const int b = threadIdx.x * per;
   uint32_t s = 0;
@@ -237,7 +303,9 @@ __global__ void k_scan_tile_sums(uint32_t* tile_sums, int ntiles) {
 // out[c] = sum_{c' < c} in[c'] for c <= n; the histogram is cleared for the
 // next step.
 __global__ void k_scan_apply(uint32_t* __restrict__ in, int64_t n,
-                             const uint32_t* __restrict__ tile_sums, uint32_t* __restrict__ out) {
+                             const uint32_t* __restrict__ tile_sums, uint32_t* __restrict__ out,
+                             const BuildCtl* ctl, double half_skin2) {
+  if (!rebuild_now(ctl, half_skin2)) return;
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint32_t s = 0;
@@ -263,20 +331,21 @@ __global__ void k_scan_apply(uint32_t* __restrict__ in, int64_t n,
 // perm[offset[key] + ticket] = old slot.
 __global__ void k_scatter(const uint32_t* __restrict__ key, const uint32_t* __restrict__ ticket,
                           const uint32_t* __restrict__ start, int64_t n,
-                          uint32_t* __restrict__ perm, const uint32_t* status) {
+                          uint32_t* __restrict__ perm, const BuildCtl* ctl, double half_skin2,
+                          const uint32_t* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (status_set(status)) return;
+  if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;
   perm[start[key[i]] + ticket[i]] = (uint32_t)i;
 }
 
 // ---- digit 2: order each cell bucket by identifier ---------------------------
 __global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncells,
                             uint32_t* __restrict__ perm, const uint32_t* __restrict__ idk,
-                            const uint32_t* status) {
+                            const BuildCtl* ctl, double half_skin2, const uint32_t* status) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
-  if (status_set(status)) return;
+  if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;
   const uint32_t b = start[c], e = start[c + 1];
   for (uint32_t k = b + 1; k < e; ++k) {
     const uint32_t v = perm[k];
@@ -292,16 +361,34 @@ __global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncells,
   }
 }
 
-// ---- gather into the new order -----------------------------------------------
-// After a device error the order is kept (identity copy), so the state of the
-// failing step survives the buffer swap.
+// ---- gather into the new order (list-build steps) ------------------------------
+// Writes the cell-ordered records into the spare buffer and the build-time
+// positions; k_copy_back then returns them to the working buffer, so the
+// buffer roles never depend on whether this step rebuilt.
+template <bool BATCH>
 __global__ void k_gather(PState src, PState dst, const uint32_t* __restrict__ perm, int64_t n,
+                         const Geo* __restrict__ geo, QRef* __restrict__ qref,
+                         uint32_t* __restrict__ slot, const BuildCtl* ctl, double half_skin2,
                          const uint32_t* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const uint32_t k = status_set(status) ? (uint32_t)i : perm[i];
-  dst.r[i] = src.r[k];
+  if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;
+  const uint32_t k = perm[i];
+  const Rec rc = src.r[k];
+  dst.r[i] = rc;
   dst.eps[i] = src.eps[k];
+  qref[i] = QRef{rc.qx, rc.qy, rc.qz, 0.0};
+  // memory index of every identifier row, for the neighbour-list build
+  slot[(BATCH ? (uint32_t)geo[rc.rep].first : 0u) + rc.id] = (uint32_t)i;
+}
+
+__global__ void k_copy_back(PState src, PState dst, int64_t n, const BuildCtl* ctl,
+                            double half_skin2, const uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;
+  dst.r[i] = src.r[i];
+  dst.eps[i] = src.eps[i];
 }
 
 }  // namespace dpde

@@ -191,6 +191,78 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* smem /* NV * 
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Order-independent sums.  A value x (|x| < 2^31) is rounded once to the grid
+// 2^-64 and held as a 128-bit two's-complement integer (hi:lo); integer
+// addition is associative, so a sum of such values is the same bit pattern
+// whatever the order, tiling or memory layout of its terms.
+// ---------------------------------------------------------------------------
+struct Fix {
+  uint64_t lo;
+  int64_t hi;
+};
+
+__device__ __forceinline__ Fix fix_zero() { return Fix{0ull, 0ll}; }
+
+__device__ __forceinline__ Fix fix_add(Fix a, Fix b) {
+  Fix r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo ? 1ll : 0ll);
+  return r;
+}
+
+// round(x * 2^64): x * 2^32 = h + f exactly with h = floor(x * 2^32) and
+// f in [0, 1); the only rounding is that of f * 2^32 to an integer.
+__device__ __forceinline__ Fix fix_of(double x) {
+  const double y = x * 0x1p32;
+  const double yh = floor(y);
+  const int64_t h = (int64_t)yh;
+  const uint64_t l = (uint64_t)rint((y - yh) * 0x1p32);
+  Fix r;
+  r.lo = ((uint64_t)h << 32);
+  r.hi = h >> 32;
+  return fix_add(r, Fix{l, 0ll});
+}
+
+__device__ __forceinline__ double fix_to_double(Fix a) {
+  return (double)a.hi + (double)a.lo * 0x1p-64;
+}
+
+__device__ __forceinline__ Fix wave_sum_fix(Fix a) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    Fix b;
+    b.lo = (uint64_t)__shfl_xor((long long)a.lo, off, kWave);
+    b.hi = (int64_t)__shfl_xor((long long)a.hi, off, kWave);
+    a = fix_add(a, b);
+  }
+  return a;
+}
+
+// Block-wide sums of NV fixed-point values; thread 0 holds the result.
+template <int NV>
+__device__ __forceinline__ void block_sum_fix(Fix (&v)[NV], Fix* smem /* NV * nwaves */) {
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum_fix(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) smem[k * nw + wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      Fix s = fix_zero();
+      for (int w = 0; w < nw; ++w) s = fix_add(s, smem[k * nw + w]);
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ bool status_set(const uint32_t* status) { return *status != 0u; }
 
 }  // namespace dpde

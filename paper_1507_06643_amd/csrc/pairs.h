@@ -132,34 +132,35 @@ __device__ __forceinline__ int64_t tile_index() {
 // ---------------------------------------------------------------------------
 constexpr int kListLds = 32;
 
-// Phase 1 of pass A: visit the 27-cell stencil and hand every neighbour with
-// r^2 < rc^2 to `sink`.  Only the pair predicate is evaluated here, so the
-// divergent candidate loop stays short; the force arithmetic runs afterwards
-// over the compact list.
+// Visit the 27-cell stencil and hand every particle j != i with r^2 < rc2 to
+// `sink(j, id_j)`.  Only the pair predicate is evaluated here, so the
+// divergent candidate loop stays short.
 template <bool MI, typename Sink>
 __device__ __forceinline__ void scan_candidates(const Geo& g, const uint32_t* __restrict__ start,
                                                 const Rec* __restrict__ R, int64_t i, double xi,
                                                 double yi, double zi, int cx, int cy, int cz,
                                                 double rc2, Sink&& sink) {
-  auto test = [&](uint32_t j, double xj, double yj, double zj) {
+  auto test = [&](uint32_t j, uint32_t idj, double xj, double yj, double zj) {
     double dx = xi - xj, dy = yi - yj, dz = zi - zj;
     if constexpr (MI) {
       if (g.periodic[0]) dx = min_image(dx, g.box[0], g.half_box[0]);
       if (g.periodic[1]) dy = min_image(dy, g.box[1], g.half_box[1]);
       if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
     }
-    if (dist2(dx, dy, dz) < rc2 && j != (uint32_t)i) sink(j);
+    if (dist2(dx, dy, dz) < rc2 && j != (uint32_t)i) sink(j, idj);
   };
   auto range = [&](uint32_t jb, uint32_t je) {
     uint32_t j = jb;
-    // two candidates per trip: both position loads are in flight together
+    // two candidates per trip: both record loads are in flight together
     for (; j + 1 < je; j += 2) {
       const double x0 = R[j].qx, y0 = R[j].qy, z0 = R[j].qz;
+      const uint32_t k0 = R[j].id;
       const double x1 = R[j + 1].qx, y1 = R[j + 1].qy, z1 = R[j + 1].qz;
-      test(j, x0, y0, z0);
-      test(j + 1, x1, y1, z1);
+      const uint32_t k1 = R[j + 1].id;
+      test(j, k0, x0, y0, z0);
+      test(j + 1, k1, x1, y1, z1);
     }
-    if (j < je) test(j, R[j].qx, R[j].qy, R[j].qz);
+    if (j < je) test(j, R[j].id, R[j].qx, R[j].qy, R[j].qz);
   };
   const Row row = stencil_row(cx, g.nc[0], g.periodic[0]);
   for (int dz = -1; dz <= 1; ++dz) {
@@ -180,15 +181,32 @@ __device__ __forceinline__ bool interior_dim(int c, int nc, int periodic) {
   return !periodic || (nc >= 4 && c >= 1 && c <= nc - 2);
 }
 
-template <bool BATCH, int PREC>
-__global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
-    PState s, const uint32_t* __restrict__ start, int64_t n, const Geo* __restrict__ geo, Phys P,
-    int mode, double* __restrict__ Fx, double* __restrict__ Fy, double* __restrict__ Fz,
-    double* __restrict__ Ui, NList nl, uint32_t* status) {
+// ---------------------------------------------------------------------------
+// Neighbour lists with a skin.  On a build step every particle collects the
+// particles within rs = rc + skin through the 27-cell stencil (phase 1 above),
+// and the list is sorted by neighbour identifier.  Every step then keeps the
+// entries with r < rc, in list order: the pair set is exactly the stencil's,
+// and every per-particle sum below runs in identifier order, so the
+// trajectory does not depend on memory order, skin width or build schedule.
+// A build is due when some particle has moved more than skin/2 since the last
+// one (then no pair within rc can be missing from the lists).
+// ---------------------------------------------------------------------------
+struct SkinList {
+  uint32_t* idx;    // k-major, capacity cap per particle
+  uint32_t* count;
+  int64_t stride;   // n
+  int32_t cap;
+  int32_t pad;
+};
+
+template <bool BATCH>
+__global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
+    PState s, const uint32_t* __restrict__ start, int64_t n, const Geo* __restrict__ geo,
+    double rs2, SkinList sl, const BuildCtl* ctl, double half_skin2, uint32_t* status) {
   __shared__ uint32_t lst[kListLds * kPairBlockMax];
+  if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;  // uniform
   const int64_t i = tile_index();
   if (i >= n) return;
-  if (status_set(status)) return;
   const int tid = threadIdx.x, bd = blockDim.x;
   const Rec* __restrict__ R = s.r;
   const double xi = R[i].qx, yi = R[i].qy, zi = R[i].qz;
@@ -197,33 +215,137 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
   const int cy = cell_coord(yi, g.scale[1], g.nc[1]);
   const int cz = cell_coord(zi, g.scale[2], g.nc[2]);
   uint32_t nn = 0;
-  const uint32_t cap = (uint32_t)P.cap;
-  // phase 1: neighbour list (staged in LDS, k-major per block)
-  auto sink = [&](uint32_t j) {
-    if (nn < (uint32_t)kListLds) lst[nn * bd + tid] = j;
-    else if (nn < cap) nl.idx[(int64_t)nn * nl.stride + i] = j;
+  const uint32_t cap = (uint32_t)sl.cap;
+  // the list holds identifier rows (first + id) until k_sort_skin has
+  // ordered them and turned them into memory indices
+  const uint32_t first = (uint32_t)g.first;
+  auto sink = [&](uint32_t, uint32_t idj) {
+    const uint32_t row = first + idj;
+    if (nn < (uint32_t)kListLds) lst[nn * bd + tid] = row;
+    else if (nn < cap) sl.idx[(int64_t)nn * sl.stride + i] = row;
     ++nn;
   };
   const bool interior = interior_dim(cx, g.nc[0], g.periodic[0]) &&
                         interior_dim(cy, g.nc[1], g.periodic[1]) &&
                         interior_dim(cz, g.nc[2], g.periodic[2]);
   if (__all(interior))
-    scan_candidates<false>(g, start, R, i, xi, yi, zi, cx, cy, cz, P.rc2, sink);
+    scan_candidates<false>(g, start, R, i, xi, yi, zi, cx, cy, cz, rs2, sink);
   else
-    scan_candidates<true>(g, start, R, i, xi, yi, zi, cx, cy, cz, P.rc2, sink);
+    scan_candidates<true>(g, start, R, i, xi, yi, zi, cx, cy, cz, rs2, sink);
   if (nn > cap) {
     atomicOr(status, ST_OVERFLOW);
     nn = cap;
   }
-  // phase 2: forces over the compact list, in list order
+  const uint32_t staged = nn < (uint32_t)kListLds ? nn : (uint32_t)kListLds;
+  for (uint32_t k = 0; k < staged; ++k) sl.idx[(int64_t)k * sl.stride + i] = lst[k * bd + tid];
+  sl.count[i] = nn;
+}
+
+// Sort each skin list by neighbour identifier and replace the identifier
+// rows by memory indices (slot[row], written by the reorder).  One list per
+// lane, held in registers padded with all-ones and sorted by a bitonic
+// network of 32 or 64 words (the wave's longest list picks the width; rows
+// are unique, so the order is total).  Lists longer than 64 words are
+// insertion-sorted in place in global memory.
+template <int N>
+__device__ __forceinline__ void bitonic_sort(uint32_t (&v)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int e = 0; e < N; ++e) {
+        const int l = e ^ j;
+        if (l > e) {
+          const uint32_t x = v[e], y = v[l];
+          const bool up = (e & k) == 0;
+          v[e] = up ? min(x, y) : max(x, y);
+          v[l] = up ? max(x, y) : min(x, y);
+        }
+      }
+    }
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void sort_list_regs(const SkinList& sl, const uint32_t* __restrict__ slot,
+                                               int64_t i, uint32_t nn) {
+  uint32_t v[N];
+  const int64_t st = sl.stride;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = (uint32_t)k < nn ? sl.idx[k * st + i] : 0xFFFFFFFFu;
+  bitonic_sort<N>(v);
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    if ((uint32_t)k < nn) sl.idx[k * st + i] = slot[v[k]];
+}
+
+__global__ __launch_bounds__(256) void k_sort_skin(int64_t n, SkinList sl,
+                                                   const uint32_t* __restrict__ slot,
+                                                   const BuildCtl* ctl, double half_skin2,
+                                                   const uint32_t* status) {
+  if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;  // uniform
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nn = i < n ? sl.count[i] : 0u;
+  uint32_t wmax = nn;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1)
+    wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, off, kWave));
+  if (i >= n || nn == 0) return;
+  if (wmax <= 32u) {
+    sort_list_regs<32>(sl, slot, i, nn);
+  } else if (nn <= 64u) {
+    sort_list_regs<64>(sl, slot, i, nn);
+  } else {
+    const int64_t st = sl.stride;
+    for (uint32_t m = 1; m < nn; ++m) {
+      const uint32_t x = sl.idx[m * st + i];
+      uint32_t q = m;
+      while (q > 0) {
+        const uint32_t y = sl.idx[(q - 1) * st + i];
+        if (y <= x) break;
+        sl.idx[q * st + i] = y;
+        --q;
+      }
+      sl.idx[q * st + i] = x;
+    }
+    for (uint32_t m = 0; m < nn; ++m) sl.idx[m * st + i] = slot[sl.idx[m * st + i]];
+  }
+}
+
+// Pass A: neighbour list of the step (skin entries with r < rc, in identifier
+// order, staged in LDS and written out coalesced), forces
+// F_i = sum_j a (1 - r/rc) d_ij / r, U_i = 1/2 sum_j v(r_ij); mode 1 also
+// applies p += dt/2 F (end of velocity-Verlet).
+template <bool BATCH, int PREC>
+__global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
+    PState s, int64_t n, const Geo* __restrict__ geo, Phys P, int mode,
+    double* __restrict__ Fx, double* __restrict__ Fy, double* __restrict__ Fz,
+    double* __restrict__ Ui, SkinList sl, NList nl, uint32_t* status) {
+  __shared__ uint32_t lst[kListLds * kPairBlockMax];
+  const int64_t i = tile_index();
+  if (i >= n) return;
+  if (status_set(status)) return;
+  const int tid = threadIdx.x, bd = blockDim.x;
+  const Rec* __restrict__ R = s.r;
+  const double xi = R[i].qx, yi = R[i].qy, zi = R[i].qz;
+  const Geo& g = geo[BATCH ? R[i].rep : 0u];
+  const uint32_t ns = sl.count[i];
+  const uint32_t cap = (uint32_t)P.cap;
+  uint32_t nn = 0;
   double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0;
   const float inv_rc_f = (float)P.inv_rc, a_f = (float)P.a;
-  for (uint32_t k = 0; k < nn; ++k) {
-    const uint32_t j = k < (uint32_t)kListLds ? lst[k * bd + tid] : nl.idx[(int64_t)k * nl.stride + i];
-    if (k < (uint32_t)kListLds) nl.idx[(int64_t)k * nl.stride + i] = j;
+  uint32_t jn = ns > 0 ? sl.idx[i] : 0u;
+  for (uint32_t k = 0; k < ns; ++k) {
+    const uint32_t j = jn;
+    if (k + 1 < ns) jn = sl.idx[(int64_t)(k + 1) * sl.stride + i];
     double dx, dy, dz;
     separation(g, xi, yi, zi, R[j].qx, R[j].qy, R[j].qz, dx, dy, dz);
     const double r2 = dist2(dx, dy, dz);
+    if (!(r2 < P.rc2)) continue;
+    if (nn < (uint32_t)kListLds) lst[nn * bd + tid] = j;
+    else if (nn < cap) nl.idx[(int64_t)nn * nl.stride + i] = j;
+    ++nn;
     if constexpr (PREC == PREC_F64) {
       const double r = sqrt(r2);
       const double w = 1.0 - r * P.inv_rc;
@@ -242,6 +364,12 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
       fz += (double)(f * (float)dz);
     }
   }
+  if (nn > cap) {
+    atomicOr(status, ST_OVERFLOW);
+    nn = cap;
+  }
+  const uint32_t staged = nn < (uint32_t)kListLds ? nn : (uint32_t)kListLds;
+  for (uint32_t k = 0; k < staged; ++k) nl.idx[(int64_t)k * nl.stride + i] = lst[k * bd + tid];
   nl.count[i] = nn;
   Fx[i] = fx;
   Fy[i] = fy;
@@ -488,47 +616,57 @@ __global__ void k_inv_temperature(PState s, int64_t n, Phys P, uint32_t* status)
 }
 
 // ---------------------------------------------------------------------------
-// Observables: per-tile partial sums, then one block per replica in tile
-// order.  Record: U, K, sum eps, E, Px, Py, Pz, T_kin, T_int, step.
+// Observables: per-tile partial sums, then one block per replica, all in the
+// fixed-point form above, so a record does not depend on the particles'
+// memory order (list rebuild schedule, batching, resume).
+// Record: U, K, sum eps, E, Px, Py, Pz, T_kin, T_int, step.
 // ---------------------------------------------------------------------------
 constexpr int kStatThreads = 256;
+constexpr int kStatVals = 8;  // U, K, sum eps, Px, Py, Pz, sum 1/T, out-of-range count
 
 __global__ __launch_bounds__(kStatThreads) void k_stats_tiles(
     PState s, const double* __restrict__ Ui, const int64_t* __restrict__ tile_begin, Phys P,
-    double* __restrict__ partials) {
+    Fix* __restrict__ partials) {
   const int64_t b = tile_begin[blockIdx.x], e = tile_begin[blockIdx.x + 1];
-  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  Fix v[kStatVals];
+#pragma unroll
+  for (int k = 0; k < kStatVals; ++k) v[k] = fix_zero();
   for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
     const Rec& rc = s.r[i];
     const double px = rc.px, py = rc.py, pz = rc.pz;
     const double p2 = px * px + py * py + pz * pz;
-    v[0] += Ui[i];
-    v[1] += p2 / (2.0 * P.mass);
-    v[2] += s.eps[i];
-    v[3] += px;
-    v[4] += py;
-    v[5] += pz;
-    v[6] += rc.invT;
+    const double x[7] = {Ui[i], p2 / (2.0 * P.mass), s.eps[i], px, py, pz, rc.invT};
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      // values outside the fixed-point range are counted, and the record is NaN
+      if (fabs(x[k]) < 0x1p30) v[k] = fix_add(v[k], fix_of(x[k]));
+      else v[7] = fix_add(v[7], Fix{1ull, 0ll});
+    }
   }
-  __shared__ double smem[7 * (kStatThreads / kWave)];
-  block_sum<7>(v, smem);
+  __shared__ Fix smem[kStatVals * (kStatThreads / kWave)];
+  block_sum_fix<kStatVals>(v, smem);
   if (threadIdx.x == 0)
-    for (int k = 0; k < 7; ++k) partials[blockIdx.x * 8 + k] = v[k];
+    for (int k = 0; k < kStatVals; ++k) partials[blockIdx.x * kStatVals + k] = v[k];
 }
 
 __global__ __launch_bounds__(kStatThreads) void k_stats_final(
-    const double* __restrict__ partials, const int32_t* __restrict__ rep_tile0,
+    const Fix* __restrict__ partials, const int32_t* __restrict__ rep_tile0,
     const Geo* __restrict__ geo, const uint64_t* __restrict__ d_step, int advance,
     double* __restrict__ rec, double* __restrict__ hist, int64_t hist_cap,
     const int64_t* __restrict__ d_hist_count, int nrep) {
   const int r = blockIdx.x;
   const int t0 = rep_tile0[r], t1 = rep_tile0[r + 1];
-  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  Fix f[kStatVals];
+#pragma unroll
+  for (int k = 0; k < kStatVals; ++k) f[k] = fix_zero();
   for (int t = t0 + threadIdx.x; t < t1; t += blockDim.x)
-    for (int k = 0; k < 7; ++k) v[k] += partials[t * 8 + k];
-  __shared__ double smem[7 * (kStatThreads / kWave)];
-  block_sum<7>(v, smem);
+    for (int k = 0; k < kStatVals; ++k) f[k] = fix_add(f[k], partials[t * kStatVals + k]);
+  __shared__ Fix smem[kStatVals * (kStatThreads / kWave)];
+  block_sum_fix<kStatVals>(f, smem);
   if (threadIdx.x == 0) {
+    const bool bad = f[7].lo != 0ull || f[7].hi != 0ll;
+    double v[7];
+    for (int k = 0; k < 7; ++k) v[k] = bad ? __builtin_nan("") : fix_to_double(f[k]);
     const double N = (double)geo[r].n;
     double o[10];
     o[0] = v[0];
@@ -550,11 +688,19 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_final(
   }
 }
 
-// End of a step: n <- n + 1, one more history record (not after an error).
-__global__ void k_step_advance(uint64_t* d_step, int64_t* d_hist_count, const uint32_t* status) {
+// End of a step: count a list build, clear the build control, and (when
+// advancing) n <- n + 1 with one more history record (not after an error).
+__global__ void k_step_end(uint64_t* d_step, int64_t* d_hist_count, BuildCtl* ctl,
+                           unsigned long long* builds, double half_skin2, int advance,
+                           const uint32_t* status) {
   if (status_set(status)) return;
-  *d_step += 1;
-  *d_hist_count += 1;
+  if (rebuild_now(ctl, half_skin2)) *builds += 1ull;
+  ctl->dmax_bits = 0ull;
+  ctl->force = 0u;
+  if (advance) {
+    *d_step += 1;
+    *d_hist_count += 1;
+  }
 }
 
 // ---------------------------------------------------------------------------

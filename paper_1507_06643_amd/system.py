@@ -32,6 +32,7 @@ class Config:
     eos_n: float = 50.0
     eos_omega: float = 2.0
     eos_c0: float = 10.0
+    skin: float = 0.3
     precision: int = L.FP64
     theta_mode: int = L.THETA_NEWTON
     scheme: int = L.SCHEME_SER
@@ -47,6 +48,7 @@ class Config:
         P.mass, P.rc, P.a, P.gamma = self.mass, self.rc, self.a, self.gamma
         P.kT_ref, P.dt, P.cv = self.kT_ref, self.dt, self.cv
         P.eos_n, P.eos_omega, P.eos_c0 = self.eos_n, self.eos_omega, self.eos_c0
+        P.skin = float(self.skin)
         P.seed, P.step0 = int(self.seed) & (2**64 - 1), int(self.step0)
         P.periodic = (C.c_int32 * 3)(*[int(x) for x in self.periodic])
         P.eos, P.precision, P.theta_mode, P.scheme = (int(self.eos), int(self.precision),
@@ -116,6 +118,11 @@ class System:
 
     def step_graph(self, nsteps: int, reps: int = 1) -> int:
         return L.check(self._lib.dpde_step_graph(self.h, int(nsteps), int(reps)))
+
+    def list_builds(self) -> int:
+        b = C.c_int64(0)
+        L.check(self._lib.dpde_list_builds(self.h, C.byref(b)))
+        return b.value
 
     def set_tuning(self, pair_block: int, aux_block: int = 256):
         L.check(self._lib.dpde_set_tuning(self.h, int(pair_block), int(aux_block)))

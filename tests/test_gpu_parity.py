@@ -96,17 +96,20 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("skin", [0.0, 0.3])
 @pytest.mark.parametrize("n,box,periodic,seed", CASES)
-def test_cells_and_pairs_bit_exact(dp, n, box, periodic, seed):
+def test_cells_and_pairs_bit_exact(dp, n, box, periodic, seed, skin):
     if box is None:
         L = W.cubic_side(n)
         box = (L, L, L)
     q = _adversarial(n, box, seed)
     _, p, e = W.equilibrium_state(n, box, seed=seed)
-    sysm = dp.System(_cfg(dp, n, box, periodic=periodic), q, p, e)
+    sysm = dp.System(_cfg(dp, n, box, periodic=periodic, skin=skin), q, p, e)
     P = _oparams(n, box, periodic=periodic)
+    # cells have side rc + skin (the reach of the neighbour lists)
+    Pc = _oparams(n, box, periodic=periodic, rc=1.0 + skin)
     cells = sysm.debug_cells().cpu().numpy()
-    assert np.array_equal(cells, O.cell_index(P, q))
+    assert np.array_equal(cells, O.cell_index(Pc, q))
     got = sysm.debug_pairs()
     want = O.pairs(P, q, "cells")
     assert got.shape == want.shape
@@ -123,7 +126,8 @@ def test_pairs_of_evolved_state_match_brute_force(dp):
     qg, _, _, _ = _gpu_state(sysm)
     P = _oparams(n, [L] * 3)
     assert np.array_equal(sysm.debug_pairs(), O.pairs(P, qg, "brute"))
-    assert np.array_equal(sysm.debug_cells().cpu().numpy(), O.cell_index(P, qg))
+    Pc = _oparams(n, [L] * 3, rc=1.0 + sysm.cfg.skin)
+    assert np.array_equal(sysm.debug_cells().cpu().numpy(), O.cell_index(Pc, qg))
 
 
 # ---------------------------------------------------------------------------
@@ -234,6 +238,30 @@ def test_bit_reproducible_and_resumable(dp):
     assert sa[3] == sc[3] == 20
     for s in (a, b, c):
         s.close()
+
+
+def test_trajectory_independent_of_skin(dp):
+    """Neighbour lists built every step (skin 0) and Verlet lists with a skin
+    rebuilt on displacement give the same trajectory bit for bit: the lists
+    are filtered to r < rc in neighbour-id order every step."""
+    n = 5000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=91)
+    states, builds, records = [], [], []
+    for skin in (0.0, 0.2, 0.5):
+        s = dp.System(_cfg(dp, n, [L] * 3, skin=skin, dt=0.01), q, p, e)
+        s.step(60)
+        states.append(_gpu_state(s))
+        builds.append(s.list_builds())
+        records.append(s.history())
+        s.close()
+    for st, rec in zip(states[1:], records[1:]):
+        for x, y in zip(states[0][:3], st[:3]):
+            assert np.array_equal(x, y)
+        # observables are fixed-point sums: independent of the memory order
+        assert np.array_equal(records[0], rec)
+    assert builds[0] == 61                 # initial build + one per step
+    assert 1 < builds[2] < builds[1] < 61  # fewer rebuilds with a larger skin
 
 
 def test_stored_increments_equal_regenerated_noise(dp):
