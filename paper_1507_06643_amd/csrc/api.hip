@@ -354,7 +354,8 @@ void enqueue_bin(dpde_handle* h, int kick) {
   launch(h, "copy_back", k_copy_back, blocks(n, b), b, h->alt, h->cur, n, ctl, hs2,
          (const uint32_t*)h->status);
   const int pb = h->pair_block;
-  launch(h, "build_skin", h->batch ? k_build_skin<true> : k_build_skin<false>, blocks(n, pb), pb,
+  launch(h, "build_skin", h->batch ? k_build_skin<true> : k_build_skin<false>,
+         blocks(n * kSub, pb), pb,
          h->cur, (const uint32_t*)h->cell_start, n, (const Geo*)h->geo, h->rs2, h->skin, ctl, hs2,
          h->status);
   launch(h, "sort_skin", k_sort_skin, blocks(n, 256), 256, n, h->skin, (const uint32_t*)h->slot,
@@ -365,7 +366,7 @@ void enqueue_forces(dpde_handle* h, int mode) {
   const int b = h->pair_block;
   const int64_t n = h->n;
   auto go = [&](auto kern) {
-    launch(h, "pass_a_forces", kern, blocks(n, b), b, h->cur, n, (const Geo*)h->geo, h->phys, mode,
+    launch(h, "pass_a_forces", kern, blocks(n * kSub, b), b, h->cur, n, (const Geo*)h->geo, h->phys, mode,
            h->Fx, h->Fy, h->Fz, h->Ui, h->skin, h->nl, h->status);
   };
   if (h->batch) {
@@ -389,18 +390,18 @@ void enqueue_fd_t(dpde_handle* h) {
   const uint64_t* d_step = h->d_step;
   const int store = h->regen ? 0 : 1;
   if (h->phys.scheme == DPDE_SCHEME_SEM) {
-    launch(h, "pass_b_sem", k_pass_b<B, PR, 1>, blocks(n, b), b, h->cur, h->nl, n,
+    launch(h, "pass_b_sem", k_pass_b<B, PR, 1>, blocks(n * kSub, b), b, h->cur, h->nl, n,
            (const Geo*)h->geo, h->phys, d_step, h->pv, h->deps, 0, h->status);
     launch(h, "apply_sem", k_apply_sem, blocks(n, h->aux_block), h->aux_block, h->cur, n, h->phys,
            (const PV*)h->pv, (const double*)h->deps, inl, h->alt.r, h->status);
   } else {
-    launch(h, "pass_b_ser", k_pass_b<B, PR, 0>, blocks(n, b), b, h->cur, h->nl, n,
+    launch(h, "pass_b_ser", k_pass_b<B, PR, 0>, blocks(n * kSub, b), b, h->cur, h->nl, n,
            (const Geo*)h->geo, h->phys, d_step, h->pv, h->deps, store, h->status);
     if (h->regen)
-      launch(h, "pass_c_ser", k_pass_c<B, PR, 1>, blocks(n, b), b, h->cur, h->nl, n,
+      launch(h, "pass_c_ser", k_pass_c<B, PR, 1>, blocks(n * kSub, b), b, h->cur, h->nl, n,
              (const Geo*)h->geo, h->phys, d_step, (const PV*)h->pv, inl, h->alt.r, h->status);
     else
-      launch(h, "pass_c_ser", k_pass_c<B, PR, 0>, blocks(n, b), b, h->cur, h->nl, n,
+      launch(h, "pass_c_ser", k_pass_c<B, PR, 0>, blocks(n * kSub, b), b, h->cur, h->nl, n,
              (const Geo*)h->geo, h->phys, d_step, (const PV*)h->pv, inl, h->alt.r, h->status);
   }
   // the updated records were written to the spare record array: swap them in

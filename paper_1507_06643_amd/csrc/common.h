@@ -81,20 +81,115 @@ __device__ __forceinline__ void pair_words(const Geo& g, uint32_t lo, uint32_t h
   philox4x32_10(w[0], w[1], w[2], w[3], g.key0, g.key1);
 }
 
+// ---------------------------------------------------------------------------
+// FP64 elementary functions for the Box-Muller transform, specialised to its
+// arguments and written from their series (relative error a few units in the
+// last place, against ~100 instructions for the general library logarithm).
+// ---------------------------------------------------------------------------
+
+// ln u for u = (x + 1/2) 2^-32 = (2x + 1) 2^-33.  With 2x + 1 = m 2^e and
+// m in [1/sqrt 2, sqrt 2): ln u = (e - 33) ln 2 + ln m, and
+// ln m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...), s = (m - 1)/(m + 1),
+// |s| <= 0.172 (eleven terms leave a relative remainder below 1e-18).
+__device__ __forceinline__ double ln_uniform_f64(uint32_t x) {
+  const double y = 2.0 * (double)x + 1.0;  // exact
+  double m = __builtin_amdgcn_frexp_mant(y);  // [1/2, 1)
+  int e = __builtin_amdgcn_frexp_exp(y);
+  if (m < 0.70710678118654752) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double f = m - 1.0;  // exact
+  const double d = m + 1.0;
+  // s = f / d: reciprocal seed, one Newton step, one residual correction
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  double s = f * r;
+  s = fma(r, fma(-s, d, f), s);
+  const double z = s * s;
+  double p = 0.09523809523809523;  // 2/21
+  p = fma(p, z, 0.10526315789473684);
+  p = fma(p, z, 0.11764705882352941);
+  p = fma(p, z, 0.13333333333333333);
+  p = fma(p, z, 0.15384615384615385);
+  p = fma(p, z, 0.18181818181818182);
+  p = fma(p, z, 0.2222222222222222);
+  p = fma(p, z, 0.2857142857142857);
+  p = fma(p, z, 0.4);
+  p = fma(p, z, 0.6666666666666666);
+  const double lnm = fma(s * z, p, 2.0 * s);  // 2s + s z (2/3 + ...)
+  const double E = (double)(e - 33);
+  // ln 2 split so that E * ln2_hi is exact
+  return fma(E, 0.6931471805601177, fma(E, -1.7239444525614835e-13, lnm));
+}
+
+// sqrt(v) for v in [2^-33, 64]: reciprocal square-root seed and two Newton
+// steps (the second on the root itself).
+__device__ __forceinline__ double sqrt_pos_f64(double v) {
+  const double r0 = __builtin_amdgcn_rsq(v);
+  double y = v * r0, h = 0.5 * r0;
+  const double e = fma(-y, h, 0.5);
+  y = fma(y, e, y);
+  h = fma(h, e, h);
+  return fma(fma(-y, y, v), h, y);
+}
+
+// 1/sqrt(v) for v >= 0 (0 for v = 0, so that v * inv_sqrt(v) = sqrt(v)):
+// reciprocal square-root seed and two Newton steps.
+__device__ __forceinline__ double inv_sqrt_f64(double v) {
+  if (!(v > 0.0)) return 0.0;
+  double r = __builtin_amdgcn_rsq(v);
+  const double h = 0.5 * v;
+  r = fma(r, fma(-h * r, r, 0.5), r);
+  r = fma(r, fma(-h * r, r, 0.5), r);
+  return r;
+}
+
+// sin(pi t) and cos(pi t) for t in [0, 2]: t = k/2 + y with k = rint(2t) and
+// |y| <= 1/4 exactly; the Taylor series of sin(pi y) and cos(pi y) to the
+// 17th and 16th power, then the quarter-turn k mod 4 rotates the pair.
+__device__ __forceinline__ void sincospi_f64(double t, double& sn, double& cs) {
+  const double k = rint(2.0 * t);
+  const double y = fma(-0.5, k, t);  // exact
+  const double w = y * y;
+  double ps = 7.952054001475513e-07;
+  ps = fma(ps, w, -2.1915353447830217e-05);
+  ps = fma(ps, w, 0.00046630280576761255);
+  ps = fma(ps, w, -0.0073704309457143504);
+  ps = fma(ps, w, 0.08214588661112823);
+  ps = fma(ps, w, -0.5992645293207921);
+  ps = fma(ps, w, 2.5501640398773455);
+  ps = fma(ps, w, -5.16771278004997);
+  const double sp = fma(y * w, ps, 3.141592653589793 * y);
+  double pc = 4.303069587032947e-06;
+  pc = fma(pc, w, -0.0001046381049248457);
+  pc = fma(pc, w, 0.0019295743094039231);
+  pc = fma(pc, w, -0.02580689139001406);
+  pc = fma(pc, w, 0.2353306303588932);
+  pc = fma(pc, w, -1.3352627688545895);
+  pc = fma(pc, w, 4.0587121264167685);
+  pc = fma(pc, w, -4.934802200544679);
+  const double cp = fma(w, pc, 1.0);
+  const int q = (int)k & 3;
+  const double a = (q & 1) ? cp : sp;  // sin of the rotated angle, up to sign
+  const double b = (q & 1) ? sp : cp;  // cos of the rotated angle, up to sign
+  sn = (q & 2) ? -a : a;
+  cs = ((q + 1) & 2) ? -b : b;
+}
+
 // FP64 normals from the four words: u = (x + 1/2) 2^-32 in (0,1).
 __device__ __forceinline__ void box_muller_f64(const uint32_t w[4], double G[3]) {
   const double s = 2.3283064365386963e-10;  // 2^-32
-  const double u0 = ((double)w[0] + 0.5) * s;
-  const double u1 = ((double)w[1] + 0.5) * s;
-  const double u2 = ((double)w[2] + 0.5) * s;
-  const double u3 = ((double)w[3] + 0.5) * s;
-  const double r1 = sqrt(-2.0 * log(u0));
-  const double r2 = sqrt(-2.0 * log(u2));
-  double sn, cs;
-  sincospi(2.0 * u1, &sn, &cs);
+  const double r1 = sqrt_pos_f64(-2.0 * ln_uniform_f64(w[0]));
+  const double r2 = sqrt_pos_f64(-2.0 * ln_uniform_f64(w[2]));
+  const double t1 = (2.0 * (double)w[1] + 1.0) * s;  // 2 u1, exact
+  const double t3 = (2.0 * (double)w[3] + 1.0) * s;
+  double sn, cs, sn3, cs3;
+  sincospi_f64(t1, sn, cs);
+  sincospi_f64(t3, sn3, cs3);
   G[0] = r1 * cs;
   G[1] = r1 * sn;
-  G[2] = r2 * cospi(2.0 * u3);
+  G[2] = r2 * cs3;
 }
 
 // ln u for u = (x + 1/2) 2^-32 in FP32.  Far from 1 the float of x keeps 24

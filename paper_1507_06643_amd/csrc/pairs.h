@@ -116,51 +116,76 @@ __device__ __forceinline__ void separation(const Geo& g, double xi, double yi, d
   if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
 }
 
-__device__ __forceinline__ int64_t tile_index() {
-  return (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+// ---------------------------------------------------------------------------
+// Lane groups.  Every particle is served by kSub consecutive lanes of one
+// wave: lane `sub` of the group takes the list entries sub, sub + kSub, ...,
+// and partial sums meet in a fixed xor butterfly.  The butterfly adds the same
+// two operands on both partner lanes (in swapped order, which addition does
+// not see), so all lanes of a group end with the same, reproducible sum.
+// Compaction into a list keeps the candidates' order: each trip the group
+// ballots its predicates and a lane's slot is the count of set bits below it.
+// ---------------------------------------------------------------------------
+constexpr int kSub = 4;
+constexpr uint32_t kSubMask = (1u << kSub) - 1u;
+constexpr int kListLds = 64;  // list entries per particle staged in LDS
+
+struct Lanes {
+  int64_t i;     // particle
+  int sub;       // lane within the group
+  int pib;       // group within the block
+  int ppb;       // groups per block
+  int shift;     // position of the group's bits in a wave ballot
+};
+
+__device__ __forceinline__ Lanes lanes() {
+  Lanes L;
+  const int64_t t = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  L.i = t / kSub;
+  L.sub = threadIdx.x % kSub;
+  L.pib = threadIdx.x / kSub;
+  L.ppb = blockDim.x / kSub;
+  L.shift = (threadIdx.x % kWave) & ~(kSub - 1);
+  return L;
 }
 
-// ---------------------------------------------------------------------------
-// Pass A: forces F_i = sum_j a (1 - r/rc) d_ij / r, U_i = 1/2 sum_j v(r_ij),
-// neighbour list; mode 1 also applies p += dt/2 F (end of velocity-Verlet).
-//
-// Each lane finds its neighbours at its own pace; the list is staged in LDS
-// (k-major per block) and written to HBM at the end, one coalesced store per
-// k, instead of scattered partial-line stores during the search.  A wave whose
-// particles all sit in interior cells (no periodic image reachable through the
-// stencil) skips the minimum-image test, which is then the identity.
-// ---------------------------------------------------------------------------
-constexpr int kListLds = 32;
+__device__ __forceinline__ double group_sum(double x) {
+#pragma unroll
+  for (int off = 1; off < kSub; off <<= 1) x += __shfl_xor(x, off, kWave);
+  return x;
+}
 
-// Visit the 27-cell stencil and hand every particle j != i with r^2 < rc2 to
-// `sink(j, id_j)`.  Only the pair predicate is evaluated here, so the
-// divergent candidate loop stays short.
+// Group bits of a wave ballot.
+__device__ __forceinline__ uint32_t group_ballot(const Lanes& L, bool pred) {
+  return (uint32_t)(__ballot(pred) >> L.shift) & kSubMask;
+}
+
+// Visit the 27-cell stencil; the group's lanes take the candidates of every
+// cell run in turn (lane sub takes run[sub], run[sub + kSub], ...) and call
+// `sink(take, j, id_j)` on every trip, `take` being r^2 < rc2 and j != i.
+// The trips are uniform across the group, so `sink` may ballot.
 template <bool MI, typename Sink>
-__device__ __forceinline__ void scan_candidates(const Geo& g, const uint32_t* __restrict__ start,
-                                                const Rec* __restrict__ R, int64_t i, double xi,
-                                                double yi, double zi, int cx, int cy, int cz,
-                                                double rc2, Sink&& sink) {
-  auto test = [&](uint32_t j, uint32_t idj, double xj, double yj, double zj) {
-    double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-    if constexpr (MI) {
-      if (g.periodic[0]) dx = min_image(dx, g.box[0], g.half_box[0]);
-      if (g.periodic[1]) dy = min_image(dy, g.box[1], g.half_box[1]);
-      if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
-    }
-    if (dist2(dx, dy, dz) < rc2 && j != (uint32_t)i) sink(j, idj);
-  };
+__device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
+                                                const uint32_t* __restrict__ start,
+                                                const Rec* __restrict__ R, double xi, double yi,
+                                                double zi, int cx, int cy, int cz, double rc2,
+                                                Sink&& sink) {
   auto range = [&](uint32_t jb, uint32_t je) {
-    uint32_t j = jb;
-    // two candidates per trip: both record loads are in flight together
-    for (; j + 1 < je; j += 2) {
-      const double x0 = R[j].qx, y0 = R[j].qy, z0 = R[j].qz;
-      const uint32_t k0 = R[j].id;
-      const double x1 = R[j + 1].qx, y1 = R[j + 1].qy, z1 = R[j + 1].qz;
-      const uint32_t k1 = R[j + 1].id;
-      test(j, k0, x0, y0, z0);
-      test(j + 1, k1, x1, y1, z1);
+    for (uint32_t base = jb; base < je; base += kSub) {
+      const uint32_t j = base + L.sub;
+      bool take = false;
+      uint32_t idj = 0;
+      if (j < je) {
+        double dx = xi - R[j].qx, dy = yi - R[j].qy, dz = zi - R[j].qz;
+        idj = R[j].id;
+        if constexpr (MI) {
+          if (g.periodic[0]) dx = min_image(dx, g.box[0], g.half_box[0]);
+          if (g.periodic[1]) dy = min_image(dy, g.box[1], g.half_box[1]);
+          if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
+        }
+        take = dist2(dx, dy, dz) < rc2 && j != (uint32_t)L.i;
+      }
+      sink(take, j, idj);
     }
-    if (j < je) test(j, R[j].id, R[j].qx, R[j].qy, R[j].qz);
   };
   const Row row = stencil_row(cx, g.nc[0], g.periodic[0]);
   for (int dz = -1; dz <= 1; ++dz) {
@@ -203,11 +228,11 @@ template <bool BATCH>
 __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
     PState s, const uint32_t* __restrict__ start, int64_t n, const Geo* __restrict__ geo,
     double rs2, SkinList sl, const BuildCtl* ctl, double half_skin2, uint32_t* status) {
-  __shared__ uint32_t lst[kListLds * kPairBlockMax];
+  __shared__ uint32_t lst[kListLds * (kPairBlockMax / kSub)];
   if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;  // uniform
-  const int64_t i = tile_index();
-  if (i >= n) return;
-  const int tid = threadIdx.x, bd = blockDim.x;
+  const Lanes L = lanes();
+  if (L.i >= n) return;  // uniform in the group
+  const int64_t i = L.i;
   const Rec* __restrict__ R = s.r;
   const double xi = R[i].qx, yi = R[i].qy, zi = R[i].qz;
   const Geo& g = geo[BATCH ? R[i].rep : 0u];
@@ -219,26 +244,31 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
   // the list holds identifier rows (first + id) until k_sort_skin has
   // ordered them and turned them into memory indices
   const uint32_t first = (uint32_t)g.first;
-  auto sink = [&](uint32_t, uint32_t idj) {
-    const uint32_t row = first + idj;
-    if (nn < (uint32_t)kListLds) lst[nn * bd + tid] = row;
-    else if (nn < cap) sl.idx[(int64_t)nn * sl.stride + i] = row;
-    ++nn;
+  auto sink = [&](bool take, uint32_t, uint32_t idj) {
+    const uint32_t bits = group_ballot(L, take);
+    if (take) {
+      const uint32_t pos = nn + __popc(bits & ((1u << L.sub) - 1u));
+      const uint32_t row = first + idj;
+      if (pos < (uint32_t)kListLds) lst[pos * L.ppb + L.pib] = row;
+      else if (pos < cap) sl.idx[(int64_t)pos * sl.stride + i] = row;
+    }
+    nn += __popc(bits);
   };
   const bool interior = interior_dim(cx, g.nc[0], g.periodic[0]) &&
                         interior_dim(cy, g.nc[1], g.periodic[1]) &&
                         interior_dim(cz, g.nc[2], g.periodic[2]);
   if (__all(interior))
-    scan_candidates<false>(g, start, R, i, xi, yi, zi, cx, cy, cz, rs2, sink);
+    scan_candidates<false>(L, g, start, R, xi, yi, zi, cx, cy, cz, rs2, sink);
   else
-    scan_candidates<true>(g, start, R, i, xi, yi, zi, cx, cy, cz, rs2, sink);
+    scan_candidates<true>(L, g, start, R, xi, yi, zi, cx, cy, cz, rs2, sink);
   if (nn > cap) {
-    atomicOr(status, ST_OVERFLOW);
+    if (L.sub == 0) atomicOr(status, ST_OVERFLOW);
     nn = cap;
   }
   const uint32_t staged = nn < (uint32_t)kListLds ? nn : (uint32_t)kListLds;
-  for (uint32_t k = 0; k < staged; ++k) sl.idx[(int64_t)k * sl.stride + i] = lst[k * bd + tid];
-  sl.count[i] = nn;
+  for (uint32_t k = L.sub; k < staged; k += kSub)
+    sl.idx[(int64_t)k * sl.stride + i] = lst[k * L.ppb + L.pib];
+  if (L.sub == 0) sl.count[i] = nn;
 }
 
 // Sort each skin list by neighbour identifier and replace the identifier
@@ -322,11 +352,11 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
     PState s, int64_t n, const Geo* __restrict__ geo, Phys P, int mode,
     double* __restrict__ Fx, double* __restrict__ Fy, double* __restrict__ Fz,
     double* __restrict__ Ui, SkinList sl, NList nl, uint32_t* status) {
-  __shared__ uint32_t lst[kListLds * kPairBlockMax];
-  const int64_t i = tile_index();
-  if (i >= n) return;
+  __shared__ uint32_t lst[kListLds * (kPairBlockMax / kSub)];
+  const Lanes L = lanes();
+  if (L.i >= n) return;  // uniform in the group
   if (status_set(status)) return;
-  const int tid = threadIdx.x, bd = blockDim.x;
+  const int64_t i = L.i;
   const Rec* __restrict__ R = s.r;
   const double xi = R[i].qx, yi = R[i].qy, zi = R[i].qz;
   const Geo& g = geo[BATCH ? R[i].rep : 0u];
@@ -335,51 +365,78 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
   uint32_t nn = 0;
   double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0;
   const float inv_rc_f = (float)P.inv_rc, a_f = (float)P.a;
-  uint32_t jn = ns > 0 ? sl.idx[i] : 0u;
-  for (uint32_t k = 0; k < ns; ++k) {
+  uint32_t jn = (uint32_t)L.sub < ns ? sl.idx[(int64_t)L.sub * sl.stride + i] : 0u;
+  for (uint32_t base = 0; base < ns; base += kSub) {
+    const uint32_t k = base + L.sub;
     const uint32_t j = jn;
-    if (k + 1 < ns) jn = sl.idx[(int64_t)(k + 1) * sl.stride + i];
-    double dx, dy, dz;
-    separation(g, xi, yi, zi, R[j].qx, R[j].qy, R[j].qz, dx, dy, dz);
-    const double r2 = dist2(dx, dy, dz);
-    if (!(r2 < P.rc2)) continue;
-    if (nn < (uint32_t)kListLds) lst[nn * bd + tid] = j;
-    else if (nn < cap) nl.idx[(int64_t)nn * nl.stride + i] = j;
-    ++nn;
-    if constexpr (PREC == PREC_F64) {
-      const double r = sqrt(r2);
-      const double w = 1.0 - r * P.inv_rc;
-      u += w * w;
-      const double f = r > 0.0 ? P.a * w / r : 0.0;
-      fx += f * dx;
-      fy += f * dy;
-      fz += f * dz;
-    } else {
-      const float r = __builtin_sqrtf((float)r2);
-      const float w = 1.0f - r * inv_rc_f;
-      u += (double)(w * w);
-      const float f = r > 0.0f ? a_f * w / r : 0.0f;
-      fx += (double)(f * (float)dx);
-      fy += (double)(f * (float)dy);
-      fz += (double)(f * (float)dz);
+    if (k + kSub < ns) jn = sl.idx[(int64_t)(k + kSub) * sl.stride + i];
+    bool take = false;
+    double dx = 0.0, dy = 0.0, dz = 0.0, r2 = 0.0;
+    if (k < ns) {
+      separation(g, xi, yi, zi, R[j].qx, R[j].qy, R[j].qz, dx, dy, dz);
+      r2 = dist2(dx, dy, dz);
+      take = r2 < P.rc2;
     }
+    const uint32_t bits = group_ballot(L, take);
+    const uint32_t c = __popc(bits);
+    if (take) {
+      const uint32_t pos = nn + __popc(bits & ((1u << L.sub) - 1u));
+      if (pos < (uint32_t)kListLds) lst[pos * L.ppb + L.pib] = j;
+      else if (pos < cap) nl.idx[(int64_t)pos * nl.stride + i] = j;
+    }
+    // the pair at list position p is summed by lane p mod kSub (as in passes
+    // B and C), whichever lane tested it: lane sub owns rank r of this trip
+    const uint32_t r = (uint32_t)(L.sub - (int)nn) & (uint32_t)(kSub - 1);
+    uint32_t b = bits;
+    for (uint32_t q = 0; q < r; ++q) b &= b - 1u;
+    const int src = L.shift + (b ? __ffs(b) - 1 : 0);
+    const double ox = __shfl(dx, src, kWave), oy = __shfl(dy, src, kWave);
+    const double oz = __shfl(dz, src, kWave), orr = __shfl(r2, src, kWave);
+    if (r < c) {
+      if constexpr (PREC == PREC_F64) {
+        const double ir = inv_sqrt_f64(orr);  // 0 at r = 0
+        const double rr = orr * ir;
+        const double w = 1.0 - rr * P.inv_rc;
+        u += w * w;
+        const double f = P.a * w * ir;
+        fx += f * ox;
+        fy += f * oy;
+        fz += f * oz;
+      } else {
+        const float rr = __builtin_sqrtf((float)orr);
+        const float w = 1.0f - rr * inv_rc_f;
+        u += (double)(w * w);
+        const float f = rr > 0.0f ? a_f * w / rr : 0.0f;
+        fx += (double)(f * (float)ox);
+        fy += (double)(f * (float)oy);
+        fz += (double)(f * (float)oz);
+      }
+    }
+    nn += c;
   }
+  fx = group_sum(fx);
+  fy = group_sum(fy);
+  fz = group_sum(fz);
+  u = group_sum(u);
   if (nn > cap) {
-    atomicOr(status, ST_OVERFLOW);
+    if (L.sub == 0) atomicOr(status, ST_OVERFLOW);
     nn = cap;
   }
   const uint32_t staged = nn < (uint32_t)kListLds ? nn : (uint32_t)kListLds;
-  for (uint32_t k = 0; k < staged; ++k) nl.idx[(int64_t)k * nl.stride + i] = lst[k * bd + tid];
-  nl.count[i] = nn;
-  Fx[i] = fx;
-  Fy[i] = fy;
-  Fz[i] = fz;
-  Ui[i] = 0.5 * P.half_a_rc * u;
-  if (mode) {
-    Rec* W = s.r;
-    W[i].px = W[i].px + P.half_dt * fx;
-    W[i].py = W[i].py + P.half_dt * fy;
-    W[i].pz = W[i].pz + P.half_dt * fz;
+  for (uint32_t k = L.sub; k < staged; k += kSub)
+    nl.idx[(int64_t)k * nl.stride + i] = lst[k * L.ppb + L.pib];
+  if (L.sub == 0) {
+    nl.count[i] = nn;
+    Fx[i] = fx;
+    Fy[i] = fy;
+    Fz[i] = fz;
+    Ui[i] = 0.5 * P.half_a_rc * u;
+    if (mode) {
+      Rec* W = s.r;
+      W[i].px = W[i].px + P.half_dt * fx;
+      W[i].py = W[i].py + P.half_dt * fy;
+      W[i].pz = W[i].pz + P.half_dt * fz;
+    }
   }
 }
 
@@ -407,7 +464,7 @@ __device__ __forceinline__ void ser_pair(const Phys& P, const Geo& g, double r2,
   uint32_t wd[4];
   pair_words(g, i_lo ? idi : idj, i_lo ? idj : idi, step, wd);
   if constexpr (PREC == PREC_F64) {
-    const double r = sqrt(r2);
+    const double r = r2 * inv_sqrt_f64(r2);
     const double w = 1.0 - r * P.inv_rc;
     const double chi = w * w;
     const double gij = P.gkT_half * invT_sum;
@@ -464,23 +521,25 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
     const uint64_t* __restrict__ d_step, PV* __restrict__ pv, double* __restrict__ deps,
     int store, uint32_t* status) {
-  const int64_t i = tile_index();
-  if (i >= n) return;
+  const Lanes L = lanes();
+  if (L.i >= n) return;  // uniform in the group
   if (status_set(status)) return;
+  const int64_t i = L.i;
   const uint64_t step = *d_step;
   const Rec* __restrict__ R = s.r;
   const Rec a = R[i];
   const Geo& g = geo[BATCH ? a.rep : 0u];
   const uint32_t nn = nl.count[i];
+  const int64_t st = nl.stride;
   double ax = 0.0, ay = 0.0, az = 0.0, de = 0.0;
-  // software pipeline: the record of neighbour k+1 is requested before the
-  // pair term of neighbour k is computed
+  // software pipeline: the record of the lane's next neighbour is requested
+  // before the pair term of the current one is computed
   Rec nb;
-  if (nn > 0) nb = R[nl.idx[i]];
-  for (uint32_t k = 0; k < nn; ++k) {
-    const int64_t e = (int64_t)k * nl.stride + i;
+  if ((uint32_t)L.sub < nn) nb = R[nl.idx[(int64_t)L.sub * st + i]];
+  for (uint32_t k = L.sub; k < nn; k += kSub) {
+    const int64_t e = (int64_t)k * st + i;
     const Rec b = nb;
-    if (k + 1 < nn) nb = R[nl.idx[e + nl.stride]];
+    if (k + kSub < nn) nb = R[nl.idx[e + kSub * st]];
     double vx, vy, vz;
     PairOut o;
     pair_from_records<PREC>(P, g, a, b, step, vx, vy, vz, o);
@@ -498,8 +557,14 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
             0.5 * P.sigma * o.w * o.gdotv * P.sqrt_dt;
     }
   }
-  pv[i] = PV{a.px, a.py, a.pz, ax, ay, az, 0.0, 0.0};
-  if constexpr (SCHEME == 1) deps[i] = de;
+  ax = group_sum(ax);
+  ay = group_sum(ay);
+  az = group_sum(az);
+  if constexpr (SCHEME == 1) de = group_sum(de);
+  if (L.sub == 0) {
+    pv[i] = PV{a.px, a.py, a.pz, ax, ay, az, 0.0, 0.0};
+    if constexpr (SCHEME == 1) deps[i] = de;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -524,9 +589,10 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
     const uint64_t* __restrict__ d_step, const PV* __restrict__ pv, int eos_inline,
     Rec* __restrict__ out, uint32_t* status) {
-  const int64_t i = tile_index();
-  if (i >= n) return;
+  const Lanes L = lanes();
+  if (L.i >= n) return;  // uniform in the group
   if (status_set(status)) return;
+  const int64_t i = L.i;
   const uint64_t step = *d_step;
   const Rec* __restrict__ R = s.r;
   const Rec a = R[i];
@@ -534,16 +600,17 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
   const PV di = pv[i];
   const double vxi = a.px * P.inv_mass, vyi = a.py * P.inv_mass, vzi = a.pz * P.inv_mass;
   const uint32_t nn = nl.count[i];
+  const int64_t st = nl.stride;
   double de = 0.0;
-  uint32_t jn = nn > 0 ? nl.idx[i] : 0u;
+  uint32_t jn = (uint32_t)L.sub < nn ? nl.idx[(int64_t)L.sub * st + i] : 0u;
   PV nv;
-  if (nn > 0) nv = pv[jn];
-  for (uint32_t k = 0; k < nn; ++k) {
-    const int64_t e = (int64_t)k * nl.stride + i;
+  if ((uint32_t)L.sub < nn) nv = pv[jn];
+  for (uint32_t k = L.sub; k < nn; k += kSub) {
+    const int64_t e = (int64_t)k * st + i;
     const uint32_t j = jn;
     const PV dj = nv;
-    if (k + 1 < nn) {
-      jn = nl.idx[e + nl.stride];
+    if (k + kSub < nn) {
+      jn = nl.idx[e + kSub * st];
       nv = pv[jn];
     }
     double ex, ey, ez, vx, vy, vz;
@@ -567,6 +634,8 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
     const double uz = vz + (di.dz - dj.dz) * P.inv_2m;
     de += -0.5 * (ex * ux + ey * uy + ez * uz);
   }
+  de = group_sum(de);
+  if (L.sub != 0) return;
   Rec o = a;
   o.px = a.px + di.dx;
   o.py = a.py + di.dy;
