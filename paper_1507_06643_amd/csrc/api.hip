@@ -79,7 +79,8 @@ struct dpde_handle {
   SkinList skin{};
   bool regen = false;  // regenerate the noise in sweep 2 instead of storing dp_ij
   double *Fx = nullptr, *Fy = nullptr, *Fz = nullptr;
-  PV* pv = nullptr;
+  Vec4* dpi = nullptr;  // dp_i of SER sweep 1
+  Vec4* hv = nullptr;   // (p_i + dp_i/2) / m
   double* deps = nullptr;
   uint32_t* idk = nullptr;
   double* Ui = nullptr;
@@ -256,7 +257,7 @@ int allocate(dpde_handle* h) {
   const int64_t n = h->n;
   if ((rc = alloc_pstate(h, h->cur)) || (rc = alloc_pstate(h, h->alt))) return rc;
   if ((rc = dalloc(h, &h->Fx, n)) || (rc = dalloc(h, &h->Fy, n)) || (rc = dalloc(h, &h->Fz, n)) ||
-      (rc = dalloc(h, &h->pv, n)) || (rc = dalloc(h, &h->deps, n)) || (rc = dalloc(h, &h->Ui, n)) ||
+      (rc = dalloc(h, &h->dpi, n)) || (rc = dalloc(h, &h->hv, n)) || (rc = dalloc(h, &h->deps, n)) || (rc = dalloc(h, &h->Ui, n)) ||
       (rc = dalloc(h, &h->idk, n)))
     return rc;
   if ((rc = dalloc(h, &h->key, n)) || (rc = dalloc(h, &h->ticket, n)) ||
@@ -391,18 +392,20 @@ void enqueue_fd_t(dpde_handle* h) {
   const int store = h->regen ? 0 : 1;
   if (h->phys.scheme == DPDE_SCHEME_SEM) {
     launch(h, "pass_b_sem", k_pass_b<B, PR, 1>, blocks(n * kSub, b), b, h->cur, h->nl, n,
-           (const Geo*)h->geo, h->phys, d_step, h->pv, h->deps, 0, h->status);
+           (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, 0, h->status);
     launch(h, "apply_sem", k_apply_sem, blocks(n, h->aux_block), h->aux_block, h->cur, n, h->phys,
-           (const PV*)h->pv, (const double*)h->deps, inl, h->alt.r, h->status);
+           (const Vec4*)h->dpi, (const double*)h->deps, inl, h->alt.r, h->status);
   } else {
     launch(h, "pass_b_ser", k_pass_b<B, PR, 0>, blocks(n * kSub, b), b, h->cur, h->nl, n,
-           (const Geo*)h->geo, h->phys, d_step, h->pv, h->deps, store, h->status);
+           (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, store, h->status);
     if (h->regen)
       launch(h, "pass_c_ser", k_pass_c<B, PR, 1>, blocks(n * kSub, b), b, h->cur, h->nl, n,
-             (const Geo*)h->geo, h->phys, d_step, (const PV*)h->pv, inl, h->alt.r, h->status);
+             (const Geo*)h->geo, h->phys, d_step, (const Vec4*)h->dpi, (const Vec4*)h->hv, inl,
+             h->alt.r, h->status);
     else
       launch(h, "pass_c_ser", k_pass_c<B, PR, 0>, blocks(n * kSub, b), b, h->cur, h->nl, n,
-             (const Geo*)h->geo, h->phys, d_step, (const PV*)h->pv, inl, h->alt.r, h->status);
+             (const Geo*)h->geo, h->phys, d_step, (const Vec4*)h->dpi, (const Vec4*)h->hv, inl,
+             h->alt.r, h->status);
   }
   // the updated records were written to the spare record array: swap them in
   // (one swap per step, so two steps restore the starting layout, which is

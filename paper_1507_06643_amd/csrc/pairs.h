@@ -34,10 +34,11 @@ struct alignas(32) DP {
 
 // Momentum after the conservative half-kick and the sweep-1 increment of one
 // particle, packed so that sweep 2 gathers one line per neighbour.
-struct alignas(64) PV {
-  double px, py, pz;
-  double dx, dy, dz;
-  double pad0, pad1;
+// Per-particle results of SER sweep 1: dp_i = sum_j dp_ij, and
+// h_i = (p_i + dp_i / 2) / m, so that the velocity combination of sweep 2,
+// v_ij + (dp_i - dp_j)/(2m), is h_i - h_j (exactly antisymmetric).
+struct alignas(32) Vec4 {
+  double x, y, z, w;
 };
 
 // Neighbour list: k-major (entry k of particle i at k*n + i), so the lanes of
@@ -519,8 +520,8 @@ __device__ __forceinline__ void pair_from_records(const Phys& P, const Geo& g, c
 template <bool BATCH, int PREC, int SCHEME>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
-    const uint64_t* __restrict__ d_step, PV* __restrict__ pv, double* __restrict__ deps,
-    int store, uint32_t* status) {
+    const uint64_t* __restrict__ d_step, Vec4* __restrict__ dpi, Vec4* __restrict__ hv,
+    double* __restrict__ deps, int store, uint32_t* status) {
   const Lanes L = lanes();
   if (L.i >= n) return;  // uniform in the group
   if (status_set(status)) return;
@@ -562,7 +563,9 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
   az = group_sum(az);
   if constexpr (SCHEME == 1) de = group_sum(de);
   if (L.sub == 0) {
-    pv[i] = PV{a.px, a.py, a.pz, ax, ay, az, 0.0, 0.0};
+    dpi[i] = Vec4{ax, ay, az, 0.0};
+    hv[i] = Vec4{fma(ax, P.inv_2m, a.px * P.inv_mass), fma(ay, P.inv_2m, a.py * P.inv_mass),
+                 fma(az, P.inv_2m, a.pz * P.inv_mass), 0.0};
     if constexpr (SCHEME == 1) deps[i] = de;
   }
 }
@@ -587,8 +590,8 @@ __device__ __forceinline__ double inv_temperature(const Phys& P, double eps, uin
 template <bool BATCH, int PREC, int REGEN>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
-    const uint64_t* __restrict__ d_step, const PV* __restrict__ pv, int eos_inline,
-    Rec* __restrict__ out, uint32_t* status) {
+    const uint64_t* __restrict__ d_step, const Vec4* __restrict__ dpi,
+    const Vec4* __restrict__ hv, int eos_inline, Rec* __restrict__ out, uint32_t* status) {
   const Lanes L = lanes();
   if (L.i >= n) return;  // uniform in the group
   if (status_set(status)) return;
@@ -597,25 +600,32 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
   const Rec* __restrict__ R = s.r;
   const Rec a = R[i];
   const Geo& g = geo[BATCH ? a.rep : 0u];
-  const PV di = pv[i];
-  const double vxi = a.px * P.inv_mass, vyi = a.py * P.inv_mass, vzi = a.pz * P.inv_mass;
+  const Vec4 di = dpi[i];
+  const Vec4 hi = hv[i];
   const uint32_t nn = nl.count[i];
   const int64_t st = nl.stride;
   double de = 0.0;
   uint32_t jn = (uint32_t)L.sub < nn ? nl.idx[(int64_t)L.sub * st + i] : 0u;
-  PV nv;
-  if ((uint32_t)L.sub < nn) nv = pv[jn];
+  double hx = 0.0, hy = 0.0, hz = 0.0;
+  if ((uint32_t)L.sub < nn) {
+    hx = hv[jn].x;
+    hy = hv[jn].y;
+    hz = hv[jn].z;
+  }
   for (uint32_t k = L.sub; k < nn; k += kSub) {
     const int64_t e = (int64_t)k * st + i;
     const uint32_t j = jn;
-    const PV dj = nv;
+    const double ux = hi.x - hx, uy = hi.y - hy, uz = hi.z - hz;
     if (k + kSub < nn) {
       jn = nl.idx[e + kSub * st];
-      nv = pv[jn];
+      hx = hv[jn].x;
+      hy = hv[jn].y;
+      hz = hv[jn].z;
     }
-    double ex, ey, ez, vx, vy, vz;
+    double ex, ey, ez;
     if constexpr (REGEN) {
       const Rec b = R[j];
+      double vx, vy, vz;
       PairOut o;
       pair_from_records<PREC>(P, g, a, b, step, vx, vy, vz, o);
       ex = o.dp[0];
@@ -625,21 +635,15 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
       ex = nl.dex[e];
       ey = nl.dey[e];
       ez = nl.dez[e];
-      vx = vxi - dj.px * P.inv_mass;
-      vy = vyi - dj.py * P.inv_mass;
-      vz = vzi - dj.pz * P.inv_mass;
     }
-    const double ux = vx + (di.dx - dj.dx) * P.inv_2m;
-    const double uy = vy + (di.dy - dj.dy) * P.inv_2m;
-    const double uz = vz + (di.dz - dj.dz) * P.inv_2m;
     de += -0.5 * (ex * ux + ey * uy + ez * uz);
   }
   de = group_sum(de);
   if (L.sub != 0) return;
   Rec o = a;
-  o.px = a.px + di.dx;
-  o.py = a.py + di.dy;
-  o.pz = a.pz + di.dz;
+  o.px = a.px + di.x;
+  o.py = a.py + di.y;
+  o.pz = a.pz + di.z;
   const double e = s.eps[i] + de;
   s.eps[i] = e;
   if (!(e > 0.0)) {
@@ -651,17 +655,17 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
 }
 
 // SEM: apply dp and d eps (both from pass B), then the next 1/T_i.
-__global__ void k_apply_sem(PState s, int64_t n, Phys P, const PV* __restrict__ pv,
+__global__ void k_apply_sem(PState s, int64_t n, Phys P, const Vec4* __restrict__ dpi,
                             const double* __restrict__ deps, int eos_inline,
                             Rec* __restrict__ out, uint32_t* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (status_set(status)) return;
   Rec o = s.r[i];
-  const PV d = pv[i];
-  o.px += d.dx;
-  o.py += d.dy;
-  o.pz += d.dz;
+  const Vec4 d = dpi[i];
+  o.px += d.x;
+  o.py += d.y;
+  o.pz += d.z;
   const double e = s.eps[i] + deps[i];
   s.eps[i] = e;
   if (!(e > 0.0)) {
