@@ -28,6 +28,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one lane-operation per lane per clock; FP64 FMA counts once)
+ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# Algorithmic VALU lane-operations of one directed SER pair term of sweep 1,
+# counted from the formulas as implemented: Philox-4x32-10 45 (two 32x32->64
+# products and two three-way xors per round), FP64 Box-Muller 173 (two
+# logarithms 38 each, two square roots 8 each, two sine/cosine pairs 36 each,
+# uniforms and products 9), pair geometry, weight and increment 63,
+# accumulation 3
+PAIR_TERM_LANE_OPS = 284
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 N_1M = 1_048_576
 
@@ -190,10 +200,9 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "learned_eos_n1m_traffic.txt")
 KERNEL_SOURCES = ["common.h", "bin.h", "pairs.h", "eos.h", "mlp.h", "api.hip"]
 
 
-def counter_traffic(kernel_prefix):
-    """HBM bytes per launch (read, write) of a kernel from the committed
-    rocprofv3 counter summary, or None when the kernel sources have changed
-    since the counters were taken."""
+def _profile_lines():
+    """Lines of the committed counter summary, or None when the kernel
+    sources have changed since the counters were taken."""
     import hashlib
     if not os.path.exists(PROFILE_TRAFFIC):
         return None
@@ -205,11 +214,107 @@ def counter_traffic(kernel_prefix):
     sha = [l.split()[1] for l in lines if l.startswith("source_sha256")]
     if not sha or sha[0] != h.hexdigest():
         return None
-    for l in lines:
+    return lines
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch (read, write) of a kernel from the committed
+    rocprofv3 counter summary (None if stale)."""
+    lines = _profile_lines()
+    for l in lines or []:
         parts = l.rsplit(" ", 2)
-        if len(parts) == 3 and parts[0].startswith(kernel_prefix):
+        if len(parts) == 3 and parts[0] == kernel:
             return float(parts[1]), float(parts[2])
     return None
+
+
+def counter_valu(kernel):
+    """Issued VALU wave-instructions per launch from the committed summary."""
+    lines = _profile_lines()
+    for l in lines or []:
+        if l.startswith("valu "):
+            name, v = l[5:].rsplit(" ", 1)
+            if name == kernel:
+                return float(v)
+    return None
+
+
+def batched_leg(dp, W, nrep=256, steps=2000, graph_steps=100, tune_steps=10):
+    """Independent replicas of uneven size in one handle, advanced by replays
+    of one captured graph, block sizes chosen by the library's autotuner."""
+    import torch
+    sizes, seeds = W.replica_sizes(nrep, 500, 8000, seed=20260103)
+    cfgs, qs, ps, es = [], [], [], []
+    for r, (nr, sd) in enumerate(zip(sizes, seeds)):
+        L = W.cubic_side(int(nr))
+        q, p, e = W.equilibrium_state(int(nr), [L] * 3, seed=30000 + r)
+        cfgs.append(dp.Config(n=int(nr), box=[L] * 3, dt=0.01, seed=int(sd), replica=r))
+        qs.append(q); ps.append(p); es.append(e)
+    s = dp.System(cfgs, np.concatenate(qs), np.concatenate(ps), np.concatenate(es))
+    pb, ab, tune_ms = s.autotune(tune_steps)
+    s.step_graph(graph_steps, 1)  # capture and warm up
+    s.history()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step_graph(graph_steps, steps // graph_steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    hist = s.history(cap=steps)  # (steps, nrep, 10)
+    drifts = np.array([drift_fit(hist[:, r, 3]) for r in range(nrep)])
+    ntot = int(sizes.sum())
+    s.close()
+    return {"workload": f"{nrep} replicas, N uniform in [500, 8000] (total {ntot}), density 3, "
+                        f"dt=0.01, {steps} steps as {steps // graph_steps} replays of a "
+                        f"{graph_steps}-step graph, FP64",
+            "value": ntot * steps / secs, "unit": "particle-steps/s",
+            "ms_per_step": 1e3 * secs / steps,
+            "autotuned": {"pair_block": pb, "aux_block": ab, "trial_ms_per_step": tune_ms},
+            "drift_per_1e4": [float(drifts.mean()), float(drifts.std(ddof=1) / np.sqrt(nrep))]}
+
+
+def shock_leg(dp, W, steps=5000, graph_steps=100, nslab=20):
+    """Symmetric impact in a 400 x 20 x 20 box (free along x): throughput,
+    energy conservation and the kinetic/internal temperature profiles."""
+    import torch
+    box = (400.0, 20.0, 20.0)
+    q, p, e = W.shock_state(box)
+    n = len(q)
+    cfg = dp.Config(n=n, box=list(box), periodic=(0, 1, 1), dt=0.005, precision=dp.FP32)
+    s = dp.System(cfg, q, p, e)
+    E0 = s.energies()[3]
+    s.step_graph(graph_steps, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step_graph(graph_steps, steps // graph_steps - 1)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    E1 = s.energies()[3]
+    qg, pg, eg, st = s.get_state()
+    qg, pg, eg = qg.cpu().numpy(), pg.cpu().numpy(), eg.cpu().numpy()
+    s.close()
+
+    def profile(qx, pp, ee):
+        edges = np.linspace(0.0, box[0], nslab + 1)
+        idx = np.clip(np.digitize(qx, edges) - 1, 0, nslab - 1)
+        tk, ti, ux = [], [], []
+        for b in range(nslab):
+            m = idx == b
+            if m.sum() < 2:
+                tk.append(None); ti.append(None); ux.append(None)
+                continue
+            v = pp[m] / cfg.mass
+            vbar = v.mean(axis=0)
+            tk.append(float(cfg.mass * ((v - vbar) ** 2).sum() / (3 * (m.sum() - 1))))
+            ti.append(float((ee[m] / cfg.cv).mean()))
+            ux.append(float(vbar[0]))
+        return {"T_kin": tk, "T_int": ti, "u_x": ux}
+    return {"workload": f"shock, N={n}, box 400x20x20 (free along x), +-2 bulk velocity, "
+                        f"dt=0.005, {steps} steps, FP32 pair terms, FP64 energies",
+            "value": n * (steps - graph_steps) / secs, "unit": "particle-steps/s",
+            "ms_per_step": 1e3 * secs / (steps - graph_steps),
+            "energy_rel_change": float((E1 - E0) / abs(E0)), "final_step": int(st),
+            "slabs": nslab, "initial_profile": profile(q[:, 0], p, e),
+            "final_profile": profile(qg[:, 0], pg, eg)}
 
 
 def cpu_baseline(W, n, steps, eos, dt, eps0):
@@ -240,6 +345,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--mlp-iters", type=int, default=3000)
     ap.add_argument("--no-drift", action="store_true", help="skip the energy-drift legs")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the batched-replica and shock legs")
     ap.add_argument("--drift-seeds", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
@@ -295,19 +402,30 @@ def main():
         bpp_k = pair_kernel_bytes(k, nbar, nskin)
         t_k = prof[k]["avg_ms"] * 1e-3
         tr = counter_traffic(symbols[k])
-        pair_roofs[k] = {"avg_launch_ms": prof[k]["avg_ms"], "algorithmic_bytes": bpp_k * n,
-                         "achieved_GBps": bpp_k * n / t_k / 1e9,
-                         "frac": bpp_k * n / t_k / 1e9 / HBM_PEAK_GBS,
-                         "counter_bytes": None if tr is None else tr[0] + tr[1],
-                         "counter_GBps": None if tr is None else (tr[0] + tr[1]) / t_k / 1e9}
+        vi = counter_valu(symbols[k])
+        r = {"avg_launch_ms": prof[k]["avg_ms"], "algorithmic_bytes": bpp_k * n,
+             "hbm_GBps": bpp_k * n / t_k / 1e9, "hbm_frac": bpp_k * n / t_k / 1e9 / HBM_PEAK_GBS,
+             "counter_bytes": None if tr is None else tr[0] + tr[1],
+             "counter_GBps": None if tr is None else (tr[0] + tr[1]) / t_k / 1e9,
+             "issued_valu_frac": None if vi is None else vi * 64 / t_k / ALU_PEAK_LANE_OPS}
+        if k.startswith("pass_b"):
+            ops = PAIR_TERM_LANE_OPS * nbar * n
+            r.update({"algorithmic_lane_ops": ops, "alu_lane_ops_per_s": ops / t_k,
+                      "alu_frac": ops / t_k / ALU_PEAK_LANE_OPS})
+        pair_roofs[k] = r
     dom = max(pair_roofs, key=lambda k: pair_roofs[k]["avg_launch_ms"])
-    bpp = pair_kernel_bytes(dom, nbar, nskin)
-    achieved = pair_roofs[dom]["achieved_GBps"]
-    roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": pair_roofs[dom]["counter_bytes"],
-            "bytes_per_particle": bpp, "mean_neighbours": nbar, "skin_list_estimate": nskin,
-            "avg_launch_ms": prof[dom]["avg_ms"], "pair_kernels": pair_roofs}
+    d = pair_roofs[dom]
+    if "alu_frac" in d:
+        # the sweep-1 kernel is bound by VALU work (counter-measured issue rate)
+        roof = {"kernel": dom, "bound": "alu", "achieved": d["alu_lane_ops_per_s"],
+                "peak": ALU_PEAK_LANE_OPS, "unit": "lane-op/s", "frac": d["alu_frac"],
+                "traffic": d["counter_bytes"], "lane_ops_per_pair_term": PAIR_TERM_LANE_OPS}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": d["hbm_GBps"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": d["hbm_frac"], "traffic": d["counter_bytes"]}
+    roof.update({"bytes_per_particle": pair_kernel_bytes(dom, nbar, nskin),
+                 "mean_neighbours": nbar, "skin_list_estimate": nskin,
+                 "avg_launch_ms": prof[dom]["avg_ms"], "pair_kernels": pair_roofs})
     line = {
         "metric": "particle-steps/s at N=1M",
         "value": value,
@@ -349,6 +467,11 @@ def main():
                               "energy_drift_per_1e4_steps": drift_per_1e4(h2)}
             s2.close()
         line["variants"] = variants
+    if not args.no_legs:
+        log("[bench] batched replicas: 256 systems, one captured graph, autotuned blocks")
+        line["batched_replicas"] = batched_leg(dp, W)
+        log("[bench] shock: N=480000, 5000 steps, FP32 pair terms")
+        line["shock"] = shock_leg(dp, W)
     if not args.no_drift:
         log("[bench] energy drift: GPU vs oracle, N=1000")
         line["drift_vs_oracle"] = drift_vs_oracle(dp, W, list(range(1, args.drift_seeds + 1)))

@@ -206,6 +206,16 @@ int dpde_step_graph(dpde_handle* h, int64_t nsteps, int64_t reps);
 /* Kernel launch shape: block size of the pair passes (64, 128, 256, 512 or 1024). */
 int dpde_set_tuning(dpde_handle* h, int32_t pair_block, int32_t aux_block);
 
+/* Autotuner: time every candidate (pair-kernel block of 64/128/256 threads x
+ * per-particle block of 128/256/512) over `steps` steps of this system and keep
+ * the fastest (applied as by dpde_set_tuning; *ms_per_step = its time).  The
+ * state, step, list-build count and history are restored after every trial,
+ * and results do not depend on the block sizes, so tuning leaves the
+ * trajectory unchanged.  Allocates a snapshot (state and history) for the
+ * duration of the call.  Not for use during graph capture. */
+int dpde_autotune(dpde_handle* h, int32_t steps, int32_t* pair_block, int32_t* aux_block,
+                  double* ms_per_step);
+
 /*
  * Per-kernel timing: when enabled, every kernel launch of dpde_step is
  * bracketed by HIP events on the handle's stream.  dpde_profile_read fills

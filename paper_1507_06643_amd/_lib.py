@@ -83,6 +83,7 @@ SIGNATURES = [
     ("dpde_energies_batch", C.c_int, [_vp, _dp]),
     ("dpde_step_graph", C.c_int, [_vp, _i64, _i64]),
     ("dpde_set_tuning", C.c_int, [_vp, _i32, _i32]),
+    ("dpde_autotune", C.c_int, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i32), _dp]),
     ("dpde_profile_enable", C.c_int, [_vp, _i32]),
     ("dpde_profile_read", C.c_int, [_vp, C.c_char_p, _dp, C.POINTER(_i64), _i32]),
     ("dpde_theta", C.c_int, [_vp, _vp, _vp, _vp, _i64, _i32]),

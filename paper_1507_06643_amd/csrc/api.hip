@@ -738,6 +738,105 @@ int dpde_set_tuning(dpde_handle* h, int32_t pair_block, int32_t aux_block) {
   return DPDE_OK;
 }
 
+int dpde_autotune(dpde_handle* h, int32_t steps, int32_t* pair_block, int32_t* aux_block,
+                  double* ms_per_step) {
+  if (!h) return fail(DPDE_EINVAL, "handle is NULL");
+  if (steps < 1) return fail(DPDE_EINVAL, "steps must be >= 1");
+  // snapshot: state in identifier order, step, list-build count, history
+  const size_t n = (size_t)h->n;
+  const size_t hist_bytes = (size_t)h->hist_cap * h->nrep * 10 * sizeof(double);
+  double *q = nullptr, *p = nullptr, *e = nullptr, *hist = nullptr;
+  auto cleanup = [&]() {
+    if (q) (void)hipFree(q);
+    if (p) (void)hipFree(p);
+    if (e) (void)hipFree(e);
+    if (hist) (void)hipFree(hist);
+  };
+  if (hipMalloc((void**)&q, 3 * n * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&p, 3 * n * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&e, n * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&hist, hist_bytes) != hipSuccess) {
+    cleanup();
+    return fail(DPDE_ENOMEM, "autotune snapshot allocation failed");
+  }
+  int rc = dpde_get_state(h, q, p, e, nullptr);
+  const int64_t step0 = h->step;
+  int64_t hist_count = 0;
+  unsigned long long builds = 0;
+  if (!rc) {
+    if (hipMemcpyAsync(&hist_count, h->d_hist_count, sizeof(int64_t), hipMemcpyDeviceToHost,
+                       h->stream) != hipSuccess ||
+        hipMemcpyAsync(&builds, h->builds, sizeof(builds), hipMemcpyDeviceToHost, h->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(hist, h->hist, hist_bytes, hipMemcpyDeviceToDevice, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      rc = fail(DPDE_EHIP, "autotune snapshot copy failed");
+  }
+  auto restore = [&]() -> int {
+    int r = dpde_set_state(h, q, p, e, step0);
+    if (r) return r;
+    if (hipMemcpyAsync(h->d_hist_count, &hist_count, sizeof(int64_t), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->builds, &builds, sizeof(builds), hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(h->hist, hist, hist_bytes, hipMemcpyDeviceToDevice, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return fail(DPDE_EHIP, "autotune restore copy failed");
+    return DPDE_OK;
+  };
+  static const int32_t kPair[] = {64, 128, 256};
+  static const int32_t kAux[] = {128, 256, 512};
+  const int32_t pb0 = h->pair_block, ab0 = h->aux_block;
+  int32_t best_pb = pb0, best_ab = ab0;
+  double best = 1e300;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (!rc && (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess))
+    rc = fail(DPDE_EHIP, "autotune event creation failed");
+  for (int32_t pb : kPair) {
+    for (int32_t ab : kAux) {
+      if (rc) break;
+      h->pair_block = pb;
+      h->aux_block = ab;
+      enqueue_step(h);  // warm-up (first launch of this shape)
+      (void)hipEventRecord(t0, h->stream);
+      for (int32_t s = 0; s < steps; ++s) enqueue_step(h);
+      (void)hipEventRecord(t1, h->stream);
+      if (hipEventSynchronize(t1) != hipSuccess) {
+        rc = fail(DPDE_EHIP, "autotune timing failed");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, t0, t1);
+      rc = read_status(h);
+      if (rc) break;
+      if (ms / steps < best) {
+        best = ms / steps;
+        best_pb = pb;
+        best_ab = ab;
+      }
+      rc = restore();
+    }
+  }
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  if (rc) {
+    h->pair_block = pb0;
+    h->aux_block = ab0;
+    (void)restore();
+    cleanup();
+    return rc;
+  }
+  cleanup();
+  rc = dpde_set_tuning(h, best_pb, best_ab);
+  if (rc) return rc;
+  if (pair_block) *pair_block = best_pb;
+  if (aux_block) *aux_block = best_ab;
+  if (ms_per_step) *ms_per_step = best;
+  return DPDE_OK;
+}
+
 int dpde_profile_enable(dpde_handle* h, int32_t enable) {
   if (!h) return fail(DPDE_EINVAL, "handle is NULL");
   h->profiling = enable != 0;

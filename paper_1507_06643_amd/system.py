@@ -127,6 +127,12 @@ class System:
     def set_tuning(self, pair_block: int, aux_block: int = 256):
         L.check(self._lib.dpde_set_tuning(self.h, int(pair_block), int(aux_block)))
 
+    def autotune(self, steps: int = 20):
+        """Pick the fastest block sizes (state restored); returns (pair, aux, ms/step)."""
+        pb, ab, ms = C.c_int32(0), C.c_int32(0), C.c_double(0.0)
+        L.check(self._lib.dpde_autotune(self.h, int(steps), C.byref(pb), C.byref(ab), C.byref(ms)))
+        return pb.value, ab.value, ms.value
+
     @property
     def stream_ptr(self) -> int:
         return self._lib.dpde_stream(self.h) or 0

@@ -334,3 +334,37 @@ def test_full_size_one_step_parity(dp):
     assert max(eq, ep, ee) < 1e-12, (eq, ep, ee)
     assert abs(en[3] - eo[3]) < 1e-12 * abs(eo[3])
     assert abs(en[8] - eo[8]) < 1e-12 * abs(eo[8])
+
+
+# ---------------------------------------------------------------------------
+# Autotuner: candidates are timed on the live system and the state restored;
+# block sizes do not enter the arithmetic, so the trajectory is unchanged.
+# ---------------------------------------------------------------------------
+def test_autotune_leaves_trajectory_unchanged(dp):
+    n = 6000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=91)
+    a = dp.System(dp.Config(n=n, box=[L] * 3), q, p, e)
+    b = dp.System(dp.Config(n=n, box=[L] * 3), q, p, e)
+    a.step(5)
+    b.step(5)
+    ha = a.history()
+    hb = b.history()
+    builds = b.list_builds()
+    pb, ab, ms = b.autotune(3)
+    assert pb in (64, 128, 256) and ab in (128, 256, 512) and ms > 0
+    assert b.list_builds() == builds
+    assert b.history().shape[0] == 0  # trial records were rolled back
+    a.step(25)
+    b.step(25)
+    sa, sb = a.get_state(), b.get_state()
+    for x, y in zip(sa[:3], sb[:3]):
+        assert torch_equal(x, y)
+    assert sa[3] == sb[3] == 30
+    assert np.array_equal(a.history(), b.history())
+    a.close()
+    b.close()
+
+
+def torch_equal(x, y):
+    return bool((x == y).all().item())
