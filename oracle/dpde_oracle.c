@@ -20,8 +20,10 @@
  *    balances the internal-energy equation of eq. (DPDE));
  *  - the SER internal-energy update carries the factor -1/2 of
  *    eq. (SER_eint_discretization); the summary eq. (SER_fd) drops it;
- *  - the conservative force is the soft DPD force a(1-r/rc) r_hat with
- *    potential (a rc/2)(1-r/rc)^2 (the paper's own runs use a splined LJ);
+ *  - the conservative force is by default the soft DPD force a(1-r/rc) r_hat
+ *    with potential (a rc/2)(1-r/rc)^2; the paper's splined LJ (eq. Ep) is the
+ *    other choice, with its cut-off rc supplied by the caller (the paper
+ *    does not state it);
  *  - the Gaussian increments G_ij^n come from Philox-4x32-10 (Salmon et al.,
  *    SC'11) keyed by (seed, replica) with counter (lo id, hi id, n), followed
  *    by Box-Muller; the paper only requires that G_ij^n be a function of
@@ -56,6 +58,13 @@ typedef struct {
   int32_t eos;       /* 0: eps = cv*theta ; 1: eps = n w/(exp(w/theta)-1) + c0 theta */
   int32_t replica;
   int32_t scheme;    /* 0: SER (Sec. 3.2.1) ; 1: SEM (Sec. 3.1.1) */
+  int32_t project;   /* 1: eps_i -= (E - E0)/N after every step (Sec. 4.2) */
+  int32_t model;     /* 0: friction/noise along v_ij (eq. DPDE, the paper's variant);
+                        1: projected on e_ij (the original DPDE model, Sec. 2.1) */
+  int32_t potential; /* 0: soft v = (a rc/2)(1-r/rc)^2 ; 1: splined LJ (eq. Ep) */
+  int32_t pad_;
+  double E0;         /* target energy of the projection */
+  double eps_lj, r_lj;
 } or_params;
 
 /* ------------------------------------------------------------------------
@@ -266,6 +275,37 @@ static int build_pairs(const or_params* P, const double* q, int32_t** out, int64
  * (eq. def_potential_energy with this v).  A coincident pair (r = 0) has no
  * direction and contributes v(0) to U and nothing to the forces.
  * ---------------------------------------------------------------------- */
+/* Pair potential v(r) and its first two derivatives, r < rc.
+ *   potential 0: v = (a rc/2)(1 - r/rc)^2, v' = -a (1 - r/rc), v'' = a/rc;
+ *   potential 1 (eq. Ep): v = v_LJ(r) - v_LJ(rc) - v_LJ'(rc)(r - rc) with
+ *     v_LJ = 4 eps_lj ((r_lj/r)^12 - (r_lj/r)^6), so that v(rc) = v'(rc) = 0.
+ */
+static void lj_terms(const or_params* P, double r, double* v, double* dv, double* d2v) {
+  double s6 = pow(P->r_lj / r, 6.0);
+  double s12 = s6 * s6;
+  *v = 4.0 * P->eps_lj * (s12 - s6);
+  *dv = -24.0 * P->eps_lj * (2.0 * s12 - s6) / r;
+  *d2v = 4.0 * P->eps_lj * (156.0 * s12 - 42.0 * s6) / (r * r);
+}
+
+void or_pair_potential(const or_params* P, double r, double* v, double* dv, double* d2v) {
+  if (P->potential == 1) {
+    double vc, dvc, d2vc;
+    lj_terms(P, P->rc, &vc, &dvc, &d2vc);
+    lj_terms(P, r, v, dv, d2v);
+    *v = *v - vc - dvc * (r - P->rc);
+    *dv = *dv - dvc;
+  } else {
+    double w = 1.0 - r / P->rc;
+    *v = 0.5 * P->a * P->rc * w * w;
+    *dv = -P->a * w;
+    *d2v = P->a / P->rc;
+  }
+}
+
+/* Conservative forces F_i = -grad_i U with U = sum_{i<j} v(r_ij)
+ * (eq. def_potential_energy).  A coincident pair (r = 0) contributes its
+ * energy but no force. */
 void or_forces_pairs(const or_params* P, const double* q, const int32_t* lohi, int64_t npairs,
                      double* F, double* U) {
   memset(F, 0, sizeof(double) * 3 * (size_t)P->n);
@@ -275,18 +315,36 @@ void or_forces_pairs(const or_params* P, const double* q, const int32_t* lohi, i
     double d[3];
     double r2 = separation(P, &q[3 * i], &q[3 * j], d);
     double r = sqrt(r2);
-    double w = 1.0 - r / P->rc;
-    u += 0.5 * P->a * P->rc * w * w;
-    if (r > 0.0) {
-      for (int c = 0; c < 3; ++c) {
-        double f = P->a * w * d[c] / r;
-        F[3 * i + c] += f;
-        F[3 * j + c] -= f;
+    if (P->potential == 0) {
+      double w = 1.0 - r / P->rc;
+      u += 0.5 * P->a * P->rc * w * w;
+      if (r > 0.0) {
+        for (int c = 0; c < 3; ++c) {
+          double f = P->a * w * d[c] / r;
+          F[3 * i + c] += f;
+          F[3 * j + c] -= f;
+        }
+      }
+    } else {
+      double v, dv, d2v;
+      or_pair_potential(P, r, &v, &dv, &d2v);
+      u += v;
+      if (r > 0.0) {
+        for (int c = 0; c < 3; ++c) {
+          double f = -dv * d[c] / r;
+          F[3 * i + c] += f;
+          F[3 * j + c] -= f;
+        }
       }
     }
   }
   *U = u;
 }
+
+/* Ingredients of the configurational temperature (eq. Tcon):
+ * |grad U|^2 = sum_i |F_i|^2 and Delta U = sum_i Laplacian_{q_i} U
+ *            = 2 sum_{i<j} (v''(r) + (d-1) v'(r)/r), d = 3. */
+int or_config_temperature(const or_params* P, const double* q, double* grad2, double* lap);
 
 int or_forces(const or_params* P, const double* q, double* F, double* U) {
   int32_t* pairs = NULL;
@@ -369,6 +427,14 @@ int or_inv_temperature(const or_params* P, const double* eps, double* invT) {
  * internal-energy update
  *   d eps_i = 1/2 sum_j (gamma_ij v_ij^2 - d sigma^2/m) chi dt
  *           - 1/2 sum_j sigma w v_ij . G_ij sqrt(dt).
+ * Model 1 (the original DPDE model with friction and noise along
+ * e_ij = (q_i - q_j)/r_ij, Sec. 2.1) replaces v_ij by (e_ij . v_ij) e_ij and
+ * G_ij by xi_ij e_ij with one scalar normal xi_ij (the first of the three):
+ *   dp_ij = (-gamma_ij chi (e_ij . v_ij) dt + sigma w xi_ij sqrt(dt)) e_ij,
+ * the same reinjection for SER, and for SEM
+ *   d eps_i = 1/2 sum_j (gamma_ij (e_ij . v_ij)^2 - sigma^2/m) chi dt
+ *           - 1/2 sum_j sigma w (e_ij . v_ij) xi_ij sqrt(dt).
+ * A coincident pair (r = 0) has no direction and no interaction in model 1.
  * ---------------------------------------------------------------------- */
 int or_fd_pairs(const or_params* P, const double* q, double* p, double* eps,
                 const int32_t* lohi, int64_t npairs, double* dp_out) {
@@ -393,9 +459,31 @@ int or_fd_pairs(const or_params* P, const double* q, double* p, double* eps,
     double gij = 0.5 * P->gamma * P->kT_ref * (invT[i] + invT[j]);
     double G[3];
     or_gauss3(P->seed, (uint32_t)P->replica, P->step, (uint32_t)i, (uint32_t)j, G);
+    double vij[3];
+    for (int c = 0; c < 3; ++c) vij[c] = p[3 * i + c] / P->mass - p[3 * j + c] / P->mass;
+    if (P->model == 1) {
+      double e[3] = {0.0, 0.0, 0.0};
+      if (r > 0.0)
+        for (int c = 0; c < 3; ++c) e[c] = d[c] / r;
+      double ev = e[0] * vij[0] + e[1] * vij[1] + e[2] * vij[2];
+      double xi = G[0];
+      double mag = -gij * chi * ev * P->dt + sigma * w * xi * sqdt;
+      for (int c = 0; c < 3; ++c) {
+        double v = mag * e[c];
+        dpij[3 * k + c] = v;
+        dp[3 * i + c] += v;
+        dp[3 * j + c] -= v;
+      }
+      if (P->scheme == 1 && r > 0.0) {
+        double de = 0.5 * (gij * ev * ev - sigma * sigma / P->mass) * chi * P->dt
+                  - 0.5 * sigma * w * ev * xi * sqdt;
+        deps[i] += de;
+        deps[j] += de;
+      }
+      continue;
+    }
     for (int c = 0; c < 3; ++c) {
-      double vij = p[3 * i + c] / P->mass - p[3 * j + c] / P->mass;
-      double v = -gij * chi * vij * P->dt + sigma * w * G[c] * sqdt;
+      double v = -gij * chi * vij[c] * P->dt + sigma * w * G[c] * sqdt;
       dpij[3 * k + c] = v;
       dp[3 * i + c] += v;
       dp[3 * j + c] -= v;
@@ -403,9 +491,8 @@ int or_fd_pairs(const or_params* P, const double* q, double* p, double* eps,
     if (P->scheme == 1) {
       double vsq = 0.0, vG = 0.0;
       for (int c = 0; c < 3; ++c) {
-        double vij = p[3 * i + c] / P->mass - p[3 * j + c] / P->mass;
-        vsq += vij * vij;
-        vG += vij * G[c];
+        vsq += vij[c] * vij[c];
+        vG += vij[c] * G[c];
       }
       double e = 0.5 * (gij * vsq - 3.0 * sigma * sigma / P->mass) * chi * P->dt
                - 0.5 * sigma * w * vG * sqdt;
@@ -476,6 +563,20 @@ int or_step(or_params* P, double* q, double* p, double* eps, double* F, double* 
   rc_ = or_fd_pairs(P, q, p, eps, pairs, np, NULL);
   free(pairs);
   P->step += 1;
+  if (rc_ == OR_OK && P->project) {
+    /* Sec. 4.2: eps_i <- eps_i - (E(x~) - E0)/N, x~ the unconstrained update */
+    double K = 0.0, S = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      K += (p[3 * i] * p[3 * i] + p[3 * i + 1] * p[3 * i + 1] + p[3 * i + 2] * p[3 * i + 2]) /
+           (2.0 * P->mass);
+      S += eps[i];
+    }
+    double shift = (*U + K + S - P->E0) / (double)n;
+    for (int64_t i = 0; i < n; ++i) {
+      eps[i] -= shift;
+      if (!(eps[i] > 0.0)) rc_ = OR_ENEG_EINT;
+    }
+  }
   return rc_;
 }
 
@@ -521,7 +622,33 @@ int or_run(or_params* P, double* q, double* p, double* eps, double* F, double* U
   return OR_OK;
 }
 
-/* Projection on the internal energies (Sec. 4.3): eps_i -= (E - E0)/N. */
+int or_config_temperature(const or_params* P, const double* q, double* grad2, double* lap) {
+  int32_t* pairs = NULL;
+  int64_t np = 0;
+  int rc_ = build_pairs(P, q, &pairs, &np);
+  if (rc_ != OR_OK) return rc_;
+  double* F = (double*)malloc(sizeof(double) * 3 * (size_t)P->n);
+  if (!F) { free(pairs); return OR_ENOMEM; }
+  double U;
+  or_forces_pairs(P, q, pairs, np, F, &U);
+  double g = 0.0, l = 0.0;
+  for (int64_t i = 0; i < 3 * P->n; ++i) g += F[i] * F[i];
+  for (int64_t k = 0; k < np; ++k) {
+    double d[3];
+    double r = sqrt(separation(P, &q[3 * pairs[2 * k]], &q[3 * pairs[2 * k + 1]], d));
+    if (!(r > 0.0)) continue;
+    double v, dv, d2v;
+    or_pair_potential(P, r, &v, &dv, &d2v);
+    l += 2.0 * (d2v + 2.0 * dv / r);
+  }
+  free(F);
+  free(pairs);
+  *grad2 = g;
+  *lap = l;
+  return OR_OK;
+}
+
+/* Projection on the internal energies (Sec. 4.2): eps_i -= (E - E0)/N. */
 void or_project(const or_params* P, double* eps, double E, double E0) {
   double shift = (E - E0) / (double)P->n;
   for (int64_t i = 0; i < P->n; ++i) eps[i] -= shift;

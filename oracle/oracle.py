@@ -27,6 +27,9 @@ class OrParams(C.Structure):
         ("n", C.c_int64), ("step", C.c_int64), ("seed", C.c_uint64),
         ("periodic", C.c_int32 * 3),
         ("eos", C.c_int32), ("replica", C.c_int32), ("scheme", C.c_int32),
+        ("project", C.c_int32), ("model", C.c_int32), ("potential", C.c_int32),
+        ("pad_", C.c_int32),
+        ("E0", C.c_double), ("eps_lj", C.c_double), ("r_lj", C.c_double),
     ]
 
 
@@ -70,6 +73,8 @@ def lib():
         L.or_run.argtypes = [P, dp, dp, dp, dp, dp, C.c_int64, dp]
         L.or_energies.argtypes = [P, dp, dp, C.c_double, dp]
         L.or_project.argtypes = [P, dp, C.c_double, C.c_double]
+        L.or_pair_potential.argtypes = [P, C.c_double, dp, dp, dp]
+        L.or_config_temperature.argtypes = [P, dp, dp, dp]
         L.or_mlp_nparam.restype = C.c_int
         L.or_mlp_forward.argtypes = [dp, dp, dp, C.c_int64]
         L.or_mlp_loss_grad.argtypes = [dp, dp, dp, C.c_int64, dp]
@@ -84,7 +89,8 @@ def _d(a):
 
 def make_params(n, box, *, periodic=(1, 1, 1), mass=1.0, rc=1.0, a=25.0, gamma=4.5, kT_ref=1.0,
                 dt=0.01, eos=0, cv=100.0, eos_n=50.0, eos_omega=2.0, eos_c0=10.0, seed=7, step=0,
-                replica=0, scheme=0) -> OrParams:
+                replica=0, scheme=0, project=0, E0=0.0, model=0, potential=0, eps_lj=1.0,
+                r_lj=1.0) -> OrParams:
     P = OrParams()
     P.box = (C.c_double * 3)(*[float(x) for x in box])
     P.mass, P.rc, P.a, P.gamma, P.kT_ref, P.dt = mass, rc, a, gamma, kT_ref, dt
@@ -92,6 +98,8 @@ def make_params(n, box, *, periodic=(1, 1, 1), mass=1.0, rc=1.0, a=25.0, gamma=4
     P.n, P.step, P.seed = int(n), int(step), int(seed)
     P.periodic = (C.c_int32 * 3)(*[int(x) for x in periodic])
     P.eos, P.replica, P.scheme = int(eos), int(replica), int(scheme)
+    P.project, P.model, P.potential = int(project), int(model), int(potential)
+    P.E0, P.eps_lj, P.r_lj = float(E0), float(eps_lj), float(r_lj)
     return P
 
 
@@ -166,7 +174,9 @@ def fd(P, q, p, eps):
 
 
 class State:
-    """Oracle trajectory state in ID order (q, p, eps, F, U, step)."""
+    """Oracle trajectory state in ID order (q, p, eps, F, U, step).  With
+    P.project set, the target energy E0 of the projection is the energy of the
+    initial state (Sec. 4.2)."""
 
     def __init__(self, P, q, p, eps):
         self.P = P
@@ -174,6 +184,8 @@ class State:
         self.p = np.array(p, dtype=np.float64, copy=True)
         self.eps = np.array(eps, dtype=np.float64, copy=True)
         self.F, self.U = forces(P, self.q)
+        if P.project:
+            P.E0 = self.energies()[3]
 
     def step(self, nsteps=1, record=False):
         rec = np.zeros((nsteps, 10)) if record else None
@@ -188,6 +200,21 @@ class State:
         check(lib().or_energies(C.byref(self.P), _d(self.p), _d(self.eps), C.c_double(self.U),
                                 _d(out)), "energies")
         return out
+
+
+def pair_potential(P, r):
+    """(v, v', v'') of the pair potential at distance r."""
+    v, dv, d2v = C.c_double(), C.c_double(), C.c_double()
+    lib().or_pair_potential(C.byref(P), float(r), C.byref(v), C.byref(dv), C.byref(d2v))
+    return v.value, dv.value, d2v.value
+
+
+def config_temperature_terms(P, q):
+    """(|grad U|^2, Laplacian of U) for the configurational temperature."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    g, l = C.c_double(), C.c_double()
+    check(lib().or_config_temperature(C.byref(P), _d(q), C.byref(g), C.byref(l)), "config T")
+    return g.value, l.value
 
 
 def energies(P, p, eps, U):
