@@ -259,7 +259,7 @@ def batched_leg(dp, W, nrep=256, steps=2000, graph_steps=100, tune_steps=10):
     s.step_graph(graph_steps, steps // graph_steps)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    hist = s.history(cap=steps)  # (steps, nrep, 10)
+    hist = s.history(cap=steps)  # (steps, nrep, record)
     drifts = np.array([drift_fit(hist[:, r, 3]) for r in range(nrep)])
     ntot = int(sizes.sum())
     s.close()

@@ -65,12 +65,26 @@ extern "C" {
 #define DPDE_SCHEME_SER 0    /* Sec. 3.2.1, eqs. SER_p, SER_eint_discretization   */
 #define DPDE_SCHEME_SEM 1    /* Sec. 3.1.1, eq. SEM_fd (not energy conserving)    */
 
+/* Direction of friction and noise (Sec. 2.1). */
+#define DPDE_MODEL_VECTOR 0  /* along v_ij with a 3-d Gaussian G_ij (eq. DPDE,    */
+                             /* the paper's variant)                              */
+#define DPDE_MODEL_PROJECTED 1 /* along e_ij = (q_i - q_j)/r_ij with one scalar   */
+                             /* normal xi_ij = xi_ji per pair (the original DPDE  */
+                             /* model); SEM then uses the Ito term sigma^2/m      */
+
+/* Conservative pair potential v(r), r < rc. */
+#define DPDE_POT_SOFT 0      /* (a rc/2)(1 - r/rc)^2, force a (1 - r/rc) r_hat    */
+#define DPDE_POT_LJ 1        /* eq. Ep: 4 eps_lj((r_lj/r)^12 - (r_lj/r)^6) shifted */
+                             /* and splined so that v(rc) = v'(rc) = 0            */
+
+/* Length of one observable record (dpde_energies, dpde_history). */
+#define DPDE_REC_LEN 12
+
 /*
  * Parameters of one system.  Sigma is derived: sigma = sqrt(2 gamma kT_ref)
  * (eq. alternative_FDR), gamma_ij = (gamma kT_ref / 2)(1/T_i + 1/T_j)
- * (eq. DPDE_fd).  Conservative pair force a (1 - r/rc) r_hat, potential
- * (a rc / 2)(1 - r/rc)^2; dissipation weight chi(r) = (1 - r/rc)^2 for r < rc
- * (eq. pot_mou).  The box is [0,box[d]) along each dimension; a periodic
+ * (eq. DPDE_fd).  Conservative pair potential by `potential`; dissipation
+ * weight chi(r) = (1 - r/rc)^2 for r < rc (eq. pot_mou).  The box is [0,box[d]) along each dimension; a periodic
  * dimension wraps positions and uses the minimum image, a non-periodic one
  * has free boundaries (its cell index is clamped to the box).
  */
@@ -85,6 +99,7 @@ typedef struct dpde_params {
   double dt;            /* timestep > 0                                         */
   double cv;            /* heat capacity of the linear EOS                      */
   double eos_n, eos_omega, eos_c0; /* Einstein EOS parameters                   */
+  double eps_lj, r_lj;  /* LJ well depth and length (DPDE_POT_LJ)               */
   double skin;          /* neighbour-list skin >= 0: lists hold pairs within    */
                         /* rc + skin and are rebuilt once some particle has     */
                         /* moved more than skin/2 since the last build; the     */
@@ -96,6 +111,8 @@ typedef struct dpde_params {
   int32_t precision;    /* DPDE_FP64 or DPDE_FP32                               */
   int32_t theta_mode;   /* DPDE_THETA_*                                         */
   int32_t scheme;       /* DPDE_SCHEME_*                                        */
+  int32_t model;        /* DPDE_MODEL_*                                         */
+  int32_t potential;    /* DPDE_POT_*                                           */
   uint32_t replica;     /* folded into the noise key (seed_hi ^ replica)        */
   int32_t neighbor_cap; /* list capacity per particle (0: 64, or 96 with skin)  */
   int32_t flags;        /* DPDE_FLAG_* bits                                     */
@@ -107,6 +124,12 @@ typedef struct dpde_params {
  * per neighbour of HBM traffic for the noise generation).  Results are
  * identical bit for bit either way. */
 #define DPDE_FLAG_REGENERATE_NOISE 1
+/* flags: after every step replace eps_i by eps_i - (E - E0)/N, E the energy of
+ * the unconstrained update and E0 that of the state given to dpde_init or
+ * dpde_set_state (per replica), so that the total energy stays E0
+ * (Sec. 4.2).  The records then report the projected state.  A step whose
+ * projection makes some eps_i <= 0 fails with DPDE_ENEG_EINT. */
+#define DPDE_FLAG_PROJECT_EINT 2
 
 typedef struct dpde_handle dpde_handle;
 
@@ -135,19 +158,22 @@ int dpde_init(const dpde_params* params, const double* q, const double* p, const
 int dpde_step(dpde_handle* h, int64_t nsteps);
 
 /*
- * Observables of the current state into host out[10]:
+ * Observables of the current state into host out[DPDE_REC_LEN]:
  *   U, K = sum p^2/(2m), sum eps, E = U + K + sum eps, P_x, P_y, P_z,
- *   T_kin = sum p^2/m / (3(N-1)), T_int = N / sum 1/T_i, n (step counter)
- * (energy of Sec. 2.1 with the kinetic term p^2/(2m); eqs. Tkin, Tint).
- * FP64 sums in a fixed order, so repeated runs agree bit for bit.
+ *   T_kin = sum p^2/m / (3(N-1)), T_int = N / sum 1/T_i, n (step counter),
+ *   |grad U|^2 = sum |F_i|^2, Laplacian of U = 2 sum_{i<j} (v'' + 2 v'/r)
+ * (energy of Sec. 2.1 with the kinetic term p^2/(2m); eqs. Tkin, Tint; the
+ * last two give the configurational temperature of eq. Tcon as the ratio of
+ * their time averages).  Each sum is exact in 128-bit fixed point before its
+ * final rounding, so records do not depend on the order of the particles.
  */
-int dpde_energies(dpde_handle* h, double out[10]);
+int dpde_energies(dpde_handle* h, double out[DPDE_REC_LEN]);
 
 /*
  * Per-step observable records written by the stepping calls, oldest first,
- * into host out[cap][nrep][10] (nrep = 1 for dpde_init handles; each record
- * as dpde_energies).  *count receives the number of steps returned: the
- * history holds the last min(65536, 2^23/nrep) steps at most.  The history is
+ * into host out[cap][nrep][DPDE_REC_LEN] (nrep = 1 for dpde_init handles; each
+ * record as dpde_energies).  *count receives the number of steps returned:
+ * the history holds the last min(65536, 2^26/(96 nrep)) steps at most.  The history is
  * cleared by the call.
  */
 int dpde_history(dpde_handle* h, double* out, int64_t cap, int64_t* count);
@@ -192,7 +218,7 @@ int dpde_init_batch(const dpde_params* params, int32_t nrep, const int64_t* offs
                     const double* q, const double* p, const double* eps, void* hip_stream,
                     dpde_handle** out);
 
-/* Observables of every replica into host out[nrep][10] (as dpde_energies). */
+/* Observables of every replica into host out[nrep][DPDE_REC_LEN] (as dpde_energies). */
 int dpde_energies_batch(dpde_handle* h, double* out);
 
 /*

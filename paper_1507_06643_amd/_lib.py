@@ -18,7 +18,11 @@ FP64, FP32 = 0, 1
 EOS_LINEAR, EOS_EINSTEIN = 0, 1
 THETA_NEWTON, THETA_MLP, THETA_MLP_NEWTON = 0, 1, 2
 SCHEME_SER, SCHEME_SEM = 0, 1
+MODEL_VECTOR, MODEL_PROJECTED = 0, 1
+POT_SOFT, POT_LJ = 0, 1
 DPDE_FLAG_REGENERATE_NOISE = 1
+DPDE_FLAG_PROJECT_EINT = 2
+REC_LEN = 12
 MLP_NPARAM = 1153
 
 ERROR_NAMES = {
@@ -36,11 +40,13 @@ class Params(C.Structure):
         ("mass", C.c_double), ("rc", C.c_double), ("a", C.c_double), ("gamma", C.c_double),
         ("kT_ref", C.c_double), ("dt", C.c_double), ("cv", C.c_double),
         ("eos_n", C.c_double), ("eos_omega", C.c_double), ("eos_c0", C.c_double),
+        ("eps_lj", C.c_double), ("r_lj", C.c_double),
         ("skin", C.c_double),
         ("seed", C.c_uint64), ("step0", C.c_int64),
         ("periodic", C.c_int32 * 3),
         ("eos", C.c_int32), ("precision", C.c_int32), ("theta_mode", C.c_int32),
-        ("scheme", C.c_int32), ("replica", C.c_uint32), ("neighbor_cap", C.c_int32),
+        ("scheme", C.c_int32), ("model", C.c_int32), ("potential", C.c_int32),
+        ("replica", C.c_uint32), ("neighbor_cap", C.c_int32),
         ("flags", C.c_int32),
     ]
 

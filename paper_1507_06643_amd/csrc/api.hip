@@ -95,6 +95,8 @@ struct dpde_handle {
   int32_t* rep_tile0 = nullptr;
   int ntiles = 0;
   Fix* partials = nullptr;
+  double* E0 = nullptr;   // per-replica target energy of the projection
+  double* Li = nullptr;   // per-particle Laplacian share of U
   double* rec = nullptr;
   double* hist = nullptr;
   int64_t hist_cap = 0;
@@ -191,14 +193,22 @@ int check_params(const dpde_params* P, bool first) {
   }
   if (P->precision != DPDE_FP64 && P->precision != DPDE_FP32)
     return fail(DPDE_EINVAL, "unknown precision %d", P->precision);
+  if (P->model != DPDE_MODEL_VECTOR && P->model != DPDE_MODEL_PROJECTED)
+    return fail(DPDE_EINVAL, "unknown model %d", P->model);
+  if (P->potential == DPDE_POT_LJ) {
+    if (!(std::isfinite(P->eps_lj) && P->eps_lj > 0 && std::isfinite(P->r_lj) && P->r_lj > 0))
+      return fail(DPDE_EINVAL, "LJ needs eps_lj > 0 and r_lj > 0");
+  } else if (P->potential != DPDE_POT_SOFT) {
+    return fail(DPDE_EINVAL, "unknown potential %d", P->potential);
+  }
+  if ((P->flags & ~(DPDE_FLAG_REGENERATE_NOISE | DPDE_FLAG_PROJECT_EINT)) != 0)
+    return fail(DPDE_EINVAL, "unknown flags 0x%x", P->flags);
   if (P->theta_mode < 0 || P->theta_mode > 2)
     return fail(DPDE_EINVAL, "unknown theta_mode %d", P->theta_mode);
   if (P->scheme != DPDE_SCHEME_SER && P->scheme != DPDE_SCHEME_SEM)
     return fail(DPDE_EINVAL, "unknown scheme %d", P->scheme);
   if (P->neighbor_cap < 0 || P->neighbor_cap > 1024)
     return fail(DPDE_EINVAL, "neighbor_cap must be in [0, 1024]");
-  if ((P->flags & ~DPDE_FLAG_REGENERATE_NOISE) != 0)
-    return fail(DPDE_EINVAL, "unknown bits in flags");
   return DPDE_OK;
 }
 
@@ -234,7 +244,20 @@ void physics(const dpde_params* P, Phys& ph) {
   ph.dt = P->dt;
   ph.half_dt = 0.5 * P->dt;
   ph.sqrt_dt = std::sqrt(P->dt);
-  ph.dsigma2_m = 3.0 * ph.sigma * ph.sigma / P->mass;
+  // Ito term of the SEM energy update: one noise dimension per component of
+  // G_ij (3), or the single scalar of the projected model (1)
+  ph.dsigma2_m = (P->model == DPDE_MODEL_PROJECTED ? 1.0 : 3.0) * ph.sigma * ph.sigma / P->mass;
+  ph.model = P->model;
+  ph.potential = P->potential;
+  ph.project = (P->flags & DPDE_FLAG_PROJECT_EINT) != 0;
+  ph.lj4e = 4.0 * P->eps_lj;
+  ph.r_lj2 = P->r_lj * P->r_lj;
+  {
+    // v_LJ(rc) and v_LJ'(rc) of the spline (eq. Ep: v(rc) = v'(rc) = 0)
+    const double s6 = std::pow(P->r_lj / P->rc, 6.0);
+    ph.lj_vc = 4.0 * P->eps_lj * (s6 * s6 - s6);
+    ph.lj_dvc = -24.0 * P->eps_lj * (2.0 * s6 * s6 - s6) / P->rc;
+  }
   ph.cv = P->cv;
   ph.eos_n = P->eos_n;
   ph.eos_omega = P->eos_omega;
@@ -258,6 +281,7 @@ int allocate(dpde_handle* h) {
   if ((rc = alloc_pstate(h, h->cur)) || (rc = alloc_pstate(h, h->alt))) return rc;
   if ((rc = dalloc(h, &h->Fx, n)) || (rc = dalloc(h, &h->Fy, n)) || (rc = dalloc(h, &h->Fz, n)) ||
       (rc = dalloc(h, &h->dpi, n)) || (rc = dalloc(h, &h->hv, n)) || (rc = dalloc(h, &h->deps, n)) || (rc = dalloc(h, &h->Ui, n)) ||
+      (rc = dalloc(h, &h->Li, n)) ||
       (rc = dalloc(h, &h->idk, n)))
     return rc;
   if ((rc = dalloc(h, &h->key, n)) || (rc = dalloc(h, &h->ticket, n)) ||
@@ -302,12 +326,13 @@ int allocate(dpde_handle* h) {
   tb.push_back(n);
   if ((rc = dalloc(h, &h->tile_begin, tb.size())) || (rc = dalloc(h, &h->rep_tile0, rt.size())) ||
       (rc = dalloc(h, &h->partials, (size_t)h->ntiles * kStatVals)) ||
-      (rc = dalloc(h, &h->rec, (size_t)h->nrep * 10)))
+      (rc = dalloc(h, &h->rec, (size_t)h->nrep * kRecLen)) ||
+      (rc = dalloc(h, &h->E0, (size_t)h->nrep)))
     return rc;
   HIPCHK(hipMemcpy(h->tile_begin, tb.data(), tb.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(h->rep_tile0, rt.data(), rt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  h->hist_cap = std::max<int64_t>(16, std::min<int64_t>(65536, kHistBytes / (h->nrep * 80)));
-  if ((rc = dalloc(h, &h->hist, (size_t)h->hist_cap * h->nrep * 10))) return rc;
+  h->hist_cap = std::max<int64_t>(16, std::min<int64_t>(65536, kHistBytes / (h->nrep * kRecLen * 8)));
+  if ((rc = dalloc(h, &h->hist, (size_t)h->hist_cap * h->nrep * kRecLen))) return rc;
   if ((rc = dalloc(h, &h->geo, h->nrep))) return rc;
   HIPCHK(hipMemcpy(h->geo, h->geo_h.data(), h->nrep * sizeof(Geo), hipMemcpyHostToDevice));
   HIPCHK(hipMemset(h->status, 0, 4 * sizeof(uint32_t)));
@@ -359,8 +384,8 @@ void enqueue_bin(dpde_handle* h, int kick) {
          blocks(n * kSub, pb), pb,
          h->cur, (const uint32_t*)h->cell_start, n, (const Geo*)h->geo, h->rs2, h->skin, ctl, hs2,
          h->status);
-  launch(h, "sort_skin", k_sort_skin, blocks(n, 256), 256, n, h->skin, (const uint32_t*)h->slot,
-         ctl, hs2, (const uint32_t*)h->status);
+  launch(h, "sort_skin", h->skin.cap > 64 ? k_sort_skin<128> : k_sort_skin<64>, blocks(n, 256),
+         256, n, h->skin, (const uint32_t*)h->slot, ctl, hs2, (const uint32_t*)h->status);
 }
 
 void enqueue_forces(dpde_handle* h, int mode) {
@@ -368,7 +393,7 @@ void enqueue_forces(dpde_handle* h, int mode) {
   const int64_t n = h->n;
   auto go = [&](auto kern) {
     launch(h, "pass_a_forces", kern, blocks(n * kSub, b), b, h->cur, n, (const Geo*)h->geo, h->phys, mode,
-           h->Fx, h->Fy, h->Fz, h->Ui, h->skin, h->nl, h->status);
+           h->Fx, h->Fy, h->Fz, h->Ui, h->Li, h->skin, h->nl, h->status);
   };
   if (h->batch) {
     if (h->phys.precision == DPDE_FP32) go(k_pass_a<true, PREC_F32>);
@@ -425,12 +450,30 @@ void enqueue_fd(dpde_handle* h) {
   }
 }
 
-void enqueue_stats(dpde_handle* h, int advance) {
+void enqueue_stats_only(dpde_handle* h, int advance) {
   launch(h, "stats_tiles", k_stats_tiles, h->ntiles, kStatThreads, h->cur, (const double*)h->Ui,
+         (const double*)h->Li, (const double*)h->Fx, (const double*)h->Fy, (const double*)h->Fz,
          (const int64_t*)h->tile_begin, h->phys, h->partials);
   launch(h, "stats_final", k_stats_final, h->nrep, kStatThreads, (const Fix*)h->partials,
          (const int32_t*)h->rep_tile0, (const Geo*)h->geo, (const uint64_t*)h->d_step, advance,
          h->rec, h->hist, h->hist_cap, (const int64_t*)h->d_hist_count, h->nrep);
+}
+
+// Observables of the step; with the projection (Sec. 4.2) the record of the
+// unconstrained update gives E, the internal energies are shifted, and the
+// record is taken again from the projected state.
+void enqueue_stats(dpde_handle* h, int advance) {
+  if (advance && h->phys.project) {
+    enqueue_stats_only(h, 0);
+    const int inl = eos_inline(h) ? 1 : 0;
+    launch(h, "project", h->batch ? k_project<true> : k_project<false>, blocks(h->n, h->aux_block),
+           h->aux_block, h->cur, h->n, (const Geo*)h->geo, h->phys, (const double*)h->rec,
+           (const double*)h->E0, inl, h->status);
+    if (!inl)
+      enqueue_theta_mlp(h->mlp, h->stream, h->cur.eps, &h->cur.r->invT, 8, h->n, h->phys,
+                        h->status);
+  }
+  enqueue_stats_only(h, advance);
   launch(h, "step_end", k_step_end, 1, 1, h->d_step, h->d_hist_count, h->ctl, h->builds,
          h->half_skin2, advance, (const uint32_t*)h->status);
 }
@@ -456,6 +499,8 @@ int prepare(dpde_handle* h) {
     enqueue_theta_mlp(h->mlp, h->stream, h->cur.eps, &h->cur.r->invT, 8, h->n, h->phys, h->status);
   }
   enqueue_stats(h, 0);
+  launch(h, "capture_e0", k_capture_e0, blocks(h->nrep, 256), 256, (const double*)h->rec, h->E0,
+         h->nrep);
   uint32_t st = 0;
   HIPCHK(hipMemcpyAsync(&st, h->status, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -536,7 +581,10 @@ int create(const dpde_params* params, int nrep, const int64_t* offsets, const do
                   params[r].kT_ref != params[0].kT_ref || params[r].dt != params[0].dt ||
                   params[r].eos != params[0].eos || params[r].precision != params[0].precision ||
                   params[r].scheme != params[0].scheme || params[r].step0 != params[0].step0 ||
-                  params[r].skin != params[0].skin)) {
+                  params[r].skin != params[0].skin || params[r].model != params[0].model ||
+                  params[r].potential != params[0].potential ||
+                  params[r].eps_lj != params[0].eps_lj || params[r].r_lj != params[0].r_lj ||
+                  params[r].flags != params[0].flags)) {
       release(h);
       return fail(DPDE_EINVAL, "replica %d: physical parameters differ from replica 0", r);
     }
@@ -656,16 +704,16 @@ int dpde_step_graph(dpde_handle* h, int64_t nsteps, int64_t reps) {
   return rc;
 }
 
-int dpde_energies(dpde_handle* h, double out[10]) {
+int dpde_energies(dpde_handle* h, double out[DPDE_REC_LEN]) {
   if (!h || !out) return fail(DPDE_EINVAL, "NULL argument");
-  HIPCHK(hipMemcpyAsync(out, h->rec, 10 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(out, h->rec, kRecLen * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return DPDE_OK;
 }
 
 int dpde_energies_batch(dpde_handle* h, double* out) {
   if (!h || !out) return fail(DPDE_EINVAL, "NULL argument");
-  HIPCHK(hipMemcpyAsync(out, h->rec, (size_t)h->nrep * 10 * sizeof(double), hipMemcpyDeviceToHost,
+  HIPCHK(hipMemcpyAsync(out, h->rec, (size_t)h->nrep * kRecLen * sizeof(double), hipMemcpyDeviceToHost,
                         h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return DPDE_OK;
@@ -679,7 +727,7 @@ int dpde_history(dpde_handle* h, double* out, int64_t cap, int64_t* count) {
   const int64_t held = std::min(total, h->hist_cap);
   const int64_t first = total - held;  // oldest record still held
   const int64_t take = std::min(held, cap);
-  const size_t rec_doubles = (size_t)h->nrep * 10;
+  const size_t rec_doubles = (size_t)h->nrep * kRecLen;
   if (out && take > 0) {
     std::vector<double> buf((size_t)h->hist_cap * rec_doubles);
     HIPCHK(hipMemcpy(buf.data(), h->hist, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -718,7 +766,7 @@ int dpde_forces(dpde_handle* h, double* F, double* U) {
   if (!h || !F) return fail(DPDE_EINVAL, "NULL argument");
   launch(h, "store_forces", k_store_vec3, blocks(h->n, 256), 256, h->cur, (const Geo*)h->geo,
          h->n, (const double*)h->Fx, (const double*)h->Fy, (const double*)h->Fz, F);
-  double rec[10];
+  double rec[kRecLen];
   HIPCHK(hipMemcpyAsync(rec, h->rec, sizeof(rec), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipGetLastError());
@@ -744,7 +792,7 @@ int dpde_autotune(dpde_handle* h, int32_t steps, int32_t* pair_block, int32_t* a
   if (steps < 1) return fail(DPDE_EINVAL, "steps must be >= 1");
   // snapshot: state in identifier order, step, list-build count, history
   const size_t n = (size_t)h->n;
-  const size_t hist_bytes = (size_t)h->hist_cap * h->nrep * 10 * sizeof(double);
+  const size_t hist_bytes = (size_t)h->hist_cap * h->nrep * kRecLen * sizeof(double);
   double *q = nullptr, *p = nullptr, *e = nullptr, *hist = nullptr;
   auto cleanup = [&]() {
     if (q) (void)hipFree(q);

@@ -38,12 +38,16 @@ struct Phys {
   double a, half_a_rc;      // force amplitude, potential prefactor a rc / 2
   double gkT_half;          // gamma kT_ref / 2: gamma_ij = gkT_half (1/T_i + 1/T_j)
   double sigma, dt, half_dt, sqrt_dt;
-  double dsigma2_m;         // d sigma^2 / m (SEM internal-energy drift)
+  double dsigma2_m;         // k sigma^2 / m with k noise dimensions (SEM drift)
   double cv, eos_n, eos_omega, eos_c0;
   double mlp_in_c, mlp_in_s, mlp_out_c, mlp_out_s, mlp_eps_lo, mlp_eps_hi;
+  // splined LJ: v = c12/r^12 - c6/r^6 - v_c - dv_c (r - rc), r_lj2 = r_lj^2
+  double lj4e, r_lj2, lj_vc, lj_dvc;
   int32_t eos, theta_mode, precision, scheme;
   int32_t cap;              // neighbour list capacity per particle
-  int32_t pad_;
+  int32_t model;            // 0: along v_ij (3-d G), 1: along e_ij (scalar xi)
+  int32_t potential;        // 0: soft, 1: splined LJ
+  int32_t project;          // eps projection after every step
 };
 
 // -------------------------------------------------------------------------
@@ -192,6 +196,14 @@ __device__ __forceinline__ void box_muller_f64(const uint32_t w[4], double G[3])
   G[2] = r2 * cs3;
 }
 
+// The first normal only (the scalar noise of the projected model).
+__device__ __forceinline__ double normal1_f64(const uint32_t w[4]) {
+  const double r1 = sqrt_pos_f64(-2.0 * ln_uniform_f64(w[0]));
+  double sn, cs;
+  sincospi_f64((2.0 * (double)w[1] + 1.0) * 2.3283064365386963e-10, sn, cs);
+  return r1 * cs;
+}
+
 // ln u for u = (x + 1/2) 2^-32 in FP32.  Far from 1 the float of x keeps 24
 // significant bits at every magnitude (the tails keep full relative
 // precision); within 2^-8 of 1, ln u = ln(1 - v) is summed as a series in the
@@ -217,6 +229,11 @@ __device__ __forceinline__ void box_muller_f32(const uint32_t w[4], float G[3]) 
   G[0] = r1 * __builtin_amdgcn_cosf(u1);
   G[1] = r1 * __builtin_amdgcn_sinf(u1);
   G[2] = r2 * __builtin_amdgcn_cosf(u3);
+}
+
+__device__ __forceinline__ float normal1_f32(const uint32_t w[4]) {
+  const float r1 = __builtin_sqrtf(-2.0f * ln_uniform_f32(w[0]));
+  return r1 * __builtin_amdgcn_cosf((float)w[1] * 2.3283064365386963e-10f);
 }
 
 // -------------------------------------------------------------------------

@@ -275,9 +275,9 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
 // Sort each skin list by neighbour identifier and replace the identifier
 // rows by memory indices (slot[row], written by the reorder).  One list per
 // lane, held in registers padded with all-ones and sorted by a bitonic
-// network of 32 or 64 words (the wave's longest list picks the width; rows
-// are unique, so the order is total).  Lists longer than 64 words are
-// insertion-sorted in place in global memory.
+// network of 32, 64 or (for long lists, MAXW = 128) 128 words (the wave's
+// longest list picks the width; rows are unique, so the order is total).
+// Longer lists are insertion-sorted in place in global memory.
 template <int N>
 __device__ __forceinline__ void bitonic_sort(uint32_t (&v)[N]) {
 #pragma unroll
@@ -311,6 +311,7 @@ __device__ __forceinline__ void sort_list_regs(const SkinList& sl, const uint32_
     if ((uint32_t)k < nn) sl.idx[k * st + i] = slot[v[k]];
 }
 
+template <int MAXW>
 __global__ __launch_bounds__(256) void k_sort_skin(int64_t n, SkinList sl,
                                                    const uint32_t* __restrict__ slot,
                                                    const BuildCtl* ctl, double half_skin2,
@@ -325,8 +326,10 @@ __global__ __launch_bounds__(256) void k_sort_skin(int64_t n, SkinList sl,
   if (i >= n || nn == 0) return;
   if (wmax <= 32u) {
     sort_list_regs<32>(sl, slot, i, nn);
-  } else if (nn <= 64u) {
+  } else if (nn <= 64u && (MAXW == 64 || wmax <= 64u)) {
     sort_list_regs<64>(sl, slot, i, nn);
+  } else if (MAXW >= 128 && nn <= 128u) {
+    sort_list_regs<MAXW>(sl, slot, i, nn);
   } else {
     const int64_t st = sl.stride;
     for (uint32_t m = 1; m < nn; ++m) {
@@ -346,13 +349,15 @@ __global__ __launch_bounds__(256) void k_sort_skin(int64_t n, SkinList sl,
 
 // Pass A: neighbour list of the step (skin entries with r < rc, in identifier
 // order, staged in LDS and written out coalesced), forces
-// F_i = sum_j a (1 - r/rc) d_ij / r, U_i = 1/2 sum_j v(r_ij); mode 1 also
-// applies p += dt/2 F (end of velocity-Verlet).
+// F_i = -sum_j v'(r_ij) d_ij / r_ij, U_i = 1/2 sum_j v(r_ij) and the Laplacian
+// share L_i = sum_j (v'' + 2 v'/r) (eq. Tcon); mode 1 also applies
+// p += dt/2 F (end of velocity-Verlet).  v is the soft potential
+// (a rc/2)(1 - r/rc)^2 or the splined LJ of eq. Ep.
 template <bool BATCH, int PREC>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
     PState s, int64_t n, const Geo* __restrict__ geo, Phys P, int mode,
     double* __restrict__ Fx, double* __restrict__ Fy, double* __restrict__ Fz,
-    double* __restrict__ Ui, SkinList sl, NList nl, uint32_t* status) {
+    double* __restrict__ Ui, double* __restrict__ Li, SkinList sl, NList nl, uint32_t* status) {
   __shared__ uint32_t lst[kListLds * (kPairBlockMax / kSub)];
   const Lanes L = lanes();
   if (L.i >= n) return;  // uniform in the group
@@ -364,7 +369,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
   const uint32_t ns = sl.count[i];
   const uint32_t cap = (uint32_t)P.cap;
   uint32_t nn = 0;
-  double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0;
+  double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, lap = 0.0;
   const float inv_rc_f = (float)P.inv_rc, a_f = (float)P.a;
   uint32_t jn = (uint32_t)L.sub < ns ? sl.idx[(int64_t)L.sub * sl.stride + i] : 0u;
   for (uint32_t base = 0; base < ns; base += kSub) {
@@ -397,17 +402,43 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
       if constexpr (PREC == PREC_F64) {
         const double ir = inv_sqrt_f64(orr);  // 0 at r = 0
         const double rr = orr * ir;
-        const double w = 1.0 - rr * P.inv_rc;
-        u += w * w;
-        const double f = P.a * w * ir;
+        double f;
+        if (P.potential == 0) {
+          const double w = 1.0 - rr * P.inv_rc;
+          u += P.half_a_rc * w * w;
+          f = P.a * w * ir;  // -v'(r)/r
+          lap += ir > 0.0 ? P.a * P.inv_rc - 2.0 * P.a * w * ir : 0.0;
+        } else {
+          const double ir2 = ir * ir;
+          const double s2 = P.r_lj2 * ir2;
+          const double s6 = s2 * s2 * s2, s12 = s6 * s6;
+          u += P.lj4e * (s12 - s6) - P.lj_vc - P.lj_dvc * (rr - P.rc);
+          const double dv = -6.0 * P.lj4e * (2.0 * s12 - s6) * ir - P.lj_dvc;
+          f = -dv * ir;
+          lap += P.lj4e * (156.0 * s12 - 42.0 * s6) * ir2 + 2.0 * dv * ir;
+        }
         fx += f * ox;
         fy += f * oy;
         fz += f * oz;
       } else {
         const float rr = __builtin_sqrtf((float)orr);
-        const float w = 1.0f - rr * inv_rc_f;
-        u += (double)(w * w);
-        const float f = rr > 0.0f ? a_f * w / rr : 0.0f;
+        const float ir = rr > 0.0f ? 1.0f / rr : 0.0f;
+        float f;
+        if (P.potential == 0) {
+          const float w = 1.0f - rr * inv_rc_f;
+          u += (double)((float)P.half_a_rc * w * w);
+          f = a_f * w * ir;
+          lap += (double)(rr > 0.0f ? a_f * inv_rc_f - 2.0f * a_f * w * ir : 0.0f);
+        } else {
+          const float ir2 = ir * ir;
+          const float s2 = (float)P.r_lj2 * ir2;
+          const float s6 = s2 * s2 * s2, s12 = s6 * s6;
+          const float e4 = (float)P.lj4e;
+          u += (double)(e4 * (s12 - s6) - (float)P.lj_vc - (float)P.lj_dvc * (rr - (float)P.rc));
+          const float dv = -6.0f * e4 * (2.0f * s12 - s6) * ir - (float)P.lj_dvc;
+          f = -dv * ir;
+          lap += (double)(e4 * (156.0f * s12 - 42.0f * s6) * ir2 + 2.0f * dv * ir);
+        }
         fx += (double)(f * (float)ox);
         fy += (double)(f * (float)oy);
         fz += (double)(f * (float)oz);
@@ -419,6 +450,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
   fy = group_sum(fy);
   fz = group_sum(fz);
   u = group_sum(u);
+  lap = group_sum(lap);
   if (nn > cap) {
     if (L.sub == 0) atomicOr(status, ST_OVERFLOW);
     nn = cap;
@@ -431,7 +463,8 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
     Fx[i] = fx;
     Fy[i] = fy;
     Fz[i] = fz;
-    Ui[i] = 0.5 * P.half_a_rc * u;
+    Ui[i] = 0.5 * u;
+    Li[i] = lap;
     if (mode) {
       Rec* W = s.r;
       W[i].px = W[i].px + P.half_dt * fx;
@@ -451,24 +484,48 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
 // ---------------------------------------------------------------------------
 struct PairOut {
   double dp[3];
-  double gdotv;  // (sign G) . v_ij, for SEM
+  double gdotv;  // noise . velocity term of the SEM energy update
+  double v2;     // squared velocity term of the SEM energy update
   double chi;
   double w;
   double gij;
 };
 
+// Model 1 (the original DPDE model, Sec. 2.1): friction and noise along
+// e_ij = d_ij / r with one scalar normal xi_ij = xi_ji per pair,
+//   dp_ij = (-gamma_ij chi (e_ij . v_ij) dt + sigma w xi_ij sqrt(dt)) e_ij,
+// antisymmetric through e_ji = -e_ij; a coincident pair does not interact.
 template <int PREC>
-__device__ __forceinline__ void ser_pair(const Phys& P, const Geo& g, double r2, double vx,
-                                         double vy, double vz, double invT_sum, uint32_t idi,
-                                         uint32_t idj, uint64_t step, PairOut& o) {
+__device__ __forceinline__ void ser_pair(const Phys& P, const Geo& g, double dx, double dy,
+                                         double dz, double r2, double vx, double vy, double vz,
+                                         double invT_sum, uint32_t idi, uint32_t idj,
+                                         uint64_t step, PairOut& o) {
   const bool i_lo = idi < idj;
   uint32_t wd[4];
   pair_words(g, i_lo ? idi : idj, i_lo ? idj : idi, step, wd);
   if constexpr (PREC == PREC_F64) {
-    const double r = r2 * inv_sqrt_f64(r2);
-    const double w = 1.0 - r * P.inv_rc;
-    const double chi = w * w;
+    const double ir = inv_sqrt_f64(r2);
+    const double r = r2 * ir;
+    double w = 1.0 - r * P.inv_rc;
     const double gij = P.gkT_half * invT_sum;
+    if (P.model == 1) {
+      if (!(r2 > 0.0)) w = 0.0;
+      const double chi = w * w;
+      const double ex = dx * ir, ey = dy * ir, ez = dz * ir;
+      const double ev = ex * vx + ey * vy + ez * vz;
+      const double xi = normal1_f64(wd);
+      const double mag = -gij * chi * ev * P.dt + P.sigma * w * xi * P.sqrt_dt;
+      o.dp[0] = mag * ex;
+      o.dp[1] = mag * ey;
+      o.dp[2] = mag * ez;
+      o.gdotv = ev * xi;
+      o.v2 = ev * ev;
+      o.chi = chi;
+      o.w = w;
+      o.gij = gij;
+      return;
+    }
+    const double chi = w * w;
     double G[3];
     box_muller_f64(wd, G);
     const double c1 = -gij * chi * P.dt;
@@ -477,23 +534,43 @@ __device__ __forceinline__ void ser_pair(const Phys& P, const Geo& g, double r2,
     o.dp[1] = c1 * vy + c2 * G[1];
     o.dp[2] = c1 * vz + c2 * G[2];
     o.gdotv = (i_lo ? 1.0 : -1.0) * (G[0] * vx + G[1] * vy + G[2] * vz);
+    o.v2 = vx * vx + vy * vy + vz * vz;
     o.chi = chi;
     o.w = w;
     o.gij = gij;
   } else {
     const float r = __builtin_sqrtf((float)r2);
-    const float w = 1.0f - r * (float)P.inv_rc;
-    const float chi = w * w;
+    float w = 1.0f - r * (float)P.inv_rc;
     const float gij = (float)(P.gkT_half * invT_sum);
+    const float v0 = (float)vx, v1 = (float)vy, v2 = (float)vz;
+    if (P.model == 1) {
+      if (!(r > 0.0f)) w = 0.0f;
+      const float chi = w * w;
+      const float ir = r > 0.0f ? 1.0f / r : 0.0f;
+      const float ex = (float)dx * ir, ey = (float)dy * ir, ez = (float)dz * ir;
+      const float ev = ex * v0 + ey * v1 + ez * v2;
+      const float xi = normal1_f32(wd);
+      const float mag = -gij * chi * ev * (float)P.dt + (float)P.sigma * w * xi * (float)P.sqrt_dt;
+      o.dp[0] = (double)(mag * ex);
+      o.dp[1] = (double)(mag * ey);
+      o.dp[2] = (double)(mag * ez);
+      o.gdotv = (double)(ev * xi);
+      o.v2 = (double)(ev * ev);
+      o.chi = (double)chi;
+      o.w = (double)w;
+      o.gij = (double)gij;
+      return;
+    }
+    const float chi = w * w;
     float G[3];
     box_muller_f32(wd, G);
     const float c1 = -gij * chi * (float)P.dt;
     const float c2 = (i_lo ? (float)P.sigma : -(float)P.sigma) * w * (float)P.sqrt_dt;
-    const float v0 = (float)vx, v1 = (float)vy, v2 = (float)vz;
     o.dp[0] = (double)(c1 * v0 + c2 * G[0]);
     o.dp[1] = (double)(c1 * v1 + c2 * G[1]);
     o.dp[2] = (double)(c1 * v2 + c2 * G[2]);
     o.gdotv = (double)((i_lo ? 1.0f : -1.0f) * (G[0] * v0 + G[1] * v1 + G[2] * v2));
+    o.v2 = vx * vx + vy * vy + vz * vz;
     o.chi = (double)chi;
     o.w = (double)w;
     o.gij = (double)gij;
@@ -511,7 +588,7 @@ __device__ __forceinline__ void pair_from_records(const Phys& P, const Geo& g, c
   vx = a.px * P.inv_mass - b.px * P.inv_mass;
   vy = a.py * P.inv_mass - b.py * P.inv_mass;
   vz = a.pz * P.inv_mass - b.pz * P.inv_mass;
-  ser_pair<PREC>(P, g, r2, vx, vy, vz, a.invT + b.invT, a.id, b.id, step, o);
+  ser_pair<PREC>(P, g, dx, dy, dz, r2, vx, vy, vz, a.invT + b.invT, a.id, b.id, step, o);
 }
 
 // ---------------------------------------------------------------------------
@@ -553,8 +630,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
       nl.dez[e] = o.dp[2];
     }
     if constexpr (SCHEME == 1) {
-      const double v2 = vx * vx + vy * vy + vz * vz;
-      de += 0.5 * (o.gij * v2 - P.dsigma2_m) * o.chi * P.dt -
+      de += 0.5 * (o.gij * o.v2 - P.dsigma2_m) * o.chi * P.dt -
             0.5 * P.sigma * o.w * o.gdotv * P.sqrt_dt;
     }
   }
@@ -695,11 +771,15 @@ __global__ void k_inv_temperature(PState s, int64_t n, Phys P, uint32_t* status)
 // Record: U, K, sum eps, E, Px, Py, Pz, T_kin, T_int, step.
 // ---------------------------------------------------------------------------
 constexpr int kStatThreads = 256;
-constexpr int kStatVals = 8;  // U, K, sum eps, Px, Py, Pz, sum 1/T, out-of-range count
+// U, K, sum eps, Px, Py, Pz, sum 1/T, |grad U|^2, Laplacian U, out-of-range count
+constexpr int kStatVals = 10;
+constexpr int kStatBad = 9;
+constexpr int kRecLen = 12;  // record: U K sum-eps E Px Py Pz Tkin Tint n |gradU|^2 lapU
 
 __global__ __launch_bounds__(kStatThreads) void k_stats_tiles(
-    PState s, const double* __restrict__ Ui, const int64_t* __restrict__ tile_begin, Phys P,
-    Fix* __restrict__ partials) {
+    PState s, const double* __restrict__ Ui, const double* __restrict__ Li,
+    const double* __restrict__ Fx, const double* __restrict__ Fy, const double* __restrict__ Fz,
+    const int64_t* __restrict__ tile_begin, Phys P, Fix* __restrict__ partials) {
   const int64_t b = tile_begin[blockIdx.x], e = tile_begin[blockIdx.x + 1];
   Fix v[kStatVals];
 #pragma unroll
@@ -708,12 +788,13 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_tiles(
     const Rec& rc = s.r[i];
     const double px = rc.px, py = rc.py, pz = rc.pz;
     const double p2 = px * px + py * py + pz * pz;
-    const double x[7] = {Ui[i], p2 / (2.0 * P.mass), s.eps[i], px, py, pz, rc.invT};
+    const double f2 = Fx[i] * Fx[i] + Fy[i] * Fy[i] + Fz[i] * Fz[i];
+    const double x[9] = {Ui[i], p2 / (2.0 * P.mass), s.eps[i], px, py, pz, rc.invT, f2, Li[i]};
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < 9; ++k) {
       // values outside the fixed-point range are counted, and the record is NaN
       if (fabs(x[k]) < 0x1p30) v[k] = fix_add(v[k], fix_of(x[k]));
-      else v[7] = fix_add(v[7], Fix{1ull, 0ll});
+      else v[kStatBad] = fix_add(v[kStatBad], Fix{1ull, 0ll});
     }
   }
   __shared__ Fix smem[kStatVals * (kStatThreads / kWave)];
@@ -737,11 +818,11 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_final(
   __shared__ Fix smem[kStatVals * (kStatThreads / kWave)];
   block_sum_fix<kStatVals>(f, smem);
   if (threadIdx.x == 0) {
-    const bool bad = f[7].lo != 0ull || f[7].hi != 0ll;
-    double v[7];
-    for (int k = 0; k < 7; ++k) v[k] = bad ? __builtin_nan("") : fix_to_double(f[k]);
+    const bool bad = f[kStatBad].lo != 0ull || f[kStatBad].hi != 0ll;
+    double v[9];
+    for (int k = 0; k < 9; ++k) v[k] = bad ? __builtin_nan("") : fix_to_double(f[k]);
     const double N = (double)geo[r].n;
-    double o[10];
+    double o[kRecLen];
     o[0] = v[0];
     o[1] = v[1];
     o[2] = v[2];
@@ -752,13 +833,42 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_final(
     o[7] = 2.0 * v[1] / (3.0 * (N - 1.0));
     o[8] = N / v[6];
     o[9] = (double)(*d_step + (uint64_t)advance);
+    o[10] = v[7];
+    o[11] = v[8];
     double* hrow = nullptr;
-    if (advance) hrow = hist + ((*d_hist_count % hist_cap) * nrep + r) * 10;
-    for (int k = 0; k < 10; ++k) {
-      rec[r * 10 + k] = o[k];
+    if (advance) hrow = hist + ((*d_hist_count % hist_cap) * nrep + r) * kRecLen;
+    for (int k = 0; k < kRecLen; ++k) {
+      rec[r * kRecLen + k] = o[k];
       if (hrow) hrow[k] = o[k];
     }
   }
+}
+
+// Projection on the internal energies (Sec. 4.2): eps_i <- eps_i - (E - E0)/N
+// per replica, E from the record of the unconstrained update, then the new
+// 1/T_i when the EOS is evaluated inline.
+template <bool BATCH>
+__global__ void k_project(PState s, int64_t n, const Geo* __restrict__ geo, Phys P,
+                          const double* __restrict__ rec, const double* __restrict__ E0,
+                          int eos_inline, uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (status_set(status)) return;
+  const uint32_t r = BATCH ? s.r[i].rep : 0u;
+  const double shift = (rec[r * kRecLen + 3] - E0[r]) / (double)geo[r].n;
+  const double e = s.eps[i] - shift;
+  s.eps[i] = e;
+  if (!(e > 0.0)) {
+    atomicOr(status, ST_NEG_EINT);
+  } else if (eos_inline) {
+    s.r[i].invT = inv_temperature(P, e, status);
+  }
+}
+
+// Target energy of the projection: the energy in the current record.
+__global__ void k_capture_e0(const double* __restrict__ rec, double* __restrict__ E0, int nrep) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrep) E0[r] = rec[r * kRecLen + 3];
 }
 
 // End of a step: count a list build, clear the build control, and (when

@@ -33,6 +33,11 @@ class Config:
     eos_omega: float = 2.0
     eos_c0: float = 10.0
     skin: float = 0.3
+    model: int = L.MODEL_VECTOR
+    potential: int = L.POT_SOFT
+    eps_lj: float = 1.0
+    r_lj: float = 1.0
+    project: bool = False
     precision: int = L.FP64
     theta_mode: int = L.THETA_NEWTON
     scheme: int = L.SCHEME_SER
@@ -49,11 +54,14 @@ class Config:
         P.kT_ref, P.dt, P.cv = self.kT_ref, self.dt, self.cv
         P.eos_n, P.eos_omega, P.eos_c0 = self.eos_n, self.eos_omega, self.eos_c0
         P.skin = float(self.skin)
+        P.eps_lj, P.r_lj = float(self.eps_lj), float(self.r_lj)
+        P.model, P.potential = int(self.model), int(self.potential)
         P.seed, P.step0 = int(self.seed) & (2**64 - 1), int(self.step0)
         P.periodic = (C.c_int32 * 3)(*[int(x) for x in self.periodic])
         P.eos, P.precision, P.theta_mode, P.scheme = (int(self.eos), int(self.precision),
                                                        int(self.theta_mode), int(self.scheme))
-        P.replica, P.neighbor_cap, P.flags = int(self.replica), int(self.neighbor_cap), 0
+        P.replica, P.neighbor_cap = int(self.replica), int(self.neighbor_cap)
+        P.flags = L.DPDE_FLAG_PROJECT_EINT if self.project else 0
         return P
 
 
@@ -140,15 +148,15 @@ class System:
     # -- observables ------------------------------------------------------------
     def energies(self) -> np.ndarray:
         if self.nrep > 1:
-            out = np.zeros((self.nrep, 10))
+            out = np.zeros((self.nrep, L.REC_LEN))
             L.check(self._lib.dpde_energies_batch(self.h, out.ctypes.data_as(C.POINTER(C.c_double))))
             return out
-        out = np.zeros(10)
+        out = np.zeros(L.REC_LEN)
         L.check(self._lib.dpde_energies(self.h, out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 
     def history(self, cap: int = 1 << 16) -> np.ndarray:
-        out = np.zeros((cap, self.nrep, 10))
+        out = np.zeros((cap, self.nrep, L.REC_LEN))
         cnt = C.c_int64(0)
         L.check(self._lib.dpde_history(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), cap,
                                        C.byref(cnt)))

@@ -261,7 +261,7 @@ def test_batched_graph_replay(dp):
     g.step_graph(2, 4)
     assert np.array_equal(a.energies(), g.energies())
     h = g.history()
-    assert h.shape == (8, 16, 10)
+    assert h.shape == (8, 16, 12)
     a.close()
     g.close()
 

@@ -1,0 +1,156 @@
+"""GPU path vs oracle for the next rows: the projection on the internal
+energies (Sec. 4.2), friction and noise along e_ij (the original DPDE model,
+Sec. 2.1), the splined LJ potential (eq. Ep) and the configurational
+temperature (eq. Tcon)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+LJ = dict(potential=1, rc=2.5, eps_lj=1.0, r_lj=1.0)
+
+
+@pytest.fixture(scope="module")
+def dp():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1507_06643_amd as m
+    return m
+
+
+def _gpu_state(s):
+    q, p, e, st = s.get_state()
+    return q.cpu().numpy(), p.cpu().numpy(), e.cpu().numpy(), st
+
+
+def _errs(box, qg, pg, eg, S):
+    dq = qg - S.q
+    for k in range(3):
+        dq[:, k] -= box[k] * np.rint(dq[:, k] / box[k])
+    return (np.abs(dq).max() / max(box), np.abs(pg - S.p).max(),
+            np.abs(eg - S.eps).max() / np.abs(S.eps).mean())
+
+
+def _step_vs_oracle(dp, q, p, e, box, cfg_kw, okw, prime=3, project=False):
+    n = len(q)
+    s = dp.System(dp.Config(n=n, box=list(box), project=project, **cfg_kw), q, p, e)
+    E0 = s.energies()[3]
+    s.step(prime)
+    qs, ps, es, st = _gpu_state(s)
+    P = O.make_params(n, box, step=st, project=int(project), **okw)
+    S = O.State(P, qs, ps, es)
+    P.E0 = E0  # the GPU's target: the energy of its initial state
+    rc, _ = S.step(1)
+    assert rc == 0
+    s.step(1)
+    qg, pg, eg, _ = _gpu_state(s)
+    errs = _errs(box, qg, pg, eg, S)
+    en, eo = s.energies(), S.energies()
+    hist = s.history()
+    s.close()
+    return errs, en, eo, E0, hist
+
+
+# ---------------------------------------------------------------------------
+# Projection on the internal energies
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_projection_step_parity(dp, scheme):
+    n = 3000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=41)
+    errs, en, eo, E0, hist = _step_vs_oracle(dp, q, p, e, [L] * 3,
+                                             dict(dt=0.02, scheme=scheme),
+                                             dict(dt=0.02, scheme=scheme), project=True)
+    assert max(errs) < TOL, errs
+    assert abs(en[3] - eo[3]) <= TOL * abs(eo[3])
+    assert np.abs(hist[:, 3] - E0).max() < 1e-12 * abs(E0)
+
+
+def test_sem_drifts_ser_conserves_projection_restores(dp):
+    n = 4000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=42)
+    drift = {}
+    for name, scheme, proj in (("sem", 1, False), ("ser", 0, False), ("sem_proj", 1, True)):
+        s = dp.System(dp.Config(n=n, box=[L] * 3, dt=0.02, scheme=scheme, project=proj), q, p, e)
+        E0 = s.energies()[3]
+        s.step(1000)
+        h = s.history()
+        drift[name] = np.abs(h[:, 3] - E0).max() / abs(E0)
+        s.close()
+    assert drift["sem_proj"] < 1e-12
+    assert drift["sem"] > 10 * drift["ser"], drift
+
+
+# ---------------------------------------------------------------------------
+# Friction and noise along e_ij
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_projected_model_step_parity(dp, scheme):
+    n = 4000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=43)
+    kw = dict(dt=0.01, scheme=scheme, model=1)
+    errs, en, eo, _, _ = _step_vs_oracle(dp, q, p, e, [L] * 3, kw, kw)
+    assert max(errs) < TOL, errs
+    assert abs(en[3] - eo[3]) <= TOL * abs(eo[3])
+    assert np.abs(en[4:7] - eo[4:7]).max() < 1e-10
+
+
+def test_projected_model_fp32(dp):
+    n = 4000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=44)
+    errs, en, eo, _, _ = _step_vs_oracle(dp, q, p, e, [L] * 3,
+                                         dict(dt=0.005, model=1, precision=dp.FP32),
+                                         dict(dt=0.005, model=1))
+    assert errs[0] < 1e-9 and errs[1] < 2e-5 and errs[2] < 2e-7, errs
+
+
+# ---------------------------------------------------------------------------
+# Splined LJ and the configurational temperature
+# ---------------------------------------------------------------------------
+def _lj_state(n_side=16, seed=45):
+    q, p, e, box = W.lattice_state(n_side, 0.8095, eps0=50.0, seed=seed)
+    return q, p, e, box
+
+
+def test_lj_forces_energy_and_config_terms(dp):
+    q, p, e, box = _lj_state()
+    n = len(q)
+    s = dp.System(dp.Config(n=n, box=box, cv=50.0, neighbor_cap=128, **LJ), q, p, e)
+    F, U = s.forces()
+    P = O.make_params(n, box, cv=50.0, **LJ)
+    Fo, Uo = O.forces(P, q)
+    assert np.abs(F.cpu().numpy() - Fo).max() <= TOL * np.abs(Fo).max()
+    assert abs(U - Uo) <= TOL * abs(Uo)
+    g2, lap = O.config_temperature_terms(P, q)
+    en = s.energies()
+    assert abs(en[10] - g2) <= 1e-11 * g2
+    assert abs(en[11] - lap) <= 1e-11 * abs(lap)
+    s.close()
+
+
+def test_lj_step_parity(dp):
+    q, p, e, box = _lj_state(seed=46)
+    kw = dict(dt=0.002, cv=50.0, gamma=8.0, **LJ)
+    errs, en, eo, _, _ = _step_vs_oracle(dp, q, p, e, box, dict(neighbor_cap=128, **kw), kw)
+    assert max(errs) < TOL, errs
+    assert abs(en[3] - eo[3]) <= TOL * abs(eo[3])
+
+
+def test_soft_config_terms(dp):
+    n = 3000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=47)
+    s = dp.System(dp.Config(n=n, box=[L] * 3), q, p, e)
+    g2, lap = O.config_temperature_terms(O.make_params(n, [L] * 3), q)
+    en = s.energies()
+    assert abs(en[10] - g2) <= 1e-11 * g2
+    assert abs(en[11] - lap) <= 1e-11 * abs(lap)
+    s.close()

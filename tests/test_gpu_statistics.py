@@ -62,3 +62,30 @@ def test_kinetic_and_internal_temperatures_agree():
     # weak order 1: the two estimators differ by O(dt); allow 5 se + 1 %
     assert abs(tk.mean() - ti.mean()) < 5 * se + 0.01 * ti.mean(), (tk.mean(), ti.mean())
     # internal-energy marginal Gamma(C_v + 1, T): <eps> = (C_v + 1) T_int
+
+
+def test_lj_temperature_estimators_agree():
+    """Melted LJ crystal at the paper's density 0.8095 with sigma = 4 and
+    C_v = 50, projected SER (Sec. 4.1-4.2): the kinetic, configurational and
+    internal temperatures (eqs. Tkin, Tcon, Tint) agree in the limit dt -> 0.
+    The scheme has weak order 1 (App. B), so each estimator carries a bias
+    linear in dt (T_kin moves by ~2 % per 0.001 here); the two runs at dt and
+    dt/2 give the Richardson extrapolation 2 T(dt/2) - T(dt)."""
+    import paper_1507_06643_amd as dp
+    q, p, e, box = W.lattice_state(16, 0.8095, eps0=50.0, seed=48)
+    n = len(q)
+    est = {}
+    for dt in (0.002, 0.001):
+        s = dp.System(dp.Config(n=n, box=box, cv=50.0, gamma=8.0, dt=dt, potential=1, rc=2.5,
+                                neighbor_cap=128, project=True), q, p, e)
+        s.step(int(round(6.0 / dt)))
+        s.history()
+        s.step(int(round(8.0 / dt)))
+        h = s.history(cap=10 ** 5)
+        s.close()
+        est[dt] = np.array([h[:, 7].mean(), h[:, 10].mean() / h[:, 11].mean(), h[:, 8].mean()])
+    tk, tpot, ti = 2.0 * est[0.001] - est[0.002]
+    assert abs(tpot - tk) / tk < 0.015, (est, tk, tpot, ti)
+    assert abs(ti - tk) / tk < 0.015, (est, tk, tpot, ti)
+    # the bias of T_kin is first order: halving dt roughly halves it
+    assert est[0.002][0] - est[0.001][0] > 0.5 * (est[0.001][0] - tk)

@@ -55,6 +55,26 @@ def shock_state(box=(400.0, 20.0, 20.0), *, density: float = DENSITY, u: float =
     return q, p, eps
 
 
+def lattice_state(n_side: int, density: float, *, kT: float = 1.0, mass: float = 1.0,
+                  eps0: float = 50.0, jitter: float = 0.05, seed: int = 20260105):
+    """Simple cubic lattice of n_side^3 particles filling a cubic box at the
+    given density, each site displaced uniformly by up to +-jitter lattice
+    spacings (a crystal to melt, for the LJ potential); Maxwell momenta with
+    zero mean; eps_i = eps0."""
+    rng = np.random.default_rng(seed)
+    n = n_side ** 3
+    L = (n / density) ** (1.0 / 3.0)
+    a = L / n_side
+    g = (np.arange(n_side) + 0.5) * a
+    q = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    q = q + rng.uniform(-jitter * a, jitter * a, size=q.shape)
+    q = np.mod(q, L)
+    p = rng.normal(0.0, np.sqrt(mass * kT), size=(n, 3))
+    p -= p.mean(axis=0)
+    eps = np.full(n, float(eps0))
+    return q, p, eps, [L, L, L]
+
+
 def replica_sizes(nrep: int, n_lo: int = 500, n_hi: int = 8000, seed: int = 20260103):
     """Replica sizes uniform in [n_lo, n_hi] and one 64-bit RNG seed per replica."""
     rng = np.random.default_rng(seed)
