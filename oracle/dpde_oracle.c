@@ -57,7 +57,8 @@ typedef struct {
   int32_t periodic[3];
   int32_t eos;       /* 0: eps = cv*theta ; 1: eps = n w/(exp(w/theta)-1) + c0 theta */
   int32_t replica;
-  int32_t scheme;    /* 0: SER (Sec. 3.2.1) ; 1: SEM (Sec. 3.1.1) */
+  int32_t scheme;    /* 0: SER (Sec. 3.2.1) ; 1: SEM (Sec. 3.1.1) ;
+                        2: Hybrid (Sec. 3.2.2): SSA inside domains, SER across */
   int32_t project;   /* 1: eps_i -= (E - E0)/N after every step (Sec. 4.2) */
   int32_t model;     /* 0: friction/noise along v_ij (eq. DPDE, the paper's variant);
                         1: projected on e_ij (the original DPDE model, Sec. 2.1) */
@@ -65,6 +66,8 @@ typedef struct {
   int32_t pad_;
   double E0;         /* target energy of the projection */
   double eps_lj, r_lj;
+  int32_t ndom[3];   /* Hybrid (scheme 2): domains per dimension (Sec. 3.2.2) */
+  int32_t pad2_;
 } or_params;
 
 /* ------------------------------------------------------------------------
@@ -525,13 +528,105 @@ int or_fd_pairs(const or_params* P, const double* q, double* p, double* eps,
   return OR_OK;
 }
 
+/* ------------------------------------------------------------------------
+ * Hybrid (Sec. 3.2.2).  The box is split into ndom[0] x ndom[1] x ndom[2]
+ * equal domains (the paper's processors); a particle belongs to the domain
+ * of its position at the start of the fluctuation/dissipation step.  The
+ * pairs A with both particles in one domain are integrated one after the
+ * other by SSA (Sec. 3.1.2, eq. SSA_ij), in increasing (lo id, hi id) order;
+ * then the remaining pairs A^c by SER on the updated state:
+ * Phi^Hybrid = Phi^{SER,A^c} o Phi^{SSA,A}.
+ * SSA pair update at fixed gamma_ij (exact Ornstein-Uhlenbeck step of
+ * p_ij = p_i - p_j), with a = +(2 gamma_ij/m) chi dt (eq. SSA_ij prints a
+ * minus sign; only the positive sign gives the decaying solution):
+ *   D = (e^{-a} - 1) p_ij + sigma sqrt(m (1 - e^{-2a}) / gamma_ij) G_ij,
+ *   p_i += D/2, p_j -= D/2, eps_i and eps_j -= dK_ij/2,
+ * with gamma_ij from the current internal energies and
+ * dK_ij = ((p_i')^2 + (p_j')^2 - p_i^2 - p_j^2)/(2m).
+ * ---------------------------------------------------------------------- */
+static int64_t domain_of(const or_params* P, const double* qi) {
+  int64_t c[3];
+  for (int d = 0; d < 3; ++d) {
+    double s = (double)P->ndom[d] / P->box[d];
+    double x = floor(qi[d] * s);
+    if (x < 0.0) x = 0.0;
+    if (x > (double)(P->ndom[d] - 1)) x = (double)(P->ndom[d] - 1);
+    c[d] = (int64_t)x;
+  }
+  return c[0] + (int64_t)P->ndom[0] * (c[1] + (int64_t)P->ndom[1] * c[2]);
+}
+
+static int ssa_pair(const or_params* P, int64_t i, int64_t j, double r, double* p, double* eps) {
+  double thi = or_theta_newton(P, eps[i], NULL), thj = or_theta_newton(P, eps[j], NULL);
+  if (!(eps[i] > 0.0) || !(eps[j] > 0.0) || !(thi > 0.0) || !(thj > 0.0)) return OR_ENEG_EINT;
+  double w = 1.0 - r / P->rc;
+  double chi = w * w;
+  double gij = 0.5 * P->gamma * P->kT_ref * (1.0 / thi + 1.0 / thj);
+  double sigma = sqrt(2.0 * P->gamma * P->kT_ref);
+  double a = 2.0 * gij / P->mass * chi * P->dt;
+  double decay = expm1(-a);                              /* e^{-a} - 1 */
+  double var = gij > 0.0 ? -expm1(-2.0 * a) / gij : 4.0 * chi * P->dt / P->mass;
+  double amp = sigma * sqrt(P->mass * var);
+  double G[3];
+  or_gauss3(P->seed, (uint32_t)P->replica, P->step, (uint32_t)i, (uint32_t)j, G);
+  double k0 = 0.0, k1 = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    double pij = p[3 * i + c] - p[3 * j + c];
+    double D = decay * pij + amp * G[c];
+    double pi = p[3 * i + c] + 0.5 * D, pj = p[3 * j + c] - 0.5 * D;
+    k0 += p[3 * i + c] * p[3 * i + c] + p[3 * j + c] * p[3 * j + c];
+    k1 += pi * pi + pj * pj;
+    p[3 * i + c] = pi;
+    p[3 * j + c] = pj;
+  }
+  double dK = (k1 - k0) / (2.0 * P->mass);
+  eps[i] -= 0.5 * dK;
+  eps[j] -= 0.5 * dK;
+  return OR_OK;
+}
+
+int or_fd_hybrid(const or_params* P, const double* q, double* p, double* eps,
+                 const int32_t* lohi, int64_t npairs) {
+  int32_t* cross = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(npairs > 0 ? npairs : 1));
+  if (!cross) return OR_ENOMEM;
+  int64_t nc = 0;
+  for (int64_t k = 0; k < npairs; ++k) {  /* lohi is sorted by (lo, hi) */
+    int64_t i = lohi[2 * k], j = lohi[2 * k + 1];
+    if (domain_of(P, &q[3 * i]) == domain_of(P, &q[3 * j])) {
+      double d[3];
+      double r = sqrt(separation(P, &q[3 * i], &q[3 * j], d));
+      int rc_ = ssa_pair(P, i, j, r, p, eps);
+      if (rc_ != OR_OK) { free(cross); return rc_; }
+    } else {
+      cross[2 * nc] = (int32_t)i;
+      cross[2 * nc + 1] = (int32_t)j;
+      ++nc;
+    }
+  }
+  or_params Q = *P;
+  Q.scheme = 0;
+  int rc_ = or_fd_pairs(&Q, q, p, eps, cross, nc, NULL);
+  free(cross);
+  return rc_;
+}
+
 /* FD sub-step alone at the current positions (pairs from the cell list). */
 int or_fd(const or_params* P, const double* q, double* p, double* eps, double* dp_out) {
   int32_t* pairs = NULL;
   int64_t np = 0;
   int rc_ = build_pairs(P, q, &pairs, &np);
   if (rc_ != OR_OK) return rc_;
-  rc_ = or_fd_pairs(P, q, p, eps, pairs, np, dp_out);
+  if (P->scheme == 2) {
+    double* p0 = dp_out ? (double*)malloc(sizeof(double) * 3 * (size_t)P->n) : NULL;
+    if (p0) memcpy(p0, p, sizeof(double) * 3 * (size_t)P->n);
+    rc_ = or_fd_hybrid(P, q, p, eps, pairs, np);
+    if (p0) {
+      for (int64_t k = 0; k < 3 * P->n; ++k) dp_out[k] = p[k] - p0[k];
+      free(p0);
+    }
+  } else {
+    rc_ = or_fd_pairs(P, q, p, eps, pairs, np, dp_out);
+  }
   free(pairs);
   return rc_;
 }
@@ -560,7 +655,8 @@ int or_step(or_params* P, double* q, double* p, double* eps, double* F, double* 
   or_forces_pairs(P, q, pairs, np, F, U);
   for (int64_t i = 0; i < n; ++i)
     for (int c = 0; c < 3; ++c) p[3 * i + c] = p[3 * i + c] + 0.5 * P->dt * F[3 * i + c];
-  rc_ = or_fd_pairs(P, q, p, eps, pairs, np, NULL);
+  rc_ = P->scheme == 2 ? or_fd_hybrid(P, q, p, eps, pairs, np)
+                      : or_fd_pairs(P, q, p, eps, pairs, np, NULL);
   free(pairs);
   P->step += 1;
   if (rc_ == OR_OK && P->project) {

@@ -30,6 +30,7 @@ class OrParams(C.Structure):
         ("project", C.c_int32), ("model", C.c_int32), ("potential", C.c_int32),
         ("pad_", C.c_int32),
         ("E0", C.c_double), ("eps_lj", C.c_double), ("r_lj", C.c_double),
+        ("ndom", C.c_int32 * 3), ("pad2_", C.c_int32),
     ]
 
 
@@ -90,7 +91,7 @@ def _d(a):
 def make_params(n, box, *, periodic=(1, 1, 1), mass=1.0, rc=1.0, a=25.0, gamma=4.5, kT_ref=1.0,
                 dt=0.01, eos=0, cv=100.0, eos_n=50.0, eos_omega=2.0, eos_c0=10.0, seed=7, step=0,
                 replica=0, scheme=0, project=0, E0=0.0, model=0, potential=0, eps_lj=1.0,
-                r_lj=1.0) -> OrParams:
+                r_lj=1.0, ndom=(1, 1, 1)) -> OrParams:
     P = OrParams()
     P.box = (C.c_double * 3)(*[float(x) for x in box])
     P.mass, P.rc, P.a, P.gamma, P.kT_ref, P.dt = mass, rc, a, gamma, kT_ref, dt
@@ -100,6 +101,7 @@ def make_params(n, box, *, periodic=(1, 1, 1), mass=1.0, rc=1.0, a=25.0, gamma=4
     P.eos, P.replica, P.scheme = int(eos), int(replica), int(scheme)
     P.project, P.model, P.potential = int(project), int(model), int(potential)
     P.E0, P.eps_lj, P.r_lj = float(E0), float(eps_lj), float(r_lj)
+    P.ndom = (C.c_int32 * 3)(*[int(x) for x in ndom])
     return P
 
 

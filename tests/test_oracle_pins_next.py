@@ -210,3 +210,73 @@ def test_config_temperature_terms_against_finite_differences(potential):
             grad[i, c] = (Up - Um) / (2 * h)
     assert abs(g2 - (grad ** 2).sum()) < 1e-5 * g2
     assert abs(lap - lap_fd) < 1e-3 * abs(lap)
+
+
+# ---------------------------------------------------------------------------
+# Hybrid (Sec. 3.2.2): SSA inside domains, SER across them
+# ---------------------------------------------------------------------------
+def test_hybrid_with_single_particle_domains_is_ser():
+    """Domains too small to hold two interacting particles leave every pair
+    to SER: the Hybrid step equals the SER step bit for bit."""
+    n = 300
+    box, q, p, e = _state(n, 21)
+    fine = [int(np.ceil(b / 0.05)) for b in box]
+    Ph = O.make_params(n, box, scheme=2, ndom=fine)
+    Ps = O.make_params(n, box, scheme=0)
+    # domains of side < 0.05 hold two particles with probability ~1e-7 each
+    Sh, Ss = O.State(Ph, q, p, e), O.State(Ps, q, p, e)
+    Sh.step(1)
+    Ss.step(1)
+    qq = Sh.q
+    dom = np.stack([np.minimum((qq[:, d] * fine[d] / box[d]).astype(int), fine[d] - 1)
+                    for d in range(3)], axis=1)
+    pairs = O.pairs(Ph, qq, "cells")
+    same = (dom[pairs[:, 0]] == dom[pairs[:, 1]]).all(axis=1)
+    if same.any():
+        pytest.skip("a pair fell inside one fine domain")
+    assert np.array_equal(Sh.p, Ss.p) and np.array_equal(Sh.eps, Ss.eps)
+
+
+@pytest.mark.parametrize("ndom", [(1, 1, 1), (2, 2, 2), (3, 1, 2)])
+def test_hybrid_conserves_energy_and_momentum(ndom):
+    n = 400
+    box, q, p, e = _state(n, 22)
+    P = O.make_params(n, box, a=0.0, scheme=2, ndom=ndom, dt=0.01)
+    S = O.State(P, q, p, e)
+    E0 = S.energies()[3]
+    P0 = S.p.sum(axis=0)
+    rc, rec = S.step(20, record=True)
+    assert rc == 0
+    assert np.abs(rec[:, 3] - E0).max() < 1e-12 * abs(E0)
+    assert np.abs(S.p.sum(axis=0) - P0).max() < 1e-11
+
+
+def test_ssa_pair_update_is_the_exact_ornstein_uhlenbeck_step():
+    """Two particles alone: one SSA update at fixed gamma_ij must sample the
+    exact solution of d p_ij = -(2 gamma chi/m) p_ij dt + 2 sigma sqrt(chi) dW,
+    mean e^{-a} p_ij and variance (sigma^2 m / gamma)(1 - e^{-2a}) per
+    component with a = (2 gamma chi/m) dt (Sec. 3.1.2 with the sign of a
+    fixed); a sign error or a lost factor 2 fails the moments."""
+    box = [6.0, 6.0, 6.0]
+    q = np.array([[1.0, 1.0, 1.0], [1.3, 1.1, 1.0]])
+    p0 = np.array([[1.5, -0.5, 0.2], [-0.7, 0.4, 0.3]])
+    e0 = np.array([100.0, 100.0])
+    r = np.linalg.norm(q[0] - q[1])
+    gamma, kT, m, dt = 4.5, 1.0, 1.0, 0.05
+    chi = (1 - r) ** 2
+    gij = gamma * kT / 2 * (1 / 1.0 + 1 / 1.0)  # T_i = eps/cv = 1
+    a = 2 * gij / m * chi * dt
+    sigma2 = 2 * gamma * kT
+    out = []
+    for step in range(6000):
+        P = O.make_params(2, box, a=0.0, scheme=2, ndom=(1, 1, 1), dt=dt, gamma=gamma, step=step)
+        rc, pp, ee, _ = O.fd(P, q, p0, e0)
+        assert rc == 0
+        out.append((pp[0] - pp[1]))
+    out = np.array(out)
+    pij0 = p0[0] - p0[1]
+    mean_exp = np.exp(-a) * pij0
+    var_exp = sigma2 * m / gij * (1 - np.exp(-2 * a))
+    se = np.sqrt(var_exp / len(out))
+    assert np.abs(out.mean(axis=0) - mean_exp).max() < 5 * se
+    assert np.abs(out.var(axis=0) / var_exp - 1).max() < 0.08
