@@ -64,6 +64,14 @@ extern "C" {
 /* Fluctuation/dissipation scheme. */
 #define DPDE_SCHEME_SER 0    /* Sec. 3.2.1, eqs. SER_p, SER_eint_discretization   */
 #define DPDE_SCHEME_SEM 1    /* Sec. 3.1.1, eq. SEM_fd (not energy conserving)    */
+#define DPDE_SCHEME_HYBRID 2 /* Sec. 3.2.2: the pairs inside one of ndom[0] x      */
+                             /* ndom[1] x ndom[2] equal spatial domains (the      */
+                             /* paper's processors) by SSA (Sec. 3.1.2, eq.       */
+                             /* SSA_ij, exponent a = +(2 gamma_ij/m) chi dt), one  */
+                             /* after the other in increasing (lo id, hi id)      */
+                             /* order; then the other pairs by SER on the updated  */
+                             /* state.  Results depend on the decomposition, as   */
+                             /* the paper notes.  Vector model, stored increments */
 
 /* Direction of friction and noise (Sec. 2.1). */
 #define DPDE_MODEL_VECTOR 0  /* along v_ij with a 3-d Gaussian G_ij (eq. DPDE,    */
@@ -116,6 +124,7 @@ typedef struct dpde_params {
   uint32_t replica;     /* folded into the noise key (seed_hi ^ replica)        */
   int32_t neighbor_cap; /* list capacity per particle (0: 64, or 96 with skin)  */
   int32_t flags;        /* DPDE_FLAG_* bits                                     */
+  int32_t ndom[3];      /* Hybrid: domains per dimension (>= 1)                 */
 } dpde_params;
 
 /* flags: regenerate G_ij^n in the second SER sweep, as the paper does to avoid

@@ -11,7 +11,7 @@ import torch  # noqa: F401
 
 from . import _lib
 from ._lib import (DpdeError, EOS_EINSTEIN, EOS_LINEAR, FP32, FP64, MODEL_PROJECTED,
-                   MODEL_VECTOR, POT_LJ, POT_SOFT, SCHEME_SEM, SCHEME_SER, THETA_MLP,
+                   MODEL_VECTOR, POT_LJ, POT_SOFT, SCHEME_HYBRID, SCHEME_SEM, SCHEME_SER, THETA_MLP,
                    THETA_MLP_NEWTON, THETA_NEWTON)
 
 _lib.load()

@@ -17,7 +17,7 @@ DPDE_ENEG_EINT, DPDE_EEOS, DPDE_EOVERFLOW, DPDE_ENONFINITE = -5, -6, -7, -8
 FP64, FP32 = 0, 1
 EOS_LINEAR, EOS_EINSTEIN = 0, 1
 THETA_NEWTON, THETA_MLP, THETA_MLP_NEWTON = 0, 1, 2
-SCHEME_SER, SCHEME_SEM = 0, 1
+SCHEME_SER, SCHEME_SEM, SCHEME_HYBRID = 0, 1, 2
 MODEL_VECTOR, MODEL_PROJECTED = 0, 1
 POT_SOFT, POT_LJ = 0, 1
 DPDE_FLAG_REGENERATE_NOISE = 1
@@ -48,6 +48,7 @@ class Params(C.Structure):
         ("scheme", C.c_int32), ("model", C.c_int32), ("potential", C.c_int32),
         ("replica", C.c_uint32), ("neighbor_cap", C.c_int32),
         ("flags", C.c_int32),
+        ("ndom", C.c_int32 * 3),
     ]
 
 

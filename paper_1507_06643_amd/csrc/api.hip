@@ -19,6 +19,7 @@
 #include "bin.h"
 #include "mlp.h"
 #include "pairs.h"
+#include "hybrid.h"
 
 using namespace dpde;
 
@@ -97,6 +98,16 @@ struct dpde_handle {
   Fix* partials = nullptr;
   double* E0 = nullptr;   // per-replica target energy of the projection
   double* Li = nullptr;   // per-particle Laplacian share of U
+  // Hybrid: domain of each particle, domain order, bucket offsets
+  bool hybrid = false;
+  int64_t ndoms = 0;
+  int dscan_tiles = 0;
+  uint32_t* dom = nullptr;
+  uint32_t* dperm = nullptr;
+  uint32_t* dcount = nullptr;
+  uint32_t* dstart = nullptr;
+  uint32_t* dscan_tmp = nullptr;
+  BuildCtl* always = nullptr;  // a build control that always says 'now'
   double* rec = nullptr;
   double* hist = nullptr;
   int64_t hist_cap = 0;
@@ -195,6 +206,15 @@ int check_params(const dpde_params* P, bool first) {
     return fail(DPDE_EINVAL, "unknown precision %d", P->precision);
   if (P->model != DPDE_MODEL_VECTOR && P->model != DPDE_MODEL_PROJECTED)
     return fail(DPDE_EINVAL, "unknown model %d", P->model);
+  if (P->scheme == DPDE_SCHEME_HYBRID) {
+    if (P->model != DPDE_MODEL_VECTOR)
+      return fail(DPDE_EINVAL, "the Hybrid scheme is implemented for the vector model");
+    if (P->flags & DPDE_FLAG_REGENERATE_NOISE)
+      return fail(DPDE_EINVAL, "the Hybrid scheme stores the SER increments");
+    for (int d = 0; d < 3; ++d)
+      if (P->ndom[d] < 1 || P->ndom[d] > (1 << 20))
+        return fail(DPDE_EINVAL, "ndom[%d] must be in [1, 2^20]", d);
+  }
   if (P->potential == DPDE_POT_LJ) {
     if (!(std::isfinite(P->eps_lj) && P->eps_lj > 0 && std::isfinite(P->r_lj) && P->r_lj > 0))
       return fail(DPDE_EINVAL, "LJ needs eps_lj > 0 and r_lj > 0");
@@ -205,7 +225,8 @@ int check_params(const dpde_params* P, bool first) {
     return fail(DPDE_EINVAL, "unknown flags 0x%x", P->flags);
   if (P->theta_mode < 0 || P->theta_mode > 2)
     return fail(DPDE_EINVAL, "unknown theta_mode %d", P->theta_mode);
-  if (P->scheme != DPDE_SCHEME_SER && P->scheme != DPDE_SCHEME_SEM)
+  if (P->scheme != DPDE_SCHEME_SER && P->scheme != DPDE_SCHEME_SEM &&
+      P->scheme != DPDE_SCHEME_HYBRID)
     return fail(DPDE_EINVAL, "unknown scheme %d", P->scheme);
   if (P->neighbor_cap < 0 || P->neighbor_cap > 1024)
     return fail(DPDE_EINVAL, "neighbor_cap must be in [0, 1024]");
@@ -227,6 +248,10 @@ int geometry(const dpde_params* P, Geo& g) {
   }
   g.key0 = (uint32_t)P->seed;
   g.key1 = (uint32_t)(P->seed >> 32) ^ P->replica;
+  for (int d = 0; d < 3; ++d) {
+    g.ndom[d] = P->scheme == DPDE_SCHEME_HYBRID ? P->ndom[d] : 1;
+    g.dscale[d] = (double)g.ndom[d] / P->box[d];
+  }
   return DPDE_OK;
 }
 
@@ -303,6 +328,18 @@ int allocate(dpde_handle* h) {
     return rc;
   h->skin.stride = n;
   h->skin.cap = h->phys.cap;
+  if (h->hybrid) {
+    h->dscan_tiles = (int)((h->ndoms + kScanTile - 1) / kScanTile);
+    if (h->dscan_tiles > 1024 * 8) return fail(DPDE_EINVAL, "too many domains");
+    if ((rc = dalloc(h, &h->dom, n)) || (rc = dalloc(h, &h->dperm, n)) ||
+        (rc = dalloc(h, &h->dcount, h->ndoms + 1)) || (rc = dalloc(h, &h->dstart, h->ndoms + 1)) ||
+        (rc = dalloc(h, &h->dscan_tmp, (size_t)h->dscan_tiles + 1)) ||
+        (rc = dalloc(h, &h->always, 1)))
+      return rc;
+    HIPCHK(hipMemset(h->dcount, 0, (h->ndoms + 1) * sizeof(uint32_t)));
+    static const BuildCtl now{0ull, 1u, 0u};
+    HIPCHK(hipMemcpy(h->always, &now, sizeof(BuildCtl), hipMemcpyHostToDevice));
+  }
   HIPCHK(hipMemset(h->qref, 0, n * sizeof(QRef)));
   HIPCHK(hipMemset(h->ctl, 0, sizeof(BuildCtl)));
   HIPCHK(hipMemset(h->builds, 0, sizeof(unsigned long long)));
@@ -408,6 +445,33 @@ bool eos_inline(const dpde_handle* h) {
   return h->phys.eos == DPDE_EOS_LINEAR || h->phys.theta_mode == DPDE_THETA_NEWTON;
 }
 
+// Hybrid (Sec. 3.2.2): particles binned by domain in identifier order, then
+// one lane per domain runs SSA over the domain's pairs.
+template <bool B>
+void enqueue_hybrid_ssa(dpde_handle* h) {
+  const int b = h->aux_block;
+  const int64_t n = h->n;
+  const BuildCtl* now = h->always;
+  launch(h, "dom_key", k_dom_key<B>, blocks(n, b), b, h->cur, n, (const Geo*)h->geo, h->dom,
+         h->key, h->ticket, h->idk, h->dcount, (const uint32_t*)h->status);
+  // the scan writes dstart[0..ndoms), and dstart[ndoms] = n closes the last domain
+  launch(h, "dom_scan_tiles", k_scan_tiles, h->dscan_tiles, kScanThreads,
+         (const uint32_t*)h->dcount, h->ndoms, h->dscan_tmp, now, 0.0);
+  launch(h, "dom_scan_tile_sums", k_scan_tile_sums, 1, 1024, h->dscan_tmp, h->dscan_tiles, now,
+         0.0);
+  launch(h, "dom_scan_apply", k_scan_apply, h->dscan_tiles, kScanThreads, h->dcount, h->ndoms,
+         (const uint32_t*)h->dscan_tmp, h->dstart, now, 0.0);
+  launch(h, "dom_scatter", k_scatter, blocks(n, b), b, (const uint32_t*)h->key,
+         (const uint32_t*)h->ticket, (const uint32_t*)h->dstart, n, h->dperm, now, 0.0,
+         (const uint32_t*)h->status);
+  launch(h, "dom_sort", k_cell_sort, blocks(h->ndoms, b), b, (const uint32_t*)h->dstart,
+         h->ndoms, h->dperm, (const uint32_t*)h->idk, now, 0.0, (const uint32_t*)h->status);
+  launch(h, "ssa_domains", k_ssa<B>, blocks(h->ndoms, 64), 64, h->cur, h->nl,
+         (const uint32_t*)h->dperm, (const uint32_t*)h->dstart, h->ndoms,
+         (const uint32_t*)h->dom, (const Geo*)h->geo, h->phys, (const uint64_t*)h->d_step,
+         h->status);
+}
+
 template <bool B, int PR>
 void enqueue_fd_t(dpde_handle* h) {
   const int b = h->pair_block;
@@ -415,14 +479,16 @@ void enqueue_fd_t(dpde_handle* h) {
   const int inl = eos_inline(h) ? 1 : 0;
   const uint64_t* d_step = h->d_step;
   const int store = h->regen ? 0 : 1;
+  const uint32_t* dom = h->hybrid ? (const uint32_t*)h->dom : nullptr;
+  if (h->hybrid) enqueue_hybrid_ssa<B>(h);
   if (h->phys.scheme == DPDE_SCHEME_SEM) {
     launch(h, "pass_b_sem", k_pass_b<B, PR, 1>, blocks(n * kSub, b), b, h->cur, h->nl, n,
-           (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, 0, h->status);
+           (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, 0, dom, h->status);
     launch(h, "apply_sem", k_apply_sem, blocks(n, h->aux_block), h->aux_block, h->cur, n, h->phys,
            (const Vec4*)h->dpi, (const double*)h->deps, inl, h->alt.r, h->status);
   } else {
     launch(h, "pass_b_ser", k_pass_b<B, PR, 0>, blocks(n * kSub, b), b, h->cur, h->nl, n,
-           (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, store, h->status);
+           (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, store, dom, h->status);
     if (h->regen)
       launch(h, "pass_c_ser", k_pass_c<B, PR, 1>, blocks(n * kSub, b), b, h->cur, h->nl, n,
              (const Geo*)h->geo, h->phys, d_step, (const Vec4*)h->dpi, (const Vec4*)h->hv, inl,
@@ -594,11 +660,15 @@ int create(const dpde_params* params, int nrep, const int64_t* offsets, const do
     g.first = h->offsets[r];
     g.n = params[r].n;
     cells += (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+    g.dom_base = h->ndoms;
+    h->ndoms += (int64_t)g.ndom[0] * g.ndom[1] * g.ndom[2];
     h->geo_h.push_back(g);
   }
   h->n = h->offsets[nrep];
   h->ncells = cells;
+  h->hybrid = params[0].scheme == DPDE_SCHEME_HYBRID;
   if (cells >= ((int64_t)1 << 31)) { release(h); return fail(DPDE_EINVAL, "too many cells"); }
+  if (h->ndoms >= ((int64_t)1 << 31) / 2) { release(h); return fail(DPDE_EINVAL, "too many domains"); }
   if (hipGetDevice(&h->device) != hipSuccess) { release(h); return fail(DPDE_EHIP, "no HIP device"); }
   if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
     release(h);

@@ -29,6 +29,10 @@ struct Geo {
   int64_t first;       // first row (identifier space) of the replica
   int64_t n;           // particles in the replica
   uint32_t key0, key1; // Philox key: seed low word, seed high word ^ replica
+  double dscale[3];    // Hybrid domains per unit length: ndom / box
+  int32_t ndom[3];     // Hybrid domains per dimension
+  int32_t pad_dom;
+  int64_t dom_base;    // global index of the replica's domain 0
 };
 
 // Physical parameters shared by all replicas of a handle.

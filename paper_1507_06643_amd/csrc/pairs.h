@@ -598,7 +598,7 @@ template <bool BATCH, int PREC, int SCHEME>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
     const uint64_t* __restrict__ d_step, Vec4* __restrict__ dpi, Vec4* __restrict__ hv,
-    double* __restrict__ deps, int store, uint32_t* status) {
+    double* __restrict__ deps, int store, const uint32_t* __restrict__ dom, uint32_t* status) {
   const Lanes L = lanes();
   if (L.i >= n) return;  // uniform in the group
   if (status_set(status)) return;
@@ -609,15 +609,31 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
   const Geo& g = geo[BATCH ? a.rep : 0u];
   const uint32_t nn = nl.count[i];
   const int64_t st = nl.stride;
+  // Hybrid: pairs inside one domain were integrated by SSA; their entries
+  // carry a zero increment here
+  const uint32_t dom_i = dom ? dom[i] : 0u;
   double ax = 0.0, ay = 0.0, az = 0.0, de = 0.0;
   // software pipeline: the record of the lane's next neighbour is requested
   // before the pair term of the current one is computed
+  uint32_t jn = (uint32_t)L.sub < nn ? nl.idx[(int64_t)L.sub * st + i] : 0u;
   Rec nb;
-  if ((uint32_t)L.sub < nn) nb = R[nl.idx[(int64_t)L.sub * st + i]];
+  if ((uint32_t)L.sub < nn) nb = R[jn];
   for (uint32_t k = L.sub; k < nn; k += kSub) {
     const int64_t e = (int64_t)k * st + i;
     const Rec b = nb;
-    if (k + kSub < nn) nb = R[nl.idx[e + kSub * st]];
+    const uint32_t j = jn;
+    if (k + kSub < nn) {
+      jn = nl.idx[e + kSub * st];
+      nb = R[jn];
+    }
+    if (dom && dom[j] == dom_i) {
+      if (store) {
+        nl.dex[e] = 0.0;
+        nl.dey[e] = 0.0;
+        nl.dez[e] = 0.0;
+      }
+      continue;
+    }
     double vx, vy, vz;
     PairOut o;
     pair_from_records<PREC>(P, g, a, b, step, vx, vy, vz, o);

@@ -38,6 +38,7 @@ class Config:
     eps_lj: float = 1.0
     r_lj: float = 1.0
     project: bool = False
+    ndom: Sequence[int] = (1, 1, 1)
     precision: int = L.FP64
     theta_mode: int = L.THETA_NEWTON
     scheme: int = L.SCHEME_SER
@@ -62,6 +63,7 @@ class Config:
                                                        int(self.theta_mode), int(self.scheme))
         P.replica, P.neighbor_cap = int(self.replica), int(self.neighbor_cap)
         P.flags = L.DPDE_FLAG_PROJECT_EINT if self.project else 0
+        P.ndom = (C.c_int32 * 3)(*[int(x) for x in self.ndom])
         return P
 
 

@@ -154,3 +154,47 @@ def test_soft_config_terms(dp):
     assert abs(en[10] - g2) <= 1e-11 * g2
     assert abs(en[11] - lap) <= 1e-11 * abs(lap)
     s.close()
+
+
+# ---------------------------------------------------------------------------
+# Hybrid (Sec. 3.2.2): SSA inside spatial domains, SER across them
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ndom", [(1, 1, 1), (4, 4, 4), (3, 2, 5)])
+def test_hybrid_step_parity(dp, ndom):
+    n = 3000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=51)
+    kw = dict(dt=0.01, scheme=2, ndom=ndom)
+    errs, en, eo, _, _ = _step_vs_oracle(dp, q, p, e, [L] * 3, kw, kw)
+    assert max(errs) < TOL, errs
+    assert abs(en[3] - eo[3]) <= TOL * abs(eo[3])
+
+
+def test_hybrid_with_fine_domains_equals_ser(dp):
+    n = 3000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=52)
+    fine = [int(np.ceil(L / 0.05))] * 3
+    a = dp.System(dp.Config(n=n, box=[L] * 3, scheme=2, ndom=fine), q, p, e)
+    b = dp.System(dp.Config(n=n, box=[L] * 3, scheme=0), q, p, e)
+    a.step(3)
+    b.step(3)
+    qa, pa, ea, _ = _gpu_state(a)
+    qb, pb, eb, _ = _gpu_state(b)
+    # domains of side 0.05 hold two particles with probability ~1e-7 each
+    assert np.array_equal(pa, pb) and np.array_equal(ea, eb)
+    a.close()
+    b.close()
+
+
+def test_hybrid_conserves_energy(dp):
+    n = 4000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=53)
+    s = dp.System(dp.Config(n=n, box=[L] * 3, a=0.0, scheme=2, ndom=(3, 3, 3)), q, p, e)
+    E0 = s.energies()[3]
+    s.step(200)
+    h = s.history()
+    s.close()
+    assert np.abs(h[:, 3] - E0).max() < 1e-12 * abs(E0)
+    assert np.abs(h[:, 4:7]).max() < 1e-10
