@@ -317,6 +317,41 @@ def shock_leg(dp, W, steps=5000, graph_steps=100, nslab=20):
             "final_profile": profile(qg[:, 0], pg, eg)}
 
 
+def next_rows_leg(dp, W, n=N_1M, steps=100, warmup=20):
+    """Throughput at N = 1M of the schemes beyond plain SER: SEM with the
+    internal-energy projection (Sec. 4.2), friction and noise along e_ij,
+    the splined LJ at the paper's density (eq. Ep), and Hybrid with 32^3
+    domains (Sec. 3.2.2)."""
+    out = {}
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=20260101)
+    cases = [
+        ("sem_projected", dict(scheme=dp.SCHEME_SEM, project=True, dt=0.005)),
+        ("projected_model_ser", dict(model=dp.MODEL_PROJECTED, dt=0.005)),
+        ("hybrid_32cubed_domains", dict(scheme=dp.SCHEME_HYBRID, ndom=(32, 32, 32), dt=0.005)),
+    ]
+    for name, kw in cases:
+        log(f"[bench] next rows: {name}")
+        s = dp.System(dp.Config(n=n, box=[L] * 3, **kw), q, p, e)
+        secs, h = timed(s, steps, warmup)
+        out[name] = {"value": n * steps / secs, "ms_per_step": 1e3 * secs / steps,
+                     "energy_drift_per_1e4_steps": drift_per_1e4(h)}
+        s.close()
+    side = int(round(n ** (1.0 / 3.0)))
+    ql, pl, el, box = W.lattice_state(side, 0.8095, eps0=50.0, seed=20260105)
+    log(f"[bench] next rows: lj_density_0.8095 (N={side ** 3})")
+    s = dp.System(dp.Config(n=side ** 3, box=box, potential=dp.POT_LJ, rc=2.5, cv=50.0, gamma=8.0,
+                            dt=0.002, neighbor_cap=128, project=True), ql, pl, el)
+    secs, h = timed(s, steps, warmup)
+    out["lj_density_0.8095"] = {"value": side ** 3 * steps / secs,
+                                "ms_per_step": 1e3 * secs / steps, "n": side ** 3,
+                                "T_kin": float(h[:, 7].mean()),
+                                "T_pot": float(h[:, 10].mean() / h[:, 11].mean()),
+                                "T_int": float(h[:, 8].mean())}
+    s.close()
+    return out
+
+
 def cpu_baseline(W, n, steps, eos, dt, eps0):
     import oracle as O
     L = W.cubic_side(n)
@@ -472,6 +507,7 @@ def main():
         line["batched_replicas"] = batched_leg(dp, W)
         log("[bench] shock: N=480000, 5000 steps, FP32 pair terms")
         line["shock"] = shock_leg(dp, W)
+        line["next_rows"] = next_rows_leg(dp, W)
     if not args.no_drift:
         log("[bench] energy drift: GPU vs oracle, N=1000")
         line["drift_vs_oracle"] = drift_vs_oracle(dp, W, list(range(1, args.drift_seeds + 1)))

@@ -421,7 +421,7 @@ void enqueue_bin(dpde_handle* h, int kick) {
          blocks(n * kSub, pb), pb,
          h->cur, (const uint32_t*)h->cell_start, n, (const Geo*)h->geo, h->rs2, h->skin, ctl, hs2,
          h->status);
-  launch(h, "sort_skin", h->skin.cap > 64 ? k_sort_skin<128> : k_sort_skin<64>, blocks(n, 256),
+  launch(h, "sort_skin", h->skin.cap > 96 ? k_sort_skin<128> : k_sort_skin<64>, blocks(n, 256),
          256, n, h->skin, (const uint32_t*)h->slot, ctl, hs2, (const uint32_t*)h->status);
 }
 
@@ -472,7 +472,7 @@ void enqueue_hybrid_ssa(dpde_handle* h) {
          h->status);
 }
 
-template <bool B, int PR>
+template <bool B, int PR, int MD>
 void enqueue_fd_t(dpde_handle* h) {
   const int b = h->pair_block;
   const int64_t n = h->n;
@@ -482,19 +482,19 @@ void enqueue_fd_t(dpde_handle* h) {
   const uint32_t* dom = h->hybrid ? (const uint32_t*)h->dom : nullptr;
   if (h->hybrid) enqueue_hybrid_ssa<B>(h);
   if (h->phys.scheme == DPDE_SCHEME_SEM) {
-    launch(h, "pass_b_sem", k_pass_b<B, PR, 1>, blocks(n * kSub, b), b, h->cur, h->nl, n,
+    launch(h, "pass_b_sem", k_pass_b<B, PR, 1, MD>, blocks(n * kSub, b), b, h->cur, h->nl, n,
            (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, 0, dom, h->status);
     launch(h, "apply_sem", k_apply_sem, blocks(n, h->aux_block), h->aux_block, h->cur, n, h->phys,
            (const Vec4*)h->dpi, (const double*)h->deps, inl, h->alt.r, h->status);
   } else {
-    launch(h, "pass_b_ser", k_pass_b<B, PR, 0>, blocks(n * kSub, b), b, h->cur, h->nl, n,
+    launch(h, "pass_b_ser", k_pass_b<B, PR, 0, MD>, blocks(n * kSub, b), b, h->cur, h->nl, n,
            (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, store, dom, h->status);
     if (h->regen)
-      launch(h, "pass_c_ser", k_pass_c<B, PR, 1>, blocks(n * kSub, b), b, h->cur, h->nl, n,
+      launch(h, "pass_c_ser", k_pass_c<B, PR, 1, MD>, blocks(n * kSub, b), b, h->cur, h->nl, n,
              (const Geo*)h->geo, h->phys, d_step, (const Vec4*)h->dpi, (const Vec4*)h->hv, inl,
              h->alt.r, h->status);
     else
-      launch(h, "pass_c_ser", k_pass_c<B, PR, 0>, blocks(n * kSub, b), b, h->cur, h->nl, n,
+      launch(h, "pass_c_ser", k_pass_c<B, PR, 0, MD>, blocks(n * kSub, b), b, h->cur, h->nl, n,
              (const Geo*)h->geo, h->phys, d_step, (const Vec4*)h->dpi, (const Vec4*)h->hv, inl,
              h->alt.r, h->status);
   }
@@ -506,13 +506,19 @@ void enqueue_fd_t(dpde_handle* h) {
     enqueue_theta_mlp(h->mlp, h->stream, h->cur.eps, &h->cur.r->invT, 8, n, h->phys, h->status);
 }
 
+template <bool B, int PR>
+void enqueue_fd_m(dpde_handle* h) {
+  if (h->phys.model == DPDE_MODEL_PROJECTED) enqueue_fd_t<B, PR, 1>(h);
+  else enqueue_fd_t<B, PR, 0>(h);
+}
+
 void enqueue_fd(dpde_handle* h) {
   if (h->batch) {
-    if (h->phys.precision == DPDE_FP32) enqueue_fd_t<true, PREC_F32>(h);
-    else enqueue_fd_t<true, PREC_F64>(h);
+    if (h->phys.precision == DPDE_FP32) enqueue_fd_m<true, PREC_F32>(h);
+    else enqueue_fd_m<true, PREC_F64>(h);
   } else {
-    if (h->phys.precision == DPDE_FP32) enqueue_fd_t<false, PREC_F32>(h);
-    else enqueue_fd_t<false, PREC_F64>(h);
+    if (h->phys.precision == DPDE_FP32) enqueue_fd_m<false, PREC_F32>(h);
+    else enqueue_fd_m<false, PREC_F64>(h);
   }
 }
 

@@ -495,7 +495,7 @@ struct PairOut {
 // e_ij = d_ij / r with one scalar normal xi_ij = xi_ji per pair,
 //   dp_ij = (-gamma_ij chi (e_ij . v_ij) dt + sigma w xi_ij sqrt(dt)) e_ij,
 // antisymmetric through e_ji = -e_ij; a coincident pair does not interact.
-template <int PREC>
+template <int PREC, int MODEL>
 __device__ __forceinline__ void ser_pair(const Phys& P, const Geo& g, double dx, double dy,
                                          double dz, double r2, double vx, double vy, double vz,
                                          double invT_sum, uint32_t idi, uint32_t idj,
@@ -508,7 +508,7 @@ __device__ __forceinline__ void ser_pair(const Phys& P, const Geo& g, double dx,
     const double r = r2 * ir;
     double w = 1.0 - r * P.inv_rc;
     const double gij = P.gkT_half * invT_sum;
-    if (P.model == 1) {
+    if constexpr (MODEL == 1) {
       if (!(r2 > 0.0)) w = 0.0;
       const double chi = w * w;
       const double ex = dx * ir, ey = dy * ir, ez = dz * ir;
@@ -543,7 +543,7 @@ __device__ __forceinline__ void ser_pair(const Phys& P, const Geo& g, double dx,
     float w = 1.0f - r * (float)P.inv_rc;
     const float gij = (float)(P.gkT_half * invT_sum);
     const float v0 = (float)vx, v1 = (float)vy, v2 = (float)vz;
-    if (P.model == 1) {
+    if constexpr (MODEL == 1) {
       if (!(r > 0.0f)) w = 0.0f;
       const float chi = w * w;
       const float ir = r > 0.0f ? 1.0f / r : 0.0f;
@@ -578,7 +578,7 @@ __device__ __forceinline__ void ser_pair(const Phys& P, const Geo& g, double dx,
 }
 
 // dp_ij of neighbour j seen from the record of particle i.
-template <int PREC>
+template <int PREC, int MODEL>
 __device__ __forceinline__ void pair_from_records(const Phys& P, const Geo& g, const Rec& a,
                                                   const Rec& b, uint64_t step, double& vx,
                                                   double& vy, double& vz, PairOut& o) {
@@ -588,13 +588,13 @@ __device__ __forceinline__ void pair_from_records(const Phys& P, const Geo& g, c
   vx = a.px * P.inv_mass - b.px * P.inv_mass;
   vy = a.py * P.inv_mass - b.py * P.inv_mass;
   vz = a.pz * P.inv_mass - b.pz * P.inv_mass;
-  ser_pair<PREC>(P, g, dx, dy, dz, r2, vx, vy, vz, a.invT + b.invT, a.id, b.id, step, o);
+  ser_pair<PREC, MODEL>(P, g, dx, dy, dz, r2, vx, vy, vz, a.invT + b.invT, a.id, b.id, step, o);
 }
 
 // ---------------------------------------------------------------------------
 // Pass B (SER sweep 1, and the whole SEM update of eq. SEM_fd).
 // ---------------------------------------------------------------------------
-template <bool BATCH, int PREC, int SCHEME>
+template <bool BATCH, int PREC, int SCHEME, int MODEL>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
     const uint64_t* __restrict__ d_step, Vec4* __restrict__ dpi, Vec4* __restrict__ hv,
@@ -636,7 +636,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
     }
     double vx, vy, vz;
     PairOut o;
-    pair_from_records<PREC>(P, g, a, b, step, vx, vy, vz, o);
+    pair_from_records<PREC, MODEL>(P, g, a, b, step, vx, vy, vz, o);
     ax += o.dp[0];
     ay += o.dp[1];
     az += o.dp[2];
@@ -679,7 +679,7 @@ __device__ __forceinline__ double inv_temperature(const Phys& P, double eps, uin
 // next 1/T_i.  The new records go to `out`, never over the records this pass
 // gathers from.
 // ---------------------------------------------------------------------------
-template <bool BATCH, int PREC, int REGEN>
+template <bool BATCH, int PREC, int REGEN, int MODEL>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
     const uint64_t* __restrict__ d_step, const Vec4* __restrict__ dpi,
@@ -719,7 +719,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
       const Rec b = R[j];
       double vx, vy, vz;
       PairOut o;
-      pair_from_records<PREC>(P, g, a, b, step, vx, vy, vz, o);
+      pair_from_records<PREC, MODEL>(P, g, a, b, step, vx, vy, vz, o);
       ex = o.dp[0];
       ey = o.dp[1];
       ez = o.dp[2];
