@@ -274,6 +274,7 @@ void physics(const dpde_params* P, Phys& ph) {
   ph.dsigma2_m = (P->model == DPDE_MODEL_PROJECTED ? 1.0 : 3.0) * ph.sigma * ph.sigma / P->mass;
   ph.model = P->model;
   ph.potential = P->potential;
+  ph.reach = P->rc + 2.0 * P->skin;
   ph.project = (P->flags & DPDE_FLAG_PROJECT_EINT) != 0;
   ph.lj4e = 4.0 * P->eps_lj;
   ph.r_lj2 = P->r_lj * P->r_lj;

@@ -47,6 +47,9 @@ struct Phys {
   double mlp_in_c, mlp_in_s, mlp_out_c, mlp_out_s, mlp_eps_lo, mlp_eps_hi;
   // splined LJ: v = c12/r^12 - c6/r^6 - v_c - dv_c (r - rc), r_lj2 = r_lj^2
   double lj4e, r_lj2, lj_vc, lj_dvc;
+  // farthest a listed neighbour can be: rc + 2 skin (built within rc + skin,
+  // each particle moves at most skin/2 before the next build)
+  double reach;
   int32_t eos, theta_mode, precision, scheme;
   int32_t cap;              // neighbour list capacity per particle
   int32_t model;            // 0: along v_ij (3-d G), 1: along e_ij (scalar xi)

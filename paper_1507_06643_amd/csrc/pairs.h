@@ -117,6 +117,31 @@ __device__ __forceinline__ void separation(const Geo& g, double xi, double yi, d
   if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
 }
 
+// A particle farther than the list reach from every periodic face sees all of
+// its listed neighbours at their stored (wrapped) positions: the minimum
+// image is then the identity.  Waves whose particles all qualify skip it.
+__device__ __forceinline__ bool away_from_faces(const Geo& g, const Phys& P, double x, double y,
+                                                double z) {
+  const double q[3] = {x, y, z};
+  bool ok = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (g.periodic[d]) ok = ok && q[d] >= P.reach && q[d] <= g.box[d] - P.reach;
+  return ok;
+}
+
+__device__ __forceinline__ void separation_mi(const Geo& g, bool mi, double xi, double yi,
+                                              double zi, double xj, double yj, double zj,
+                                              double& dx, double& dy, double& dz) {
+  if (mi) {
+    separation(g, xi, yi, zi, xj, yj, zj, dx, dy, dz);
+  } else {
+    dx = xi - xj;
+    dy = yi - yj;
+    dz = zi - zj;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Lane groups.  Every particle is served by kSub consecutive lanes of one
 // wave: lane `sub` of the group takes the list entries sub, sub + kSub, ...,
@@ -368,6 +393,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
   const Geo& g = geo[BATCH ? R[i].rep : 0u];
   const uint32_t ns = sl.count[i];
   const uint32_t cap = (uint32_t)P.cap;
+  const bool mi = !__all(away_from_faces(g, P, xi, yi, zi));  // uniform in the wave
   uint32_t nn = 0;
   double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, lap = 0.0;
   const float inv_rc_f = (float)P.inv_rc, a_f = (float)P.a;
@@ -379,7 +405,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
     bool take = false;
     double dx = 0.0, dy = 0.0, dz = 0.0, r2 = 0.0;
     if (k < ns) {
-      separation(g, xi, yi, zi, R[j].qx, R[j].qy, R[j].qz, dx, dy, dz);
+      separation_mi(g, mi, xi, yi, zi, R[j].qx, R[j].qy, R[j].qz, dx, dy, dz);
       r2 = dist2(dx, dy, dz);
       take = r2 < P.rc2;
     }
@@ -579,11 +605,12 @@ __device__ __forceinline__ void ser_pair(const Phys& P, const Geo& g, double dx,
 
 // dp_ij of neighbour j seen from the record of particle i.
 template <int PREC, int MODEL>
-__device__ __forceinline__ void pair_from_records(const Phys& P, const Geo& g, const Rec& a,
-                                                  const Rec& b, uint64_t step, double& vx,
-                                                  double& vy, double& vz, PairOut& o) {
+__device__ __forceinline__ void pair_from_records(const Phys& P, const Geo& g, bool mi,
+                                                  const Rec& a, const Rec& b, uint64_t step,
+                                                  double& vx, double& vy, double& vz,
+                                                  PairOut& o) {
   double dx, dy, dz;
-  separation(g, a.qx, a.qy, a.qz, b.qx, b.qy, b.qz, dx, dy, dz);
+  separation_mi(g, mi, a.qx, a.qy, a.qz, b.qx, b.qy, b.qz, dx, dy, dz);
   const double r2 = dist2(dx, dy, dz);
   vx = a.px * P.inv_mass - b.px * P.inv_mass;
   vy = a.py * P.inv_mass - b.py * P.inv_mass;
@@ -607,6 +634,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
   const Rec* __restrict__ R = s.r;
   const Rec a = R[i];
   const Geo& g = geo[BATCH ? a.rep : 0u];
+  const bool mi = !__all(away_from_faces(g, P, a.qx, a.qy, a.qz));  // uniform in the wave
   const uint32_t nn = nl.count[i];
   const int64_t st = nl.stride;
   // Hybrid: pairs inside one domain were integrated by SSA; their entries
@@ -636,7 +664,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
     }
     double vx, vy, vz;
     PairOut o;
-    pair_from_records<PREC, MODEL>(P, g, a, b, step, vx, vy, vz, o);
+    pair_from_records<PREC, MODEL>(P, g, mi, a, b, step, vx, vy, vz, o);
     ax += o.dp[0];
     ay += o.dp[1];
     az += o.dp[2];
@@ -692,6 +720,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
   const Rec* __restrict__ R = s.r;
   const Rec a = R[i];
   const Geo& g = geo[BATCH ? a.rep : 0u];
+  const bool mi = REGEN ? !__all(away_from_faces(g, P, a.qx, a.qy, a.qz)) : true;
   const Vec4 di = dpi[i];
   const Vec4 hi = hv[i];
   const uint32_t nn = nl.count[i];
@@ -719,7 +748,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
       const Rec b = R[j];
       double vx, vy, vz;
       PairOut o;
-      pair_from_records<PREC, MODEL>(P, g, a, b, step, vx, vy, vz, o);
+      pair_from_records<PREC, MODEL>(P, g, mi, a, b, step, vx, vy, vz, o);
       ex = o.dp[0];
       ey = o.dp[1];
       ez = o.dp[2];
