@@ -298,3 +298,29 @@ def test_stored_increments_equal_regenerated_noise(dp):
         assert np.array_equal(sa[2], eo.cpu().numpy())
         lib.dpde_free(h)
         a.close()
+
+
+def test_dense_region_uses_the_list_fallback(dp):
+    """A blob at ~11x the density puts more than 1024 stencil candidates in
+    some cells: their particles take the per-particle list build, the rest
+    the per-cell one; pairs and one step still match the oracle."""
+    rng = np.random.default_rng(17)
+    L = 20.0
+    base = 3 * int(L ** 3)
+    q = np.vstack([rng.random((base, 3)) * L, 8.0 + rng.random((2000, 3)) * 4.0])
+    n = len(q)
+    _, p, e = W.equilibrium_state(n, [L] * 3, seed=18)
+    cfg = dict(dt=0.002, neighbor_cap=512)
+    sysm = dp.System(_cfg(dp, n, [L] * 3, **cfg), q, p, e)
+    P = _oparams(n, [L] * 3, dt=0.002)
+    assert np.array_equal(sysm.debug_pairs(), O.pairs(P, q, "cells"))
+    sysm.step(2)
+    qs, ps, es, st = _gpu_state(sysm)
+    S = O.State(_oparams(n, [L] * 3, dt=0.002, step=st), qs, ps, es)
+    rc, _ = S.step(1)
+    assert rc == 0
+    sysm.step(1)
+    qg, pg, eg, _ = _gpu_state(sysm)
+    errs = _state_errors([L] * 3, (1, 1, 1), (qg, pg, eg), (S.q, S.p, S.eps), np.abs(S.eps).mean())
+    assert max(errs) < TOL, errs
+    sysm.close()
