@@ -234,7 +234,7 @@ __device__ __forceinline__ bool interior_dim(int c, int nc, int periodic) {
 
 // ---------------------------------------------------------------------------
 // Neighbour lists with a skin.  On a build step every particle collects the
-// particles within rs = rc + skin through the 27-cell stencil (phase 1 above),
+// particles within rs = rc + skin through the 27-cell stencil (scan_candidates),
 // and the list is sorted by neighbour identifier.  Every step then keeps the
 // entries with r < rc, in list order: the pair set is exactly the stencil's,
 // and every per-particle sum below runs in identifier order, so the
@@ -618,6 +618,35 @@ __device__ __forceinline__ void pair_from_records(const Phys& P, const Geo& g, b
   ser_pair<PREC, MODEL>(P, g, dx, dy, dz, r2, vx, vy, vz, a.invT + b.invT, a.id, b.id, step, o);
 }
 
+// Stored increments dp_ij: FP64, or FP32 for the FP32 pair terms, whose
+// increments are FP32 values to begin with (exact either way).
+template <int PREC>
+__device__ __forceinline__ void store_dp(const NList& nl, int64_t e, double x, double y, double z) {
+  if constexpr (PREC == PREC_F32) {
+    reinterpret_cast<float*>(nl.dex)[e] = (float)x;
+    reinterpret_cast<float*>(nl.dey)[e] = (float)y;
+    reinterpret_cast<float*>(nl.dez)[e] = (float)z;
+  } else {
+    nl.dex[e] = x;
+    nl.dey[e] = y;
+    nl.dez[e] = z;
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ void load_dp(const NList& nl, int64_t e, double& x, double& y,
+                                        double& z) {
+  if constexpr (PREC == PREC_F32) {
+    x = (double)reinterpret_cast<const float*>(nl.dex)[e];
+    y = (double)reinterpret_cast<const float*>(nl.dey)[e];
+    z = (double)reinterpret_cast<const float*>(nl.dez)[e];
+  } else {
+    x = nl.dex[e];
+    y = nl.dey[e];
+    z = nl.dez[e];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pass B (SER sweep 1, and the whole SEM update of eq. SEM_fd).
 // ---------------------------------------------------------------------------
@@ -655,11 +684,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
       nb = R[jn];
     }
     if (dom && dom[j] == dom_i) {
-      if (store) {
-        nl.dex[e] = 0.0;
-        nl.dey[e] = 0.0;
-        nl.dez[e] = 0.0;
-      }
+      if (store) store_dp<PREC>(nl, e, 0.0, 0.0, 0.0);
       continue;
     }
     double vx, vy, vz;
@@ -668,11 +693,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
     ax += o.dp[0];
     ay += o.dp[1];
     az += o.dp[2];
-    if (store) {
-      nl.dex[e] = o.dp[0];
-      nl.dey[e] = o.dp[1];
-      nl.dez[e] = o.dp[2];
-    }
+    if (store) store_dp<PREC>(nl, e, o.dp[0], o.dp[1], o.dp[2]);
     if constexpr (SCHEME == 1) {
       de += 0.5 * (o.gij * o.v2 - P.dsigma2_m) * o.chi * P.dt -
             0.5 * P.sigma * o.w * o.gdotv * P.sqrt_dt;
@@ -753,9 +774,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
       ey = o.dp[1];
       ez = o.dp[2];
     } else {
-      ex = nl.dex[e];
-      ey = nl.dey[e];
-      ez = nl.dez[e];
+      load_dp<PREC>(nl, e, ex, ey, ez);
     }
     de += -0.5 * (ex * ux + ey * uy + ez * uz);
   }
