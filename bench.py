@@ -430,9 +430,10 @@ def main():
     b0 = sysm.list_builds()
     sysm.step(100)
     builds_per_step = (sysm.list_builds() - b0) / 100.0
-    # kernel names as rocprofv3 reports them (batch, precision, scheme/regen, model)
+    # kernel names as rocprofv3 reports them (batch, precision, scheme/regen, model
+    # and, for sweep 2, the surrogate fused in: this workload's learned EOS)
     symbols = {"pass_a_forces": "k_pass_a<false, 0>", "pass_b_ser": "k_pass_b<false, 0, 0, 0>",
-               "pass_c_ser": "k_pass_c<false, 0, 0, 0>"}
+               "pass_c_ser": "k_pass_c<false, 0, 0, 0, 1>"}
     pair_roofs = {}
     for k in [k for k in prof if k in symbols]:
         bpp_k = pair_kernel_bytes(k, nbar, nskin)

@@ -490,20 +490,27 @@ void enqueue_fd_t(dpde_handle* h) {
   } else {
     launch(h, "pass_b_ser", k_pass_b<B, PR, 0, MD>, blocks(n * kSub, b), b, h->cur, h->nl, n,
            (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, store, dom, h->status);
-    if (h->regen)
-      launch(h, "pass_c_ser", k_pass_c<B, PR, 1, MD>, blocks(n * kSub, b), b, h->cur, h->nl, n,
-             (const Geo*)h->geo, h->phys, d_step, (const Vec4*)h->dpi, (const Vec4*)h->hv, inl,
-             h->alt.r, h->status);
-    else
-      launch(h, "pass_c_ser", k_pass_c<B, PR, 0, MD>, blocks(n * kSub, b), b, h->cur, h->nl, n,
-             (const Geo*)h->geo, h->phys, d_step, (const Vec4*)h->dpi, (const Vec4*)h->hv, inl,
-             h->alt.r, h->status);
+    // the surrogate's 1/T_i is computed inside sweep 2 (learned-EOS modes)
+    const MlpDev m = mlp_dev(h->mlp);
+    const int mode = h->mlp.trained ? h->phys.theta_mode : 0;
+    auto pass_c = [&](auto kern) {
+      launch(h, "pass_c_ser", kern, blocks(n * kSub, b), b, h->cur, h->nl, n, (const Geo*)h->geo,
+             h->phys, d_step, (const Vec4*)h->dpi, (const Vec4*)h->hv, inl, m, mode, h->alt.r,
+             h->status);
+    };
+    if (h->regen) {
+      if (inl) pass_c(k_pass_c<B, PR, 1, MD, 0>);
+      else pass_c(k_pass_c<B, PR, 1, MD, 1>);
+    } else {
+      if (inl) pass_c(k_pass_c<B, PR, 0, MD, 0>);
+      else pass_c(k_pass_c<B, PR, 0, MD, 1>);
+    }
   }
   // the updated records were written to the spare record array: swap them in
   // (one swap per step, so two steps restore the starting layout, which is
   // what an even-length captured graph relies on)
   std::swap(h->cur.r, h->alt.r);
-  if (!inl)
+  if (!inl && h->phys.scheme == DPDE_SCHEME_SEM)
     enqueue_theta_mlp(h->mlp, h->stream, h->cur.eps, &h->cur.r->invT, 8, n, h->phys, h->status);
 }
 

@@ -76,7 +76,9 @@ __device__ __forceinline__ float fast_tanh(float x) {
 }
 
 // ---- inference: every lane of the wave must call; returns this lane's y ---------
-__device__ __forceinline__ float mlp_wave_bf16(const uint16_t* __restrict__ wb, float x) {
+// 32 particles: lane l serves particle l % 32 (both half-waves pass that
+// particle's x) and every lane gets that particle's y.
+__device__ __forceinline__ float mlp_wave32_bf16(const uint16_t* __restrict__ wb, float xp) {
   const int l = threadIdx.x % kWave;
   const int half = l >> 5, col = l & 31;
   bf16x8 a[2];
@@ -85,32 +87,36 @@ __device__ __forceinline__ float mlp_wave_bf16(const uint16_t* __restrict__ wb, 
 #pragma unroll
     for (int e = 0; e < 8; ++e)
       a[ks][e] = __builtin_bit_cast(__bf16, wb[OFF_W2 + col * kH + ks * 16 + 8 * half + e]);
+  f32x16 acc = {};
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
+    bf16x8 b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = ks * 16 + 8 * half + e;
+      const float h = fast_tanh(bf16_bits_to_f32(wb[OFF_W1 + k]) * xp +
+                                bf16_bits_to_f32(wb[OFF_B1 + k]));
+      b[e] = __builtin_bit_cast(__bf16, f32_to_bf16_bits(h));
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b, acc, 0, 0, 0);
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int u = 8 * (r >> 2) + 4 * half + (r & 3);
+    s += bf16_bits_to_f32(wb[OFF_W3 + u]) * fast_tanh(acc[r] + bf16_bits_to_f32(wb[OFF_B2 + u]));
+  }
+  s += __shfl_xor(s, 32, kWave);
+  return s + bf16_bits_to_f32(wb[OFF_B3]);
+}
+
+// 64 particles: lane l passes the x of particle l and gets its y.
+__device__ __forceinline__ float mlp_wave_bf16(const uint16_t* __restrict__ wb, float x) {
+  const int l = threadIdx.x % kWave;
+  const int half = l >> 5, col = l & 31;
   float y[2];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb) {
-    const float xp = __shfl(x, 32 * mb + col, kWave);
-    f32x16 acc = {};
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      bf16x8 b;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = ks * 16 + 8 * half + e;
-        const float h = fast_tanh(bf16_bits_to_f32(wb[OFF_W1 + k]) * xp +
-                                  bf16_bits_to_f32(wb[OFF_B1 + k]));
-        b[e] = __builtin_bit_cast(__bf16, f32_to_bf16_bits(h));
-      }
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b, acc, 0, 0, 0);
-    }
-    float s = 0.0f;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int u = 8 * (r >> 2) + 4 * half + (r & 3);
-      s += bf16_bits_to_f32(wb[OFF_W3 + u]) * fast_tanh(acc[r] + bf16_bits_to_f32(wb[OFF_B2 + u]));
-    }
-    s += __shfl_xor(s, 32, kWave);
-    y[mb] = s + bf16_bits_to_f32(wb[OFF_B3]);
-  }
+  for (int mb = 0; mb < 2; ++mb) y[mb] = mlp_wave32_bf16(wb, __shfl(x, 32 * mb + col, kWave));
   return half ? y[1] : y[0];
 }
 
@@ -123,6 +129,25 @@ struct MlpDev {
 // network inside [eps_lo, eps_hi], Newton outside; mode 2: Newton started
 // from the network's estimate (or the asymptote outside the range); mode 0:
 // Newton alone.  No lane leaves before the matrix-core step.
+// Network input for eps: normalised log, clamped to the training interval.
+__device__ __forceinline__ float mlp_input(const MlpDev& m, double e) {
+  double xd = (log(e > 0.0 ? e : 1.0) - m.in_c) / m.in_s;
+  xd = xd < -1.0 ? -1.0 : (xd > 1.0 ? 1.0 : xd);
+  return (float)xd;
+}
+
+// theta from the network output y (modes 1, 2) or by Newton (mode 0, and
+// outside the training range in mode 1).
+__device__ __forceinline__ double theta_from_net(const Phys& P, const MlpDev& m, int mode,
+                                                 double e, float y, int& it) {
+  it = 0;
+  if (P.eos == 0) return e / P.cv;
+  const bool in_range = e >= m.eps_lo && e <= m.eps_hi;
+  const double th_net = mode != 0 ? exp(m.out_c + m.out_s * (double)y) : 0.0;
+  if (mode == 1 && in_range) return th_net;
+  return theta_newton_dev(P, e, (mode == 2 && in_range) ? th_net : theta_start_dev(P, e), it);
+}
+
 template <int OUT_INV>
 __global__ __launch_bounds__(256) void k_theta(const double* __restrict__ eps, double* __restrict__ out,
                                                int64_t ostride, int32_t* __restrict__ iters,
@@ -131,22 +156,10 @@ __global__ __launch_bounds__(256) void k_theta(const double* __restrict__ eps, d
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < n;
   const double e = valid ? eps[i] : 1.0;
-  double th;
-  int it = 0;
-  if (P.eos == 0) {
-    th = e / P.cv;
-  } else {
-    const bool in_range = e >= m.eps_lo && e <= m.eps_hi;
-    double th_net = 0.0;
-    if (mode != 0) {
-      double xd = (log(e > 0.0 ? e : 1.0) - m.in_c) / m.in_s;
-      xd = xd < -1.0 ? -1.0 : (xd > 1.0 ? 1.0 : xd);
-      const float y = mlp_wave_bf16(m.wb, (float)xd);
-      th_net = exp(m.out_c + m.out_s * (double)y);
-    }
-    if (mode == 1 && in_range) th = th_net;
-    else th = theta_newton_dev(P, e, (mode == 2 && in_range) ? th_net : theta_start_dev(P, e), it);
-  }
+  float y = 0.0f;
+  if (P.eos != 0 && mode != 0) y = mlp_wave_bf16(m.wb, mlp_input(m, e));  // uniform
+  int it;
+  const double th = theta_from_net(P, m, mode, e, y, it);
   if (!valid) return;
   if (!(e > 0.0)) {
     if (status) atomicOr(status, ST_NEG_EINT);

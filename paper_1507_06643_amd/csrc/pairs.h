@@ -21,6 +21,7 @@
 
 #include "bin.h"
 #include "eos.h"
+#include "mlp.h"
 
 namespace dpde {
 
@@ -728,70 +729,120 @@ __device__ __forceinline__ double inv_temperature(const Phys& P, double eps, uin
 // next 1/T_i.  The new records go to `out`, never over the records this pass
 // gathers from.
 // ---------------------------------------------------------------------------
-template <bool BATCH, int PREC, int REGEN, int MODEL>
+// THETA = 1: the surrogate network gives the next 1/T_i inside this pass
+// (the learned-EOS modes): the block's particles put their inputs in LDS,
+// one wave evaluates the network for all of them on the matrix cores, and
+// each particle finishes as the stand-alone theta kernel does (Newton outside
+// the training range).  The block therefore meets at barriers and takes no
+// early exit before them.
+template <bool BATCH, int PREC, int REGEN, int MODEL, int THETA>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
     const uint64_t* __restrict__ d_step, const Vec4* __restrict__ dpi,
-    const Vec4* __restrict__ hv, int eos_inline, Rec* __restrict__ out, uint32_t* status) {
+    const Vec4* __restrict__ hv, int eos_inline, MlpDev m, int mlp_mode, Rec* __restrict__ out,
+    uint32_t* status) {
+  __shared__ float net_x[kPairBlockMax / kSub];
+  __shared__ float net_y[kPairBlockMax / kSub];
+  __shared__ uint32_t st_flag;
   const Lanes L = lanes();
-  if (L.i >= n) return;  // uniform in the group
-  if (status_set(status)) return;
-  const int64_t i = L.i;
-  const uint64_t step = *d_step;
-  const Rec* __restrict__ R = s.r;
-  const Rec a = R[i];
-  const Geo& g = geo[BATCH ? a.rep : 0u];
-  const bool mi = REGEN ? !__all(away_from_faces(g, P, a.qx, a.qy, a.qz)) : true;
-  const Vec4 di = dpi[i];
-  const Vec4 hi = hv[i];
-  const uint32_t nn = nl.count[i];
-  const int64_t st = nl.stride;
-  double de = 0.0;
-  uint32_t jn = (uint32_t)L.sub < nn ? nl.idx[(int64_t)L.sub * st + i] : 0u;
-  double hx = 0.0, hy = 0.0, hz = 0.0;
-  if ((uint32_t)L.sub < nn) {
-    hx = hv[jn].x;
-    hy = hv[jn].y;
-    hz = hv[jn].z;
+  const bool live = L.i < n;  // uniform in the group
+  if constexpr (THETA) {
+    if (threadIdx.x == 0) st_flag = *status;
+    __syncthreads();
+    if (st_flag) return;  // uniform in the block
+  } else {
+    if (!live) return;
+    if (status_set(status)) return;
   }
-  for (uint32_t k = L.sub; k < nn; k += kSub) {
-    const int64_t e = (int64_t)k * st + i;
-    const uint32_t j = jn;
-    const double ux = hi.x - hx, uy = hi.y - hy, uz = hi.z - hz;
-    if (k + kSub < nn) {
-      jn = nl.idx[e + kSub * st];
+  const int64_t i = live ? L.i : 0;
+  double de = 0.0;
+  Rec a{};
+  Vec4 di{};
+  if (live) {
+    const uint64_t step = *d_step;
+    const Rec* __restrict__ R = s.r;
+    a = R[i];
+    const Geo& g = geo[BATCH ? a.rep : 0u];
+    const bool mi = REGEN ? !__all(away_from_faces(g, P, a.qx, a.qy, a.qz)) : true;
+    di = dpi[i];
+    const Vec4 hi = hv[i];
+    const uint32_t nn = nl.count[i];
+    const int64_t st = nl.stride;
+    uint32_t jn = (uint32_t)L.sub < nn ? nl.idx[(int64_t)L.sub * st + i] : 0u;
+    double hx = 0.0, hy = 0.0, hz = 0.0;
+    if ((uint32_t)L.sub < nn) {
       hx = hv[jn].x;
       hy = hv[jn].y;
       hz = hv[jn].z;
     }
-    double ex, ey, ez;
-    if constexpr (REGEN) {
-      const Rec b = R[j];
-      double vx, vy, vz;
-      PairOut o;
-      pair_from_records<PREC, MODEL>(P, g, mi, a, b, step, vx, vy, vz, o);
-      ex = o.dp[0];
-      ey = o.dp[1];
-      ez = o.dp[2];
-    } else {
-      load_dp<PREC>(nl, e, ex, ey, ez);
+    for (uint32_t k = L.sub; k < nn; k += kSub) {
+      const int64_t e = (int64_t)k * st + i;
+      const uint32_t j = jn;
+      const double ux = hi.x - hx, uy = hi.y - hy, uz = hi.z - hz;
+      if (k + kSub < nn) {
+        jn = nl.idx[e + kSub * st];
+        hx = hv[jn].x;
+        hy = hv[jn].y;
+        hz = hv[jn].z;
+      }
+      double ex, ey, ez;
+      if constexpr (REGEN) {
+        const Rec b = R[j];
+        double vx, vy, vz;
+        PairOut o;
+        pair_from_records<PREC, MODEL>(P, g, mi, a, b, step, vx, vy, vz, o);
+        ex = o.dp[0];
+        ey = o.dp[1];
+        ez = o.dp[2];
+      } else {
+        load_dp<PREC>(nl, e, ex, ey, ez);
+      }
+      de += -0.5 * (ex * ux + ey * uy + ez * uz);
     }
-    de += -0.5 * (ex * ux + ey * uy + ez * uz);
+    de = group_sum(de);
   }
-  de = group_sum(de);
-  if (L.sub != 0) return;
-  Rec o = a;
-  o.px = a.px + di.x;
-  o.py = a.py + di.y;
-  o.pz = a.pz + di.z;
-  const double e = s.eps[i] + de;
-  s.eps[i] = e;
-  if (!(e > 0.0)) {
-    atomicOr(status, ST_NEG_EINT);
-  } else if (eos_inline) {
-    o.invT = inv_temperature(P, e, status);
+  const double e = live ? s.eps[i] + de : 1.0;
+  // The record (with the old 1/T_i) is written before the network, so that
+  // only e and i stay live across it; the new 1/T_i follows.
+  const bool own = live && L.sub == 0;
+  bool need_t = false;
+  if (own) {
+    Rec o = a;
+    o.px = a.px + di.x;
+    o.py = a.py + di.y;
+    o.pz = a.pz + di.z;
+    s.eps[i] = e;
+    if (!(e > 0.0)) {
+      atomicOr(status, ST_NEG_EINT);
+    } else if constexpr (THETA) {
+      need_t = true;
+    } else if (eos_inline) {
+      o.invT = inv_temperature(P, e, status);
+    }
+    out[i] = o;
   }
-  out[i] = o;
+  if constexpr (THETA) {
+    float y = 0.0f;
+    if (mlp_mode != 0) {  // uniform
+      if (L.sub == 0) net_x[L.pib] = mlp_input(m, e);
+      __syncthreads();
+      // waves 0 and 1 take 32 particles each
+      const int w = threadIdx.x / kWave, col = threadIdx.x % 32;
+      if (w < 2 && 32 * w < L.ppb) {  // uniform in the wave
+        const int p = 32 * w + col;
+        const float yw = mlp_wave32_bf16(m.wb, p < L.ppb ? net_x[p] : 0.0f);
+        if (threadIdx.x % kWave < 32) net_y[p] = yw;
+      }
+      __syncthreads();
+      y = net_y[L.pib];
+    }
+    if (need_t) {
+      int it;
+      const double th = theta_from_net(P, m, mlp_mode, e, y, it);
+      if (!(th > 0.0) || !isfinite(th)) atomicOr(status, ST_EOS);
+      out[i].invT = 1.0 / th;
+    }
+  }
 }
 
 // SEM: apply dp and d eps (both from pass B), then the next 1/T_i.

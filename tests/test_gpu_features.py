@@ -191,6 +191,28 @@ def test_mlp_training_and_surrogate_accuracy(dp, eos_system):
     assert it_out.cpu().numpy().min() > 0
 
 
+def test_surrogate_inside_sweep2_matches_theta_kernel(dp, eos_system):
+    """In the learned-EOS mode sweep 2 evaluates the network for its own
+    particles; the resulting 1/T_i equal those of the stand-alone theta kernel
+    for the same internal energies (T_int of the record against
+    N / sum 1/theta recomputed from the state)."""
+    eos_system.mlp_train(nsamples=200000, iters=500, batch=4096, lr=3e-3, seed=6)
+    n = 4000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=95, eps0=25.0)
+    w, norm = eos_system.mlp_get()
+    for mode in (dp.THETA_MLP, dp.THETA_MLP_NEWTON):
+        s = dp.System(dp.Config(n=n, box=[L] * 3, eos=dp.EOS_EINSTEIN, theta_mode=mode,
+                                dt=0.005), q, p, e)
+        s.mlp_set(w, norm)
+        s.step(3)
+        _, _, eg, _ = s.get_state()
+        th, _ = s.theta(eg, mode=mode)
+        tint = n / (1.0 / th.cpu().numpy()).sum()
+        assert abs(s.energies()[8] / tint - 1) < 1e-13
+        s.close()
+
+
 # ---------------------------------------------------------------------------
 # Batched replicas: each replica equals the single system built from its own
 # parameters, bit for bit; graph replay equals eager stepping bit for bit.
