@@ -399,14 +399,26 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
   double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, lap = 0.0;
   const float inv_rc_f = (float)P.inv_rc, a_f = (float)P.a;
   uint32_t jn = (uint32_t)L.sub < ns ? sl.idx[(int64_t)L.sub * sl.stride + i] : 0u;
+  double qnx = 0.0, qny = 0.0, qnz = 0.0;
+  if ((uint32_t)L.sub < ns) {
+    qnx = R[jn].qx;
+    qny = R[jn].qy;
+    qnz = R[jn].qz;
+  }
   for (uint32_t base = 0; base < ns; base += kSub) {
     const uint32_t k = base + L.sub;
     const uint32_t j = jn;
-    if (k + kSub < ns) jn = sl.idx[(int64_t)(k + kSub) * sl.stride + i];
+    const double qjx = qnx, qjy = qny, qjz = qnz;
+    if (k + kSub < ns) {
+      jn = sl.idx[(int64_t)(k + kSub) * sl.stride + i];
+      qnx = R[jn].qx;
+      qny = R[jn].qy;
+      qnz = R[jn].qz;
+    }
     bool take = false;
     double dx = 0.0, dy = 0.0, dz = 0.0, r2 = 0.0;
     if (k < ns) {
-      separation_mi(g, mi, xi, yi, zi, R[j].qx, R[j].qy, R[j].qz, dx, dy, dz);
+      separation_mi(g, mi, xi, yi, zi, qjx, qjy, qjz, dx, dy, dz);
       r2 = dist2(dx, dy, dz);
       take = r2 < P.rc2;
     }
@@ -671,19 +683,12 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
   // carry a zero increment here
   const uint32_t dom_i = dom ? dom[i] : 0u;
   double ax = 0.0, ay = 0.0, az = 0.0, de = 0.0;
-  // software pipeline: the record of the lane's next neighbour is requested
-  // before the pair term of the current one is computed
-  uint32_t jn = (uint32_t)L.sub < nn ? nl.idx[(int64_t)L.sub * st + i] : 0u;
-  Rec nb;
-  if ((uint32_t)L.sub < nn) nb = R[jn];
+  // no software pipeline: the registers a prefetched record would hold buy
+  // one more wave per SIMD, which hides the gather latency better
   for (uint32_t k = L.sub; k < nn; k += kSub) {
     const int64_t e = (int64_t)k * st + i;
-    const Rec b = nb;
-    const uint32_t j = jn;
-    if (k + kSub < nn) {
-      jn = nl.idx[e + kSub * st];
-      nb = R[jn];
-    }
+    const uint32_t j = nl.idx[e];
+    const Rec b = R[j];
     if (dom && dom[j] == dom_i) {
       if (store) store_dp<PREC>(nl, e, 0.0, 0.0, 0.0);
       continue;
