@@ -46,7 +46,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int kHistBytes = 64 << 20;
-constexpr int64_t kStatTile = 4096;
+constexpr int64_t kStatTile = 1024;
 
 struct ProfileRec {
   const char* name;
@@ -103,15 +103,24 @@ struct dpde_handle {
   int64_t ndoms = 0;
   int dscan_tiles = 0;
   uint32_t* dom = nullptr;
-  uint32_t* dperm = nullptr;
+  uint32_t* dbucket = nullptr;  // particles by domain, in ticket order
+  uint32_t* dperm = nullptr;    // particles by domain, by identifier inside each
+  uint32_t* lslot = nullptr;    // rank of a particle inside its domain
   uint32_t* dcount = nullptr;
   uint32_t* dstart = nullptr;
   uint32_t* dscan_tmp = nullptr;
+  // intra-domain pairs in SSA order: count per sorted slot, offsets, pairs
+  int pscan_tiles = 0;
+  uint32_t* pcnt = nullptr;
+  uint32_t* poff = nullptr;
+  uint32_t* pscan_tmp = nullptr;
+  SsaPairs ssa{};
   BuildCtl* always = nullptr;  // a build control that always says 'now'
   double* rec = nullptr;
   double* hist = nullptr;
   int64_t hist_cap = 0;
   unsigned long long* counter = nullptr;
+  uint32_t* stats_ticket = nullptr;  // blocks of the observables' final pass done
 
   // surrogate network
   MlpState mlp{};
@@ -332,12 +341,25 @@ int allocate(dpde_handle* h) {
   if (h->hybrid) {
     h->dscan_tiles = (int)((h->ndoms + kScanTile - 1) / kScanTile);
     if (h->dscan_tiles > 1024 * 8) return fail(DPDE_EINVAL, "too many domains");
+    h->pscan_tiles = (int)((n + kScanTile - 1) / kScanTile);
+    if (h->pscan_tiles > 1024 * 8)
+      return fail(DPDE_EINVAL, "Hybrid supports at most %lld particles",
+                  (long long)(1024 * 8) * kScanTile);
+    // each intra-domain pair is counted once, from its lower identifier: at
+    // most half the list entries
+    h->ssa.cap = ((int64_t)h->phys.cap * n + 1) / 2;
     if ((rc = dalloc(h, &h->dom, n)) || (rc = dalloc(h, &h->dperm, n)) ||
+        (rc = dalloc(h, &h->dbucket, n)) || (rc = dalloc(h, &h->lslot, n)) ||
         (rc = dalloc(h, &h->dcount, h->ndoms + 1)) || (rc = dalloc(h, &h->dstart, h->ndoms + 1)) ||
         (rc = dalloc(h, &h->dscan_tmp, (size_t)h->dscan_tiles + 1)) ||
+        (rc = dalloc(h, &h->pcnt, n)) || (rc = dalloc(h, &h->poff, n + 1)) ||
+        (rc = dalloc(h, &h->pscan_tmp, (size_t)h->pscan_tiles + 1)) ||
+        (rc = dalloc(h, &h->ssa.idx, (size_t)h->ssa.cap)) ||
+        (rc = dalloc(h, &h->ssa.gc, (size_t)h->ssa.cap)) ||
         (rc = dalloc(h, &h->always, 1)))
       return rc;
     HIPCHK(hipMemset(h->dcount, 0, (h->ndoms + 1) * sizeof(uint32_t)));
+    HIPCHK(hipMemset(h->pcnt, 0, n * sizeof(uint32_t)));
     static const BuildCtl now{0ull, 1u, 0u};
     HIPCHK(hipMemcpy(h->always, &now, sizeof(BuildCtl), hipMemcpyHostToDevice));
   }
@@ -350,7 +372,8 @@ int allocate(dpde_handle* h) {
                     (rc = dalloc(h, &h->nl.dez, (size_t)h->phys.cap * n))))
     return rc;
   if ((rc = dalloc(h, &h->status, 4)) || (rc = dalloc(h, &h->d_step, 1)) ||
-      (rc = dalloc(h, &h->d_hist_count, 1)) || (rc = dalloc(h, &h->counter, 1)))
+      (rc = dalloc(h, &h->d_hist_count, 1)) || (rc = dalloc(h, &h->counter, 1)) ||
+      (rc = dalloc(h, &h->stats_ticket, 1)))
     return rc;
   // observable tiles: chunks of kStatTile inside each replica
   std::vector<int64_t> tb;
@@ -376,6 +399,7 @@ int allocate(dpde_handle* h) {
   HIPCHK(hipMemset(h->status, 0, 4 * sizeof(uint32_t)));
   HIPCHK(hipMemset(h->cell_count, 0, h->ncells * sizeof(uint32_t)));
   HIPCHK(hipMemset(h->d_hist_count, 0, sizeof(int64_t)));
+  HIPCHK(hipMemset(h->stats_ticket, 0, sizeof(uint32_t)));
   return DPDE_OK;
 }
 
@@ -446,8 +470,9 @@ bool eos_inline(const dpde_handle* h) {
   return h->phys.eos == DPDE_EOS_LINEAR || h->phys.theta_mode == DPDE_THETA_NEWTON;
 }
 
-// Hybrid (Sec. 3.2.2): particles binned by domain in identifier order, then
-// one lane per domain runs SSA over the domain's pairs.
+// Hybrid (Sec. 3.2.2): particles binned by domain and ranked by identifier
+// inside it, the intra-domain pairs listed in SSA order with their weights
+// and noise, then one lane per domain runs SSA over its pairs.
 template <bool B>
 void enqueue_hybrid_ssa(dpde_handle* h) {
   const int b = h->aux_block;
@@ -463,14 +488,35 @@ void enqueue_hybrid_ssa(dpde_handle* h) {
   launch(h, "dom_scan_apply", k_scan_apply, h->dscan_tiles, kScanThreads, h->dcount, h->ndoms,
          (const uint32_t*)h->dscan_tmp, h->dstart, now, 0.0);
   launch(h, "dom_scatter", k_scatter, blocks(n, b), b, (const uint32_t*)h->key,
-         (const uint32_t*)h->ticket, (const uint32_t*)h->dstart, n, h->dperm, now, 0.0,
+         (const uint32_t*)h->ticket, (const uint32_t*)h->dstart, n, h->dbucket, now, 0.0,
          (const uint32_t*)h->status);
-  launch(h, "dom_sort", k_cell_sort, blocks(h->ndoms, b), b, (const uint32_t*)h->dstart,
-         h->ndoms, h->dperm, (const uint32_t*)h->idk, now, 0.0, (const uint32_t*)h->status);
-  launch(h, "ssa_domains", k_ssa<B>, blocks(h->ndoms, 64), 64, h->cur, h->nl,
-         (const uint32_t*)h->dperm, (const uint32_t*)h->dstart, h->ndoms,
-         (const uint32_t*)h->dom, (const Geo*)h->geo, h->phys, (const uint64_t*)h->d_step,
+  launch(h, "dom_rank", k_dom_rank, blocks(n, b), b, (const uint32_t*)h->dbucket,
+         (const uint32_t*)h->dstart, (const uint32_t*)h->dom, (const uint32_t*)h->idk, n, h->dperm,
+         h->lslot, (const uint32_t*)h->status);
+  launch(h, "ssa_count", k_ssa_count, blocks(n, b), b, h->nl, (const uint32_t*)h->dperm, n,
+         (const uint32_t*)h->dom, (const uint32_t*)h->idk, h->pcnt, (const uint32_t*)h->status);
+  // poff[k] = first pair of sorted slot k, poff[n] = all pairs
+  launch(h, "ssa_scan_tiles", k_scan_tiles, h->pscan_tiles, kScanThreads,
+         (const uint32_t*)h->pcnt, n, h->pscan_tmp, now, 0.0);
+  launch(h, "ssa_scan_tile_sums", k_scan_tile_sums, 1, 1024, h->pscan_tmp, h->pscan_tiles, now,
+         0.0);
+  launch(h, "ssa_scan_apply", k_scan_apply, h->pscan_tiles, kScanThreads, h->pcnt, n,
+         (const uint32_t*)h->pscan_tmp, h->poff, now, 0.0);
+  const int pb = h->pair_block;
+  launch(h, "ssa_pairs", k_ssa_pairs<B>, blocks(n * kSub, pb), pb, h->cur, h->nl, (const uint32_t*)h->dperm,
+         (const uint32_t*)h->lslot, n, (const uint32_t*)h->dom, (const uint32_t*)h->idk,
+         (const uint32_t*)h->poff, (const Geo*)h->geo, h->phys, (const uint64_t*)h->d_step, h->ssa,
          h->status);
+  auto walk = [&](auto kern) {
+    launch(h, "ssa_domains", kern, blocks(h->ndoms, kWave), kWave, h->cur,
+           (const uint32_t*)h->dperm, (const uint32_t*)h->dstart, h->ndoms,
+           (const uint32_t*)h->poff, h->ssa, h->phys, h->status);
+  };
+  // LDS slots a wave of domains needs at 1.25 times the mean domain size
+  const double need = kWave * 1.25 * (double)n / (double)h->ndoms + 128.0;
+  if (need <= 512.0) walk(k_ssa_walk<512>);
+  else if (need <= 1024.0) walk(k_ssa_walk<1024>);
+  else walk(k_ssa_walk<kSsaPoolMax>);
 }
 
 template <bool B, int PR, int MD>
@@ -530,13 +576,14 @@ void enqueue_fd(dpde_handle* h) {
   }
 }
 
-void enqueue_stats_only(dpde_handle* h, int advance) {
+void enqueue_stats_only(dpde_handle* h, int advance, int finish) {
   launch(h, "stats_tiles", k_stats_tiles, h->ntiles, kStatThreads, h->cur, (const double*)h->Ui,
          (const double*)h->Li, (const double*)h->Fx, (const double*)h->Fy, (const double*)h->Fz,
          (const int64_t*)h->tile_begin, h->phys, h->partials);
-  launch(h, "stats_final", k_stats_final, h->nrep, kStatThreads, (const Fix*)h->partials,
-         (const int32_t*)h->rep_tile0, (const Geo*)h->geo, (const uint64_t*)h->d_step, advance,
-         h->rec, h->hist, h->hist_cap, (const int64_t*)h->d_hist_count, h->nrep);
+  launch(h, "stats_final", k_stats_final, h->nrep, kStatFinalThreads, (const Fix*)h->partials,
+         (const int32_t*)h->rep_tile0, (const Geo*)h->geo, h->d_step, advance, h->rec, h->hist,
+         h->hist_cap, h->d_hist_count, h->nrep, finish, h->stats_ticket, h->ctl, h->builds,
+         h->half_skin2, (const uint32_t*)h->status);
 }
 
 // Observables of the step; with the projection (Sec. 4.2) the record of the
@@ -544,7 +591,7 @@ void enqueue_stats_only(dpde_handle* h, int advance) {
 // record is taken again from the projected state.
 void enqueue_stats(dpde_handle* h, int advance) {
   if (advance && h->phys.project) {
-    enqueue_stats_only(h, 0);
+    enqueue_stats_only(h, 0, 0);
     const int inl = eos_inline(h) ? 1 : 0;
     launch(h, "project", h->batch ? k_project<true> : k_project<false>, blocks(h->n, h->aux_block),
            h->aux_block, h->cur, h->n, (const Geo*)h->geo, h->phys, (const double*)h->rec,
@@ -553,9 +600,8 @@ void enqueue_stats(dpde_handle* h, int advance) {
       enqueue_theta_mlp(h->mlp, h->stream, h->cur.eps, &h->cur.r->invT, 8, h->n, h->phys,
                         h->status);
   }
-  enqueue_stats_only(h, advance);
-  launch(h, "step_end", k_step_end, 1, 1, h->d_step, h->d_hist_count, h->ctl, h->builds,
-         h->half_skin2, advance, (const uint32_t*)h->status);
+  // the last block of the final pass also ends the step
+  enqueue_stats_only(h, advance, 1);
 }
 
 void enqueue_step(dpde_handle* h) {

@@ -923,11 +923,33 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_tiles(
     for (int k = 0; k < kStatVals; ++k) partials[blockIdx.x * kStatVals + k] = v[k];
 }
 
-__global__ __launch_bounds__(kStatThreads) void k_stats_final(
+// End of the step: count a list build, clear the build control, advance the
+// step and history counters (nothing when the status is raised).
+__device__ __forceinline__ void step_end(uint64_t* d_step, int64_t* d_hist_count, BuildCtl* ctl,
+                                         unsigned long long* builds, double half_skin2,
+                                         int advance, const uint32_t* status) {
+  if (status_set(status)) return;
+  if (rebuild_now(ctl, half_skin2)) *builds += 1ull;
+  ctl->dmax_bits = 0ull;
+  ctl->force = 0u;
+  if (advance) {
+    *d_step += 1;
+    *d_hist_count += 1;
+  }
+}
+
+// Per replica: sum the tile partials, write the record (and the history
+// row).  With `finish`, the last block to complete also ends the step: a
+// ticket taken after each block's reads of the step and history counters
+// tells it that every other block is done with them.
+constexpr int kStatFinalThreads = 1024;  // one tile per thread up to 1024 tiles
+
+__global__ __launch_bounds__(kStatFinalThreads) void k_stats_final(
     const Fix* __restrict__ partials, const int32_t* __restrict__ rep_tile0,
-    const Geo* __restrict__ geo, const uint64_t* __restrict__ d_step, int advance,
+    const Geo* __restrict__ geo, uint64_t* d_step, int advance,
     double* __restrict__ rec, double* __restrict__ hist, int64_t hist_cap,
-    const int64_t* __restrict__ d_hist_count, int nrep) {
+    int64_t* d_hist_count, int nrep, int finish, uint32_t* ticket, BuildCtl* ctl,
+    unsigned long long* builds, double half_skin2, const uint32_t* status) {
   const int r = blockIdx.x;
   const int t0 = rep_tile0[r], t1 = rep_tile0[r + 1];
   Fix f[kStatVals];
@@ -935,7 +957,7 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_final(
   for (int k = 0; k < kStatVals; ++k) f[k] = fix_zero();
   for (int t = t0 + threadIdx.x; t < t1; t += blockDim.x)
     for (int k = 0; k < kStatVals; ++k) f[k] = fix_add(f[k], partials[t * kStatVals + k]);
-  __shared__ Fix smem[kStatVals * (kStatThreads / kWave)];
+  __shared__ Fix smem[kStatVals * (kStatFinalThreads / kWave)];
   block_sum_fix<kStatVals>(f, smem);
   if (threadIdx.x == 0) {
     const bool bad = f[kStatBad].lo != 0ull || f[kStatBad].hi != 0ll;
@@ -960,6 +982,15 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_final(
     for (int k = 0; k < kRecLen; ++k) {
       rec[r * kRecLen + k] = o[k];
       if (hrow) hrow[k] = o[k];
+    }
+    if (finish) {
+      __threadfence();
+      // one replica: this block is the last one
+      if (gridDim.x == 1u || atomicAdd(ticket, 1u) == gridDim.x - 1u) {
+        __threadfence();
+        step_end(d_step, d_hist_count, ctl, builds, half_skin2, advance, status);
+        atomicExch(ticket, 0u);
+      }
     }
   }
 }
@@ -993,18 +1024,6 @@ __global__ void k_capture_e0(const double* __restrict__ rec, double* __restrict_
 
 // End of a step: count a list build, clear the build control, and (when
 // advancing) n <- n + 1 with one more history record (not after an error).
-__global__ void k_step_end(uint64_t* d_step, int64_t* d_hist_count, BuildCtl* ctl,
-                           unsigned long long* builds, double half_skin2, int advance,
-                           const uint32_t* status) {
-  if (status_set(status)) return;
-  if (rebuild_now(ctl, half_skin2)) *builds += 1ull;
-  ctl->dmax_bits = 0ull;
-  ctl->force = 0u;
-  if (advance) {
-    *d_step += 1;
-    *d_hist_count += 1;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Test hooks.

@@ -159,7 +159,11 @@ def test_soft_config_terms(dp):
 # ---------------------------------------------------------------------------
 # Hybrid (Sec. 3.2.2): SSA inside spatial domains, SER across them
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("ndom", [(1, 1, 1), (4, 4, 4), (3, 2, 5)])
+# domains of ~3000, ~100 and ~47 particles sweep in the particle arrays (the
+# last mixed with LDS lanes); ~24, ~6 and ~3 keep their state in LDS pools of
+# the three sizes
+@pytest.mark.parametrize("ndom", [(1, 1, 1), (4, 4, 4), (3, 2, 5), (5, 5, 5), (8, 8, 8),
+                                  (10, 10, 10)])
 def test_hybrid_step_parity(dp, ndom):
     n = 3000
     L = W.cubic_side(n)
