@@ -491,10 +491,8 @@ void enqueue_hybrid_ssa(dpde_handle* h) {
          (const uint32_t*)h->ticket, (const uint32_t*)h->dstart, n, h->dbucket, now, 0.0,
          (const uint32_t*)h->status);
   launch(h, "dom_rank", k_dom_rank, blocks(n, b), b, (const uint32_t*)h->dbucket,
-         (const uint32_t*)h->dstart, (const uint32_t*)h->dom, (const uint32_t*)h->idk, n, h->dperm,
-         h->lslot, (const uint32_t*)h->status);
-  launch(h, "ssa_count", k_ssa_count, blocks(n, b), b, h->nl, (const uint32_t*)h->dperm, n,
-         (const uint32_t*)h->dom, (const uint32_t*)h->idk, h->pcnt, (const uint32_t*)h->status);
+         (const uint32_t*)h->dstart, (const uint32_t*)h->dom, (const uint32_t*)h->idk, n, h->nl,
+         h->dperm, h->lslot, h->pcnt, (const uint32_t*)h->status);
   // poff[k] = first pair of sorted slot k, poff[n] = all pairs
   launch(h, "ssa_scan_tiles", k_scan_tiles, h->pscan_tiles, kScanThreads,
          (const uint32_t*)h->pcnt, n, h->pscan_tmp, now, 0.0);

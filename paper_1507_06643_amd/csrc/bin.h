@@ -181,6 +181,32 @@ __global__ void k_kick(PState s, const double* __restrict__ Fx, const double* __
   }
 }
 
+// Histogram increment with one atomic per run of equal keys among
+// consecutive lanes of a wave; the run's lanes take consecutive tickets.
+// Every lane of the wave calls (dead lanes with live = false).
+__device__ __forceinline__ uint32_t run_ticket(uint32_t c, bool live, uint32_t* count) {
+  const int lane = threadIdx.x % kWave;
+  const uint32_t prev = __shfl_up(c, 1, kWave);
+  const bool head = live && (lane == 0 || prev != c);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long below = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+  const int my_head = 63 - __clzll(heads & below);  // last head at or below this lane
+  const unsigned long long above = heads & ~below;   // heads strictly above
+  const int next_head = above ? __ffsll((long long)above) - 1 : kWave;
+  // the run of a head ends before the next head or at the first dead lane
+  const unsigned long long alive = __ballot(live);
+  int run_end = next_head;
+  const unsigned long long dead_above = ~alive & ~below;
+  if (dead_above) {
+    const int first_dead = __ffsll((long long)dead_above) - 1;
+    if (first_dead < run_end) run_end = first_dead;
+  }
+  uint32_t base = 0;
+  if (head) base = atomicAdd(&count[c], (uint32_t)(run_end - lane));
+  base = __shfl(base, my_head, kWave);
+  return base + (uint32_t)(lane - my_head);
+}
+
 // Cell key of every particle and the cell histogram (list-build steps only).
 // The identifier is also written to a compact array for the per-cell sort.
 // The histogram update is aggregated per run of equal keys inside a wave (the
@@ -206,27 +232,8 @@ __global__ void k_bin_key(PState s, int64_t n, const Geo* __restrict__ geo,
     key[i] = c;
     idk[i] = rc.id;
   }
-  // runs of equal keys among consecutive lanes
-  const int lane = threadIdx.x % kWave;
-  const uint32_t prev = __shfl_up(c, 1, kWave);
-  const bool head = live && (lane == 0 || prev != c);
-  const unsigned long long heads = __ballot(head);
-  const unsigned long long below = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
-  const int my_head = 63 - __clzll(heads & below);  // last head at or below this lane
-  const unsigned long long above = heads & ~below;   // heads strictly above
-  const int next_head = above ? __ffsll((long long)above) - 1 : kWave;
-  // the run of a head ends before the next head or at the first dead lane
-  const unsigned long long alive = __ballot(live);
-  int run_end = next_head;
-  const unsigned long long dead_above = ~alive & ~below;
-  if (dead_above) {
-    const int first_dead = __ffsll((long long)dead_above) - 1;
-    if (first_dead < run_end) run_end = first_dead;
-  }
-  uint32_t base = 0;
-  if (head) base = atomicAdd(&count[c], (uint32_t)(run_end - lane));
-  base = __shfl(base, my_head, kWave);
-  if (live) ticket[i] = base + (uint32_t)(lane - my_head);
+  const uint32_t t = run_ticket(c, live, count);
+  if (live) ticket[i] = t;
 }
 
 // ---- exclusive scan of the cell histogram -> cell offsets --------------------

@@ -21,31 +21,45 @@ __device__ __forceinline__ uint32_t domain_index(const Geo& g, double x, double 
 }
 
 // Domain of every particle (positions at the start of the fluctuation/
-// dissipation step), bucket histogram and ticket, identifier for the
-// per-domain sort.
+// dissipation step), bucket histogram and ticket (one atomic per run of
+// equal domains in a wave), identifier for the per-domain ranking.
 template <bool BATCH>
 __global__ void k_dom_key(PState s, int64_t n, const Geo* __restrict__ geo,
                           uint32_t* __restrict__ dom, uint32_t* __restrict__ key,
                           uint32_t* __restrict__ ticket, uint32_t* __restrict__ idk,
                           uint32_t* __restrict__ count, const uint32_t* status) {
+  if (status_set(status)) return;  // uniform
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (status_set(status)) return;
-  const Rec& rc = s.r[i];
-  const Geo& g = geo[BATCH ? rc.rep : 0u];
-  const uint32_t d = domain_index(g, rc.qx, rc.qy, rc.qz);
-  dom[i] = d;
-  key[i] = d;
-  idk[i] = rc.id;
-  ticket[i] = atomicAdd(&count[d], 1u);
+  const bool live = i < n;
+  uint32_t d = 0xFFFFFFFFu;
+  if (live) {
+    const Rec& rc = s.r[i];
+    const Geo& g = geo[BATCH ? rc.rep : 0u];
+    d = domain_index(g, rc.qx, rc.qy, rc.qz);
+    dom[i] = d;
+    key[i] = d;
+    idk[i] = rc.id;
+  }
+  const uint32_t t = run_ticket(d, live, count);
+  if (live) ticket[i] = t;
 }
 
 // Rank of every particle inside its domain by identifier (the order the SSA
 // sweep takes the domain's particles), out of place: one thread per bucket
 // slot counts the smaller identifiers of its bucket.  lslot[i] is the rank.
+// The thread also counts the particle's pairs of the sweep (below) for its
+// sorted slot.
+//
+// The intra-domain pairs in the order of the SSA sweep: the domain's
+// particles by increasing identifier, each with its list neighbours (in
+// identifier order) of higher identifier in the same domain.  After a scan
+// of the counts, k_ssa_pairs writes each pair's local slots, its weight
+// chi = w(r)^2 and its noise G_ij (positions are fixed during the sweep, so
+// both are known before it starts).
 __global__ void k_dom_rank(const uint32_t* __restrict__ bucket, const uint32_t* __restrict__ dstart,
                            const uint32_t* __restrict__ dom, const uint32_t* __restrict__ idk,
-                           int64_t n, uint32_t* __restrict__ sorted, uint32_t* __restrict__ lslot,
+                           int64_t n, NList nl, uint32_t* __restrict__ sorted,
+                           uint32_t* __restrict__ lslot, uint32_t* __restrict__ pcnt,
                            const uint32_t* status) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
@@ -58,30 +72,13 @@ __global__ void k_dom_rank(const uint32_t* __restrict__ bucket, const uint32_t* 
   for (uint32_t m = b; m < e; ++m) r += idk[bucket[m]] < my ? 1u : 0u;
   sorted[b + r] = i;
   lslot[i] = r;
-}
-
-// The intra-domain pairs in the order of the SSA sweep: the domain's
-// particles by increasing identifier, each with its list neighbours (in
-// identifier order) of higher identifier in the same domain.  k_ssa_count
-// counts them per sorted slot; after a scan, k_ssa_pairs writes each pair's
-// local slots, its weight chi = w(r)^2 and its noise G_ij (positions are
-// fixed during the sweep, so both are known before it starts).
-__global__ void k_ssa_count(NList nl, const uint32_t* __restrict__ sorted, int64_t n,
-                            const uint32_t* __restrict__ dom, const uint32_t* __restrict__ idk,
-                            uint32_t* __restrict__ pcnt, const uint32_t* status) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
   uint32_t c = 0;
-  if (!status_set(status)) {
-    const uint32_t i = sorted[k];
-    const uint32_t d = dom[i], id = idk[i];
-    const uint32_t nn = nl.count[i];
-    for (uint32_t m = 0; m < nn; ++m) {
-      const uint32_t j = nl.idx[(int64_t)m * nl.stride + i];
-      c += (dom[j] == d && idk[j] > id) ? 1u : 0u;
-    }
+  const uint32_t nn = nl.count[i];
+  for (uint32_t m = 0; m < nn; ++m) {
+    const uint32_t j = nl.idx[(int64_t)m * nl.stride + i];
+    c += (dom[j] == d && idk[j] > my) ? 1u : 0u;
   }
-  pcnt[k] = c;
+  pcnt[b + r] = c;
 }
 
 struct SsaPairs {
@@ -116,7 +113,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_ssa_pairs(
     bool take = false;
     if (m < nn) {
       j = nl.idx[(int64_t)m * nl.stride + i];
-      take = dom[j] == d && idk[j] > id;  // the same test as k_ssa_count
+      take = dom[j] == d && idk[j] > id;  // the same test as k_dom_rank
     }
     const uint32_t bits = group_ballot(L, take);
     if (take) {
