@@ -197,7 +197,7 @@ def pair_kernel_bytes(name, nbar, nskin=None, fp32=False):
 
 
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "learned_eos_n1m_traffic.txt")
-KERNEL_SOURCES = ["common.h", "bin.h", "pairs.h", "eos.h", "mlp.h", "api.hip"]
+KERNEL_SOURCES = ["common.h", "bin.h", "pairs.h", "eos.h", "mlp.h", "hybrid.h", "api.hip"]
 
 
 def _profile_lines():

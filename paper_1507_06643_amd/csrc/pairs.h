@@ -924,17 +924,24 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_tiles(
 }
 
 // End of the step: count a list build, clear the build control, advance the
-// step and history counters (nothing when the status is raised).
-__device__ __forceinline__ void step_end(uint64_t* d_step, int64_t* d_hist_count, BuildCtl* ctl,
-                                         unsigned long long* builds, double half_skin2,
-                                         int advance, const uint32_t* status) {
-  if (status_set(status)) return;
-  if (rebuild_now(ctl, half_skin2)) *builds += 1ull;
+// step and history counters (nothing when the status is raised).  The
+// counters' values were read before (no other block writes them).
+struct StepNow {
+  uint64_t step;
+  int64_t hist;
+  unsigned long long builds;
+  bool rebuilt, failed;
+};
+
+__device__ __forceinline__ void step_end(const StepNow& c, uint64_t* d_step, int64_t* d_hist_count,
+                                         BuildCtl* ctl, unsigned long long* builds, int advance) {
+  if (c.failed) return;
+  if (c.rebuilt) *builds = c.builds + 1ull;
   ctl->dmax_bits = 0ull;
   ctl->force = 0u;
   if (advance) {
-    *d_step += 1;
-    *d_hist_count += 1;
+    *d_step = c.step + 1;
+    *d_hist_count = c.hist + 1;
   }
 }
 
@@ -942,7 +949,7 @@ __device__ __forceinline__ void step_end(uint64_t* d_step, int64_t* d_hist_count
 // row).  With `finish`, the last block to complete also ends the step: a
 // ticket taken after each block's reads of the step and history counters
 // tells it that every other block is done with them.
-constexpr int kStatFinalThreads = 1024;  // one tile per thread up to 1024 tiles
+constexpr int kStatFinalThreads = kStatVals * kWave;  // one wave per recorded sum
 
 __global__ __launch_bounds__(kStatFinalThreads) void k_stats_final(
     const Fix* __restrict__ partials, const int32_t* __restrict__ rep_tile0,
@@ -952,18 +959,29 @@ __global__ __launch_bounds__(kStatFinalThreads) void k_stats_final(
     unsigned long long* builds, double half_skin2, const uint32_t* status) {
   const int r = blockIdx.x;
   const int t0 = rep_tile0[r], t1 = rep_tile0[r + 1];
-  Fix f[kStatVals];
-#pragma unroll
-  for (int k = 0; k < kStatVals; ++k) f[k] = fix_zero();
-  for (int t = t0 + threadIdx.x; t < t1; t += blockDim.x)
-    for (int k = 0; k < kStatVals; ++k) f[k] = fix_add(f[k], partials[t * kStatVals + k]);
-  __shared__ Fix smem[kStatVals * (kStatFinalThreads / kWave)];
-  block_sum_fix<kStatVals>(f, smem);
+  // the values the record and the end of the step need, requested before
+  // the reduction so that their latency overlaps it
+  StepNow now{*d_step, *d_hist_count, 0ull, false, false};
+  if (finish) {
+    now.builds = *builds;
+    now.rebuilt = rebuild_now(ctl, half_skin2);
+    now.failed = status_set(status);
+  }
+  const double N = (double)geo[r].n;
+  // wave k adds value k over the replica's tiles
+  const int k0 = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  Fix acc = fix_zero();
+  for (int t = t0 + lane; t < t1; t += kWave) acc = fix_add(acc, partials[t * kStatVals + k0]);
+  acc = wave_sum_fix(acc);
+  __shared__ Fix tot[kStatVals];
+  if (lane == 0) tot[k0] = acc;
+  __syncthreads();
   if (threadIdx.x == 0) {
+    Fix f[kStatVals];
+    for (int k = 0; k < kStatVals; ++k) f[k] = tot[k];
     const bool bad = f[kStatBad].lo != 0ull || f[kStatBad].hi != 0ll;
     double v[9];
     for (int k = 0; k < 9; ++k) v[k] = bad ? __builtin_nan("") : fix_to_double(f[k]);
-    const double N = (double)geo[r].n;
     double o[kRecLen];
     o[0] = v[0];
     o[1] = v[1];
@@ -974,11 +992,11 @@ __global__ __launch_bounds__(kStatFinalThreads) void k_stats_final(
     o[6] = v[5];
     o[7] = 2.0 * v[1] / (3.0 * (N - 1.0));
     o[8] = N / v[6];
-    o[9] = (double)(*d_step + (uint64_t)advance);
+    o[9] = (double)(now.step + (uint64_t)advance);
     o[10] = v[7];
     o[11] = v[8];
     double* hrow = nullptr;
-    if (advance) hrow = hist + ((*d_hist_count % hist_cap) * nrep + r) * kRecLen;
+    if (advance) hrow = hist + ((now.hist % hist_cap) * nrep + r) * kRecLen;
     for (int k = 0; k < kRecLen; ++k) {
       rec[r * kRecLen + k] = o[k];
       if (hrow) hrow[k] = o[k];
@@ -988,7 +1006,7 @@ __global__ __launch_bounds__(kStatFinalThreads) void k_stats_final(
       // one replica: this block is the last one
       if (gridDim.x == 1u || atomicAdd(ticket, 1u) == gridDim.x - 1u) {
         __threadfence();
-        step_end(d_step, d_hist_count, ctl, builds, half_skin2, advance, status);
+        step_end(now, d_step, d_hist_count, ctl, builds, advance);
         atomicExch(ticket, 0u);
       }
     }
