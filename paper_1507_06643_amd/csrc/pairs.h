@@ -632,17 +632,19 @@ __device__ __forceinline__ void pair_from_records(const Phys& P, const Geo& g, b
 }
 
 // Stored increments dp_ij: FP64, or FP32 for the FP32 pair terms, whose
-// increments are FP32 values to begin with (exact either way).
+// increments are FP32 values to begin with (exact either way).  They are
+// written once and read once, so both go non-temporal: the stream does not
+// evict the neighbour data the gathers of both sweeps reuse from L2.
 template <int PREC>
 __device__ __forceinline__ void store_dp(const NList& nl, int64_t e, double x, double y, double z) {
   if constexpr (PREC == PREC_F32) {
-    reinterpret_cast<float*>(nl.dex)[e] = (float)x;
-    reinterpret_cast<float*>(nl.dey)[e] = (float)y;
-    reinterpret_cast<float*>(nl.dez)[e] = (float)z;
+    __builtin_nontemporal_store((float)x, reinterpret_cast<float*>(nl.dex) + e);
+    __builtin_nontemporal_store((float)y, reinterpret_cast<float*>(nl.dey) + e);
+    __builtin_nontemporal_store((float)z, reinterpret_cast<float*>(nl.dez) + e);
   } else {
-    nl.dex[e] = x;
-    nl.dey[e] = y;
-    nl.dez[e] = z;
+    __builtin_nontemporal_store(x, nl.dex + e);
+    __builtin_nontemporal_store(y, nl.dey + e);
+    __builtin_nontemporal_store(z, nl.dez + e);
   }
 }
 
@@ -650,13 +652,13 @@ template <int PREC>
 __device__ __forceinline__ void load_dp(const NList& nl, int64_t e, double& x, double& y,
                                         double& z) {
   if constexpr (PREC == PREC_F32) {
-    x = (double)reinterpret_cast<const float*>(nl.dex)[e];
-    y = (double)reinterpret_cast<const float*>(nl.dey)[e];
-    z = (double)reinterpret_cast<const float*>(nl.dez)[e];
+    x = (double)__builtin_nontemporal_load(reinterpret_cast<const float*>(nl.dex) + e);
+    y = (double)__builtin_nontemporal_load(reinterpret_cast<const float*>(nl.dey) + e);
+    z = (double)__builtin_nontemporal_load(reinterpret_cast<const float*>(nl.dez) + e);
   } else {
-    x = nl.dex[e];
-    y = nl.dey[e];
-    z = nl.dez[e];
+    x = __builtin_nontemporal_load(nl.dex + e);
+    y = __builtin_nontemporal_load(nl.dey + e);
+    z = __builtin_nontemporal_load(nl.dez + e);
   }
 }
 
