@@ -74,6 +74,7 @@ struct dpde_handle {
   PState cur{}, alt{};
   double half_skin2 = 0.0, rs2 = 0.0;
   QRef* qref = nullptr;
+  QId* qid = nullptr;  // build-time positions and identifiers, cell order
   uint32_t* slot = nullptr;  // memory index of each identifier row
   BuildCtl* ctl = nullptr;
   unsigned long long* builds = nullptr;
@@ -330,7 +331,8 @@ int allocate(dpde_handle* h) {
   h->nl.stride = n;
   if ((rc = dalloc(h, &h->nl.idx, (size_t)h->phys.cap * n)) || (rc = dalloc(h, &h->nl.count, n)))
     return rc;
-  if ((rc = dalloc(h, &h->qref, n)) || (rc = dalloc(h, &h->ctl, 1)) ||
+  if ((rc = dalloc(h, &h->qref, n)) || (rc = dalloc(h, &h->qid, n)) ||
+      (rc = dalloc(h, &h->ctl, 1)) ||
       (rc = dalloc(h, &h->builds, 1)) ||
       (rc = dalloc(h, &h->skin.idx, (size_t)h->phys.cap * n)) ||
       (rc = dalloc(h, &h->slot, n)) ||
@@ -437,15 +439,15 @@ void enqueue_bin(dpde_handle* h, int kick) {
   launch(h, "cell_sort", k_cell_sort, blocks(h->ncells, b), b, (const uint32_t*)h->cell_start,
          h->ncells, h->perm, (const uint32_t*)h->idk, ctl, hs2, (const uint32_t*)h->status);
   launch(h, "gather", h->batch ? k_gather<true> : k_gather<false>, blocks(n, b), b, h->cur, h->alt,
-         (const uint32_t*)h->perm, n, (const Geo*)h->geo, h->qref, h->slot, ctl, hs2,
+         (const uint32_t*)h->perm, n, (const Geo*)h->geo, h->qref, h->qid, h->slot, ctl, hs2,
          (const uint32_t*)h->status);
   launch(h, "copy_back", k_copy_back, blocks(n, b), b, h->alt, h->cur, n, ctl, hs2,
          (const uint32_t*)h->status);
   const int pb = h->pair_block;
   launch(h, "build_skin", h->batch ? k_build_skin<true> : k_build_skin<false>,
          blocks(n * kSub, pb), pb,
-         h->cur, (const uint32_t*)h->cell_start, n, (const Geo*)h->geo, h->rs2, h->skin, ctl, hs2,
-         h->status);
+         h->cur, (const QId*)h->qid, (const uint32_t*)h->cell_start, n, (const Geo*)h->geo,
+         h->rs2, h->skin, ctl, hs2, h->status);
   launch(h, "sort_skin", h->skin.cap > 96 ? k_sort_skin<128> : k_sort_skin<64>, blocks(n, 256),
          256, n, h->skin, (const uint32_t*)h->slot, ctl, hs2, (const uint32_t*)h->status);
 }

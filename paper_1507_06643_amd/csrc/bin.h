@@ -54,6 +54,12 @@ struct alignas(32) QRef {
   double x, y, z, pad;
 };
 
+// Position and identifier of a particle in one 32-byte block: what the
+// list build's candidate scans read (written by the reorder).
+struct alignas(32) QId {
+  double x, y, z, id;
+};
+
 // XCD-aware tile order: the hardware deals workgroups round-robin over the 8
 // XCDs (each with its own L2); the remap makes XCD x work through one
 // contiguous share of the cell-sorted particles, a slab of the box whose
@@ -375,8 +381,8 @@ __global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncells,
 template <bool BATCH>
 __global__ void k_gather(PState src, PState dst, const uint32_t* __restrict__ perm, int64_t n,
                          const Geo* __restrict__ geo, QRef* __restrict__ qref,
-                         uint32_t* __restrict__ slot, const BuildCtl* ctl, double half_skin2,
-                         const uint32_t* status) {
+                         QId* __restrict__ qid, uint32_t* __restrict__ slot, const BuildCtl* ctl,
+                         double half_skin2, const uint32_t* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;
@@ -385,6 +391,7 @@ __global__ void k_gather(PState src, PState dst, const uint32_t* __restrict__ pe
   dst.r[i] = rc;
   dst.eps[i] = src.eps[k];
   qref[i] = QRef{rc.qx, rc.qy, rc.qz, 0.0};
+  qid[i] = QId{rc.qx, rc.qy, rc.qz, (double)rc.id};
   // memory index of every identifier row, for the neighbour-list build
   slot[(BATCH ? (uint32_t)geo[rc.rep].first : 0u) + rc.id] = (uint32_t)i;
 }

@@ -193,7 +193,7 @@ __device__ __forceinline__ uint32_t group_ballot(const Lanes& L, bool pred) {
 template <bool MI, typename Sink>
 __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
                                                 const uint32_t* __restrict__ start,
-                                                const Rec* __restrict__ R, double xi, double yi,
+                                                const QId* __restrict__ qid, double xi, double yi,
                                                 double zi, int cx, int cy, int cz, double rc2,
                                                 Sink&& sink) {
   auto range = [&](uint32_t jb, uint32_t je) {
@@ -202,8 +202,9 @@ __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
       bool take = false;
       uint32_t idj = 0;
       if (j < je) {
-        double dx = xi - R[j].qx, dy = yi - R[j].qy, dz = zi - R[j].qz;
-        idj = R[j].id;
+        const QId c = qid[j];
+        double dx = xi - c.x, dy = yi - c.y, dz = zi - c.z;
+        idj = (uint32_t)c.id;
         if constexpr (MI) {
           if (g.periodic[0]) dx = min_image(dx, g.box[0], g.half_box[0]);
           if (g.periodic[1]) dy = min_image(dy, g.box[1], g.half_box[1]);
@@ -253,8 +254,9 @@ struct SkinList {
 
 template <bool BATCH>
 __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
-    PState s, const uint32_t* __restrict__ start, int64_t n, const Geo* __restrict__ geo,
-    double rs2, SkinList sl, const BuildCtl* ctl, double half_skin2, uint32_t* status) {
+    PState s, const QId* __restrict__ qid, const uint32_t* __restrict__ start, int64_t n,
+    const Geo* __restrict__ geo, double rs2, SkinList sl, const BuildCtl* ctl, double half_skin2,
+    uint32_t* status) {
   __shared__ uint32_t lst[kListLds * (kPairBlockMax / kSub)];
   if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;  // uniform
   const Lanes L = lanes();
@@ -285,9 +287,9 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
                         interior_dim(cy, g.nc[1], g.periodic[1]) &&
                         interior_dim(cz, g.nc[2], g.periodic[2]);
   if (__all(interior))
-    scan_candidates<false>(L, g, start, R, xi, yi, zi, cx, cy, cz, rs2, sink);
+    scan_candidates<false>(L, g, start, qid, xi, yi, zi, cx, cy, cz, rs2, sink);
   else
-    scan_candidates<true>(L, g, start, R, xi, yi, zi, cx, cy, cz, rs2, sink);
+    scan_candidates<true>(L, g, start, qid, xi, yi, zi, cx, cy, cz, rs2, sink);
   if (nn > cap) {
     if (L.sub == 0) atomicOr(status, ST_OVERFLOW);
     nn = cap;
