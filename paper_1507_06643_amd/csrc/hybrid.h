@@ -222,7 +222,7 @@ __device__ bool ssa_sweep(const St& S, int64_t t0, int64_t t1, const SsaPairs& s
 }
 
 // One lane per domain (Sec. 3.2.2: SSA inside the domain), its pairs taken
-// in the order above.  The wave's domains share an LDS pool of kSsaPool
+// in the order above.  The wave's domains share an LDS pool of POOL
 // particle slots, handed out by a prefix sum of the domain sizes; a domain
 // beyond the pool sweeps in the particle arrays.  Finally 1/T of the domain's
 // particles is refreshed for the SER sweeps.  Domains are disjoint, so no two
@@ -231,12 +231,12 @@ __device__ bool ssa_sweep(const St& S, int64_t t0, int64_t t1, const SsaPairs& s
 // 1.25 times the mean size (the largest, 80 KiB, leaves two blocks per CU).
 constexpr int kSsaPoolMax = 2560;
 
-template <int kSsaPool>
+template <int POOL>
 __global__ __launch_bounds__(kWave) void k_ssa_walk(PState s, const uint32_t* __restrict__ sorted,
                                                    const uint32_t* __restrict__ dstart,
                                                    int64_t ndoms, const uint32_t* __restrict__ poff,
                                                    SsaPairs sp, Phys P, uint32_t* status) {
-  __shared__ double pool[kSsaPool * 4];
+  __shared__ double pool[POOL * 4];
   const int64_t d = (int64_t)blockIdx.x * kWave + threadIdx.x;
   const bool live = d < ndoms;
   const uint32_t b = live ? dstart[d] : 0u;
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kWave) void k_ssa_walk(PState s, const uint32_t* __
   Rec* R = s.r;
   double* eps = s.eps;
   const int64_t t0 = poff[b], t1 = min((int64_t)poff[b + c], sp.cap);
-  if (end <= (uint32_t)kSsaPool) {
+  if (end <= (uint32_t)POOL) {
     const SsaLds S{pool + 4 * (end - c)};
     for (uint32_t q = 0; q < c; ++q) {
       const uint32_t i = sorted[b + q];

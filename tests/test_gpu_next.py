@@ -174,6 +174,53 @@ def test_hybrid_step_parity(dp, ndom):
     assert abs(en[3] - eo[3]) <= TOL * abs(eo[3])
 
 
+def test_hybrid_step_parity_nonlinear_eos(dp):
+    """Hybrid with the Einstein EOS: every SSA pair takes gamma_ij from
+    temperatures found by Newton on the current internal energies."""
+    n = 3000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=54)
+    kw = dict(dt=0.01, scheme=2, ndom=(6, 6, 6), eos=1)
+    errs, en, eo, _, _ = _step_vs_oracle(dp, q, p, e, [L] * 3, kw, kw)
+    assert max(errs) < TOL, errs
+    assert abs(en[3] - eo[3]) <= TOL * abs(eo[3])
+
+
+def test_batched_hybrid_replicas_match_single_systems(dp):
+    """Replicas with different domain decompositions in one handle: each
+    equals its own single run bit for bit, stepped eagerly and by graph
+    replay."""
+    sizes, seeds = W.replica_sizes(4, 500, 3000, seed=79)
+    ndoms = [(2, 2, 2), (3, 3, 3), (1, 2, 3), (5, 5, 5)]
+    cfgs, qs, ps, es = [], [], [], []
+    for r, (nr, sd) in enumerate(zip(sizes, seeds)):
+        L = W.cubic_side(int(nr))
+        q, p, e = W.equilibrium_state(int(nr), [L] * 3, seed=3000 + r)
+        cfgs.append(dp.Config(n=int(nr), box=[L] * 3, seed=int(sd), replica=r, scheme=2,
+                              ndom=ndoms[r]))
+        qs.append(q); ps.append(p); es.append(e)
+    Q, Pm, E = np.concatenate(qs), np.concatenate(ps), np.concatenate(es)
+    b = dp.System(cfgs, Q, Pm, E)
+    b.step(6)
+    qb, pb, eb, _ = _gpu_state(b)
+    enb = b.energies()
+    for r in range(len(cfgs)):
+        s = dp.System(cfgs[r], qs[r], ps[r], es[r])
+        s.step(6)
+        q1, p1, e1, _ = _gpu_state(s)
+        lo, hi = b.offsets[r], b.offsets[r + 1]
+        assert np.array_equal(qb[lo:hi], q1)
+        assert np.array_equal(pb[lo:hi], p1)
+        assert np.array_equal(eb[lo:hi], e1)
+        assert np.array_equal(enb[r], s.energies())
+        s.close()
+    g = dp.System(cfgs, Q, Pm, E)
+    g.step_graph(2, 3)
+    assert np.array_equal(g.energies(), enb)
+    g.close()
+    b.close()
+
+
 def test_hybrid_with_fine_domains_equals_ser(dp):
     n = 3000
     L = W.cubic_side(n)
@@ -191,11 +238,15 @@ def test_hybrid_with_fine_domains_equals_ser(dp):
     b.close()
 
 
-def test_hybrid_conserves_energy(dp):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_hybrid_conserves_energy(dp, precision):
+    """SSA steps (FP64) and SER across domains (FP64 or FP32 pair terms, FP64
+    reinjection) conserve energy to round-off without conservative forces."""
     n = 4000
     L = W.cubic_side(n)
     q, p, e = W.equilibrium_state(n, [L] * 3, seed=53)
-    s = dp.System(dp.Config(n=n, box=[L] * 3, a=0.0, scheme=2, ndom=(3, 3, 3)), q, p, e)
+    s = dp.System(dp.Config(n=n, box=[L] * 3, a=0.0, scheme=2, ndom=(3, 3, 3),
+                            precision=precision), q, p, e)
     E0 = s.energies()[3]
     s.step(200)
     h = s.history()
