@@ -74,7 +74,8 @@ struct dpde_handle {
   PState cur{}, alt{};
   double half_skin2 = 0.0, rs2 = 0.0;
   QRef* qref = nullptr;
-  QId* qid = nullptr;  // build-time positions and identifiers, cell order
+  QIdF* qid = nullptr;  // build-time FP32 positions and identifiers, cell order
+  double box_max = 0.0;  // largest box side over the replicas
   uint32_t* slot = nullptr;  // memory index of each identifier row
   BuildCtl* ctl = nullptr;
   unsigned long long* builds = nullptr;
@@ -446,8 +447,8 @@ void enqueue_bin(dpde_handle* h, int kick) {
   const int pb = h->pair_block;
   launch(h, "build_skin", h->batch ? k_build_skin<true> : k_build_skin<false>,
          blocks(n * kSub, pb), pb,
-         h->cur, (const QId*)h->qid, (const uint32_t*)h->cell_start, n, (const Geo*)h->geo,
-         h->rs2, h->skin, ctl, hs2, h->status);
+         h->cur, (const QIdF*)h->qid, (const uint32_t*)h->cell_start, n, (const Geo*)h->geo,
+         std::sqrt(h->rs2), h->box_max, h->skin, ctl, hs2, h->status);
   launch(h, "sort_skin", h->skin.cap > 96 ? k_sort_skin<128> : k_sort_skin<64>, blocks(n, 256),
          256, n, h->skin, (const uint32_t*)h->slot, ctl, hs2, (const uint32_t*)h->status);
 }
@@ -716,6 +717,7 @@ int create(const dpde_params* params, int nrep, const int64_t* offsets, const do
     }
     Geo g{};
     if ((rc = geometry(&params[r], g))) { release(h); return rc; }
+    for (int d = 0; d < 3; ++d) h->box_max = std::max(h->box_max, params[r].box[d]);
     g.cell_base = cells;
     g.first = h->offsets[r];
     g.n = params[r].n;

@@ -44,6 +44,7 @@ struct BuildCtl {
   unsigned long long dmax_bits;
   uint32_t force;
   uint32_t pad;
+  unsigned long long qmax_bits;  // largest |coordinate| outside the box this step
 };
 
 __device__ __forceinline__ bool rebuild_now(const BuildCtl* c, double half_skin2) {
@@ -54,10 +55,13 @@ struct alignas(32) QRef {
   double x, y, z, pad;
 };
 
-// Position and identifier of a particle in one 32-byte block: what the
-// list build's candidate scans read (written by the reorder).
-struct alignas(32) QId {
-  double x, y, z, id;
+// Position (FP32) and identifier of a particle in 16 bytes: what the list
+// build's candidate scans read (written by the reorder).  The FP32 distance
+// test is widened by a bound on its rounding error, so a list still holds
+// every pair within rc + skin; the exact r < rc filter of each step is FP64.
+struct alignas(16) QIdF {
+  float x, y, z;
+  uint32_t id;
 };
 
 // XCD-aware tile order: the hardware deals workgroups round-robin over the 8
@@ -137,7 +141,7 @@ __global__ void k_kick(PState s, const double* __restrict__ Fx, const double* __
   // no early return: every thread reaches the block barrier below (another
   // block may raise the status while this one runs)
   const bool run = !status_set(status);
-  double d2 = 0.0;
+  double d2 = 0.0, qa = 0.0;
   if (run && i < n) {
     Rec rc = s.r[i];
     const Geo& g = geo[BATCH ? rc.rep : 0u];
@@ -161,6 +165,11 @@ __global__ void k_kick(PState s, const double* __restrict__ Fx, const double* __
     if (!(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]))) {
       atomicOr(status, ST_NONFINITE);
     } else {
+      // coordinates outside [0, box) (free boundaries) for the list build's
+      // rounding margin; inside, the box side bounds them already
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (!(q[d] >= 0.0 && q[d] < g.box[d])) qa = fmax(qa, fabs(q[d]));
       const QRef r0 = qref[i];
       double dx = q[0] - r0.x, dy = q[1] - r0.y, dz = q[2] - r0.z;
       if (g.periodic[0]) dx = min_image(dx, g.box[0], g.half_box[0]);
@@ -169,9 +178,22 @@ __global__ void k_kick(PState s, const double* __restrict__ Fx, const double* __
       d2 = dx * dx + dy * dy + dz * dz;
     }
   }
-  // block maximum, then one atomic per block and only when it raises the
-  // running maximum (non-negative doubles order like their bit patterns; a
-  // stale read can only be smaller than the true value, never skip a raise)
+  // |q| outside the box only occurs with free boundaries: waves that have
+  // any take their maximum and one atomic (when it raises the running one)
+  if (__any(qa > 0.0)) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) qa = fmax(qa, __shfl_xor(qa, off, kWave));
+    if ((threadIdx.x % kWave) == 0 && run) {
+      const unsigned long long qbits = (unsigned long long)__double_as_longlong(qa);
+      const unsigned long long qcur =
+          __hip_atomic_load(&ctl->qmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (qbits > qcur) atomicMax(&ctl->qmax_bits, qbits);
+    }
+  }
+  // block maximum of the displacement, then one atomic per block and only
+  // when it raises the running maximum (non-negative doubles order like their
+  // bit patterns; a stale read can only be smaller than the true value, never
+  // skip a raise)
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) d2 = fmax(d2, __shfl_xor(d2, off, kWave));
   __shared__ double wmax[kAuxMaxThreads / kWave];
@@ -381,7 +403,7 @@ __global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncells,
 template <bool BATCH>
 __global__ void k_gather(PState src, PState dst, const uint32_t* __restrict__ perm, int64_t n,
                          const Geo* __restrict__ geo, QRef* __restrict__ qref,
-                         QId* __restrict__ qid, uint32_t* __restrict__ slot, const BuildCtl* ctl,
+                         QIdF* __restrict__ qid, uint32_t* __restrict__ slot, const BuildCtl* ctl,
                          double half_skin2, const uint32_t* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -391,7 +413,7 @@ __global__ void k_gather(PState src, PState dst, const uint32_t* __restrict__ pe
   dst.r[i] = rc;
   dst.eps[i] = src.eps[k];
   qref[i] = QRef{rc.qx, rc.qy, rc.qz, 0.0};
-  qid[i] = QId{rc.qx, rc.qy, rc.qz, (double)rc.id};
+  qid[i] = QIdF{(float)rc.qx, (float)rc.qy, (float)rc.qz, rc.id};
   // memory index of every identifier row, for the neighbour-list build
   slot[(BATCH ? (uint32_t)geo[rc.rep].first : 0u) + rc.id] = (uint32_t)i;
 }

@@ -190,27 +190,34 @@ __device__ __forceinline__ uint32_t group_ballot(const Lanes& L, bool pred) {
 // cell run in turn (lane sub takes run[sub], run[sub + kSub], ...) and call
 // `sink(take, j, id_j)` on every trip, `take` being r^2 < rc2 and j != i.
 // The trips are uniform across the group, so `sink` may ballot.
+__device__ __forceinline__ float min_image_f(float d, float L, float halfL) {
+  if (d > halfL) d -= L;
+  else if (d < -halfL) d += L;
+  return d;
+}
+
 template <bool MI, typename Sink>
 __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
                                                 const uint32_t* __restrict__ start,
-                                                const QId* __restrict__ qid, double xi, double yi,
-                                                double zi, int cx, int cy, int cz, double rc2,
+                                                const QIdF* __restrict__ qid, float xi, float yi,
+                                                float zi, int cx, int cy, int cz, float thr2,
                                                 Sink&& sink) {
+  const float bx = (float)g.box[0], by = (float)g.box[1], bz = (float)g.box[2];
   auto range = [&](uint32_t jb, uint32_t je) {
     for (uint32_t base = jb; base < je; base += kSub) {
       const uint32_t j = base + L.sub;
       bool take = false;
       uint32_t idj = 0;
       if (j < je) {
-        const QId c = qid[j];
-        double dx = xi - c.x, dy = yi - c.y, dz = zi - c.z;
-        idj = (uint32_t)c.id;
+        const QIdF c = qid[j];
+        float dx = xi - c.x, dy = yi - c.y, dz = zi - c.z;
+        idj = c.id;
         if constexpr (MI) {
-          if (g.periodic[0]) dx = min_image(dx, g.box[0], g.half_box[0]);
-          if (g.periodic[1]) dy = min_image(dy, g.box[1], g.half_box[1]);
-          if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
+          if (g.periodic[0]) dx = min_image_f(dx, bx, 0.5f * bx);
+          if (g.periodic[1]) dy = min_image_f(dy, by, 0.5f * by);
+          if (g.periodic[2]) dz = min_image_f(dz, bz, 0.5f * bz);
         }
-        take = dist2(dx, dy, dz) < rc2 && j != (uint32_t)L.i;
+        take = (dx * dx + dy * dy) + dz * dz < thr2 && j != (uint32_t)L.i;
       }
       sink(take, j, idj);
     }
@@ -254,9 +261,9 @@ struct SkinList {
 
 template <bool BATCH>
 __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
-    PState s, const QId* __restrict__ qid, const uint32_t* __restrict__ start, int64_t n,
-    const Geo* __restrict__ geo, double rs2, SkinList sl, const BuildCtl* ctl, double half_skin2,
-    uint32_t* status) {
+    PState s, const QIdF* __restrict__ qid, const uint32_t* __restrict__ start, int64_t n,
+    const Geo* __restrict__ geo, double rs, double box_max, SkinList sl, const BuildCtl* ctl,
+    double half_skin2, uint32_t* status) {
   __shared__ uint32_t lst[kListLds * (kPairBlockMax / kSub)];
   if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;  // uniform
   const Lanes L = lanes();
@@ -265,6 +272,15 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
   const Rec* __restrict__ R = s.r;
   const double xi = R[i].qx, yi = R[i].qy, zi = R[i].qz;
   const Geo& g = geo[BATCH ? R[i].rep : 0u];
+  // FP32 test radius: rs plus a bound on the rounding of the FP32 distance
+  // (conversions of coordinates up to Q = max(|q|, box), their difference,
+  // the minimum image and the squared sum stay below 8 2^-24 (Q + rs); twice
+  // that is added), rounded up
+  const double Q = fmax(__longlong_as_double((long long)ctl->qmax_bits), box_max);
+  const double thr = rs + 16.0 * 0x1p-24 * (Q + rs);
+  float thr2 = (float)(thr * thr);
+  if ((double)thr2 < thr * thr) thr2 = nextafterf(thr2, INFINITY);
+  const QIdF own = qid[i];
   const int cx = cell_coord(xi, g.scale[0], g.nc[0]);
   const int cy = cell_coord(yi, g.scale[1], g.nc[1]);
   const int cz = cell_coord(zi, g.scale[2], g.nc[2]);
@@ -287,9 +303,9 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
                         interior_dim(cy, g.nc[1], g.periodic[1]) &&
                         interior_dim(cz, g.nc[2], g.periodic[2]);
   if (__all(interior))
-    scan_candidates<false>(L, g, start, qid, xi, yi, zi, cx, cy, cz, rs2, sink);
+    scan_candidates<false>(L, g, start, qid, own.x, own.y, own.z, cx, cy, cz, thr2, sink);
   else
-    scan_candidates<true>(L, g, start, qid, xi, yi, zi, cx, cy, cz, rs2, sink);
+    scan_candidates<true>(L, g, start, qid, own.x, own.y, own.z, cx, cy, cz, thr2, sink);
   if (nn > cap) {
     if (L.sub == 0) atomicOr(status, ST_OVERFLOW);
     nn = cap;
@@ -943,6 +959,7 @@ __device__ __forceinline__ void step_end(const StepNow& c, uint64_t* d_step, int
   if (c.rebuilt) *builds = c.builds + 1ull;
   ctl->dmax_bits = 0ull;
   ctl->force = 0u;
+  ctl->qmax_bits = 0ull;
   if (advance) {
     *d_step = c.step + 1;
     *d_hist_count = c.hist + 1;

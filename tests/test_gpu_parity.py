@@ -117,6 +117,38 @@ def test_cells_and_pairs_bit_exact(dp, n, box, periodic, seed, skin):
     sysm.close()
 
 
+@pytest.mark.parametrize("skin", [0.0, 0.3])
+def test_pairs_far_outside_free_boundary(dp, skin):
+    """Particles far outside a free boundary (clamped into the end cells)
+    keep every pair.  The list build compares FP32 distances against a radius
+    widened by a bound on their rounding, which grows with the largest
+    coordinate: at x ~ 900 a pair at r = rc - 1e-6 rounds to r = rc in FP32,
+    so without the widening it would be lost (skin 0: the list radius is rc)."""
+    box = (24.0, 8.0, 8.0)
+    n = 1200
+    q, p, e = W.equilibrium_state(n, box, seed=31)
+    rng = np.random.default_rng(5)
+    q[:40] = np.array([900.0, 4.0, 4.0]) + rng.random((40, 3)) * 1.5
+    q[40:80] = np.array([-300.0, 4.0, 4.0]) + rng.random((40, 3)) * 1.5
+    q[80] = (900.0, 2.0, 2.0)
+    q[81] = (900.0 + 1.0 - 1e-6, 2.0, 2.0)
+    q[82] = (-300.0, 6.0, 6.0)
+    q[83] = (-300.0 - 1.0 + 1e-6, 6.0, 6.0)
+    sysm = dp.System(_cfg(dp, n, box, periodic=(0, 1, 1), skin=skin), q, p, e)
+    P = _oparams(n, box, periodic=(0, 1, 1))
+    got = sysm.debug_pairs()
+    assert np.array_equal(got, O.pairs(P, q, "brute"))
+    assert {(80, 81), (82, 83)} <= {tuple(x) for x in got.tolist()}
+    S = O.State(P, q, p, e)
+    rc, _ = S.step(1)
+    assert rc == 0
+    sysm.step(1)
+    qg, pg, eg, _ = _gpu_state(sysm)
+    errs = _state_errors(box, (0, 1, 1), (qg, pg, eg), (S.q, S.p, S.eps), np.abs(S.eps).mean())
+    assert max(errs) < TOL, errs
+    sysm.close()
+
+
 def test_pairs_of_evolved_state_match_brute_force(dp):
     n = 600
     L = W.cubic_side(n)
