@@ -375,25 +375,22 @@ __global__ void k_scatter(const uint32_t* __restrict__ key, const uint32_t* __re
 }
 
 // ---- digit 2: order each cell bucket by identifier ---------------------------
-__global__ void k_cell_sort(const uint32_t* __restrict__ start, int64_t ncells,
-                            uint32_t* __restrict__ perm, const uint32_t* __restrict__ idk,
-                            const BuildCtl* ctl, double half_skin2, const uint32_t* status) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncells) return;
+// Out of place: one thread per bucket slot counts the smaller identifiers of
+// its cell's bucket, which is its place in the cell.
+__global__ void k_cell_rank(const uint32_t* __restrict__ bucket, const uint32_t* __restrict__ start,
+                            const uint32_t* __restrict__ key, const uint32_t* __restrict__ idk,
+                            int64_t n, uint32_t* __restrict__ perm, const BuildCtl* ctl,
+                            double half_skin2, const uint32_t* status) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
   if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;
+  const uint32_t i = bucket[k];
+  const uint32_t c = key[i];
   const uint32_t b = start[c], e = start[c + 1];
-  for (uint32_t k = b + 1; k < e; ++k) {
-    const uint32_t v = perm[k];
-    const uint32_t kv = idk[v];
-    uint32_t m = k;
-    while (m > b) {
-      const uint32_t u = perm[m - 1];
-      if (idk[u] <= kv) break;
-      perm[m] = u;
-      --m;
-    }
-    perm[m] = v;
-  }
+  const uint32_t my = idk[i];
+  uint32_t r = 0;
+  for (uint32_t m = b; m < e; ++m) r += idk[bucket[m]] < my ? 1u : 0u;
+  perm[b + r] = i;
 }
 
 // ---- gather into the new order (list-build steps) ------------------------------
