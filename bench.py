@@ -78,6 +78,26 @@ def timed(sysm, steps, warmup):
     return t1 - t0, sysm.history()
 
 
+def timed_graph(sysm, steps, warmup, g=100):
+    """Like timed(), with the timed steps run as replays of one captured
+    g-step graph (dpde_step_graph); the capture and its first replay belong
+    to the warm-up.  A remainder that is not a multiple of g runs eagerly."""
+    import torch
+    g = max(2, min(g, steps - steps % 2))
+    reps, rem = divmod(steps, g)
+    sysm.step(warmup)
+    sysm.step_graph(g, 1)
+    sysm.history()  # drop warm-up records
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sysm.step_graph(g, reps)
+    if rem:
+        sysm.step(rem)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return t1 - t0, sysm.history()
+
+
 def drift_per_1e4(hist):
     """Slope of (E_n - E_0)/|E_0| per 10^4 steps over a timed run.  The timed
     runs start from the synthetic (unrelaxed) state, so this includes the
@@ -381,6 +401,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default block sizes (profiling runs: no tuning trials)")
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--mlp-iters", type=int, default=3000)
     ap.add_argument("--no-drift", action="store_true", help="skip the energy-drift legs")
@@ -422,11 +444,18 @@ def main():
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"[bench] surrogate trained in {t_train:.2f} s, final loss {curve[-1]:.3e}")
-    log(f"[bench] timing {args.steps} steps after {args.warmup} warm-up")
-    secs, hist = timed(sysm, args.steps, args.warmup)
+    if args.no_autotune:
+        pb, ab = 256, 256
+    else:
+        pb, ab, _ = sysm.autotune(20)
+    log(f"[bench] blocks: pair {pb}, per-particle {ab}")
+    log(f"[bench] timing {args.steps} steps (100-step graph replays) after {args.warmup} warm-up")
+    secs, hist = timed_graph(sysm, args.steps, args.warmup)
     value = n * args.steps / secs
     ms_step = 1e3 * secs / args.steps
     log(f"[bench] {value:.4e} particle-steps/s ({ms_step:.3f} ms/step)")
+    secs_e, _ = timed(sysm, 100, 0)
+    eager_ms = 1e3 * secs_e / 100
     prof = kernel_profile(sysm, args.profile_steps)
     nbar = mean_neighbours(sysm, n)
     # skin-list length from the density of the uniform fluid: pairs within rc + skin
@@ -483,7 +512,10 @@ def main():
         "config": {"workload": "learned-EOS N=1,048,576 density 3, Einstein EOS (n=50, w=2, c0=10) "
                                "via BF16 surrogate + Newton fallback, dt=0.005, FP64 pair terms",
                    "n": n, "dt": dt, "precision": "fp64", "theta": "mlp+newton-fallback",
-                   "skin": cfg.skin, "list_builds_per_step": builds_per_step},
+                   "skin": cfg.skin, "list_builds_per_step": builds_per_step,
+                   "execution": "replays of a captured 100-step graph",
+                   "blocks": [pb, ab], "autotuned": not args.no_autotune},
+        "eager_ms_per_step": eager_ms,
         "roofline": roof,
         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in prof.items()},
         "timed_run_energy_slope_per_1e4": drift_per_1e4(hist),
@@ -500,7 +532,9 @@ def main():
             s2, _, _, _ = make_system(dp, W, n, eos=eos, theta_mode=tm, precision=prec, dt=vdt)
             if tm != dp.THETA_NEWTON:
                 s2.mlp_train(nsamples=10**6, iters=args.mlp_iters, batch=4096, lr=3e-3)
-            sec2, h2 = timed(s2, max(50, args.steps // 2), 10)
+            if not args.no_autotune:
+                s2.autotune(20)
+            sec2, h2 = timed_graph(s2, max(50, args.steps // 2), 10)
             p2 = kernel_profile(s2, args.profile_steps)
             variants[name] = {"value": n * max(50, args.steps // 2) / sec2,
                               "ms_per_step": 1e3 * sec2 / max(50, args.steps // 2),
