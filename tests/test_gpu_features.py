@@ -116,7 +116,7 @@ def test_step_parity_einstein_eos(dp):
 # ---------------------------------------------------------------------------
 # Surrogate network: GPU gradients vs the oracle's FP64 backprop, BF16
 # inference vs the oracle forward on the BF16-rounded weights, training, and
-# the error of the surrogate temperature judged by Newton.
+# the error of the surrogate temperature against Newton's.
 # ---------------------------------------------------------------------------
 def _bf16_round(w):
     w = np.asarray(w, dtype=np.float32)
