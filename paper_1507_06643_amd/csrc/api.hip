@@ -83,7 +83,7 @@ struct dpde_handle {
   bool regen = false;  // regenerate the noise in sweep 2 instead of storing dp_ij
   double *Fx = nullptr, *Fy = nullptr, *Fz = nullptr;
   Vec4* dpi = nullptr;  // dp_i of SER sweep 1
-  Vec4* hv = nullptr;   // (p_i + dp_i/2) / m
+  H3* hv = nullptr;   // (p_i + dp_i/2) / m
   double* deps = nullptr;
   uint32_t* idk = nullptr;
   double* Ui = nullptr;
@@ -544,7 +544,7 @@ void enqueue_fd_t(dpde_handle* h) {
     const int mode = h->mlp.trained ? h->phys.theta_mode : 0;
     auto pass_c = [&](auto kern) {
       launch(h, "pass_c_ser", kern, blocks(n * kSub, b), b, h->cur, h->nl, n, (const Geo*)h->geo,
-             h->phys, d_step, (const Vec4*)h->dpi, (const Vec4*)h->hv, inl, m, mode, h->alt.r,
+             h->phys, d_step, (const Vec4*)h->dpi, (const H3*)h->hv, inl, m, mode, h->alt.r,
              h->status);
     };
     if (h->regen) {

@@ -680,13 +680,18 @@ __device__ __forceinline__ void load_dp(const NList& nl, int64_t e, double& x, d
   }
 }
 
+// h_i = (p_i + dp_i/2)/m packed in 24 bytes (gathered by sweep 2)
+struct H3 {
+  double x, y, z;
+};
+
 // ---------------------------------------------------------------------------
 // Pass B (SER sweep 1, and the whole SEM update of eq. SEM_fd).
 // ---------------------------------------------------------------------------
 template <bool BATCH, int PREC, int SCHEME, int MODEL>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
-    const uint64_t* __restrict__ d_step, Vec4* __restrict__ dpi, Vec4* __restrict__ hv,
+    const uint64_t* __restrict__ d_step, Vec4* __restrict__ dpi, H3* __restrict__ hv,
     double* __restrict__ deps, int store, const uint32_t* __restrict__ dom, uint32_t* status) {
   const Lanes L = lanes();
   if (L.i >= n) return;  // uniform in the group
@@ -731,8 +736,8 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
   if constexpr (SCHEME == 1) de = group_sum(de);
   if (L.sub == 0) {
     dpi[i] = Vec4{ax, ay, az, 0.0};
-    hv[i] = Vec4{fma(ax, P.inv_2m, a.px * P.inv_mass), fma(ay, P.inv_2m, a.py * P.inv_mass),
-                 fma(az, P.inv_2m, a.pz * P.inv_mass), 0.0};
+    hv[i] = H3{fma(ax, P.inv_2m, a.px * P.inv_mass), fma(ay, P.inv_2m, a.py * P.inv_mass),
+                 fma(az, P.inv_2m, a.pz * P.inv_mass)};
     if constexpr (SCHEME == 1) deps[i] = de;
   }
 }
@@ -764,7 +769,7 @@ template <bool BATCH, int PREC, int REGEN, int MODEL, int THETA>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
     const uint64_t* __restrict__ d_step, const Vec4* __restrict__ dpi,
-    const Vec4* __restrict__ hv, int eos_inline, MlpDev m, int mlp_mode, Rec* __restrict__ out,
+    const H3* __restrict__ hv, int eos_inline, MlpDev m, int mlp_mode, Rec* __restrict__ out,
     uint32_t* status) {
   __shared__ float net_x[kPairBlockMax / kSub];
   __shared__ float net_y[kPairBlockMax / kSub];
@@ -790,7 +795,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
     const Geo& g = geo[BATCH ? a.rep : 0u];
     const bool mi = REGEN ? !__all(away_from_faces(g, P, a.qx, a.qy, a.qz)) : true;
     di = dpi[i];
-    const Vec4 hi = hv[i];
+    const H3 hi = hv[i];
     const uint32_t nn = nl.count[i];
     const int64_t st = nl.stride;
     uint32_t jn = (uint32_t)L.sub < nn ? nl.idx[(int64_t)L.sub * st + i] : 0u;
