@@ -1,0 +1,99 @@
+"""The FP32 distance tests of the list build are widened by 16 2^-24 (Q + rs)
+(Q bounds every coordinate, rs is the list radius), stated to be twice a
+bound on the rounding of the FP32 distance.  This checks that bound on the
+host: the kernel's FP32 steps (conversion of FP64 coordinates, difference,
+minimum image against the FP32 box side, squared sum, with or without fused
+multiply-adds) emulated in numpy, against the exact FP64 distance, on
+coordinates up to Q, including pairs across periodic faces and far outside a
+free boundary."""
+import numpy as np
+
+U = 2.0 ** -24
+
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float32)
+
+
+def _fma32(a, b, c):
+    # a*b is exact in FP64 for FP32 operands; one rounding to FP32 after the add
+    return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(np.float32)
+
+
+def _min_image32(d, L):
+    L = np.float32(L)
+    h = np.float32(0.5) * L
+    return np.where(d > h, d - L, np.where(d < -h, d + L, d)).astype(np.float32)
+
+
+def _dist_fp32(qi, qj, box, periodic, fused):
+    d = []
+    for k in range(3):
+        dk = (_f32(qi[:, k]) - _f32(qj[:, k])).astype(np.float32)
+        if periodic[k]:
+            dk = _min_image32(dk, box[k])
+        d.append(dk)
+    if fused:
+        s = _fma32(d[1], d[1], (d[2] * d[2]).astype(np.float32))
+        s = _fma32(d[0], d[0], s)
+    else:
+        s = ((d[0] * d[0]).astype(np.float32) + (d[1] * d[1]).astype(np.float32)).astype(np.float32)
+        s = (s + (d[2] * d[2]).astype(np.float32)).astype(np.float32)
+    return np.sqrt(s.astype(np.float64))
+
+
+def _dist_exact(qi, qj, box, periodic):
+    d = qi - qj
+    for k in range(3):
+        if periodic[k]:
+            d[:, k] -= box[k] * np.round(d[:, k] / box[k])
+    return np.sqrt((d * d).sum(axis=1))
+
+
+def _pairs(rng, n, box, periodic, rs, far=0.0):
+    box = np.asarray(box, dtype=np.float64)
+    qi = rng.random((n, 3)) * box
+    # neighbours within ~1.2 rs, some across periodic faces
+    qj = qi + (rng.random((n, 3)) - 0.5) * 2.4 * rs / np.sqrt(3.0)
+    for k in range(3):
+        if periodic[k]:
+            qj[:, k] %= box[k]
+    if far:
+        m = n // 4
+        shift = rng.choice([-far, far + box[0]], size=m)
+        qi[:m, 0] += shift
+        qj[:m, 0] += shift
+    return qi, qj
+
+
+def test_fp32_distance_error_within_half_the_margin():
+    rng = np.random.default_rng(11)
+    rs = 1.3
+    cases = [((70.44, 70.44, 70.44), (1, 1, 1), 0.0),
+             ((400.0, 20.0, 20.0), (0, 1, 1), 0.0),
+             ((24.0, 8.0, 8.0), (0, 1, 1), 900.0),
+             ((6.93, 6.93, 6.93), (1, 1, 1), 0.0)]
+    for box, periodic, far in cases:
+        qi, qj = _pairs(rng, 200000, box, periodic, rs, far)
+        Q = max(max(box), np.abs(qi).max(), np.abs(qj).max())
+        bound = 8.0 * U * (Q + rs)
+        r = _dist_exact(qi.copy(), qj.copy(), box, periodic)
+        near = r < 1.5 * rs
+        for fused in (False, True):
+            rf = _dist_fp32(qi, qj, box, periodic, fused)
+            err = np.abs(rf - r)[near].max()
+            assert err <= bound, (box, far, fused, err, bound)
+            # and it is not vacuous: the error reaches a sizeable part of it
+            assert err > 0.01 * bound
+
+
+def test_margin_keeps_pairs_that_fp32_alone_loses():
+    """A pair at rc - 1e-6 near x = 900: FP32 alone puts it at or beyond rc,
+    the widened radius keeps it."""
+    rc = 1.0
+    qi = np.array([[900.0, 2.0, 2.0]])
+    qj = np.array([[900.0 + rc - 1e-6, 2.0, 2.0]])
+    rf = _dist_fp32(qi, qj, (24.0, 8.0, 8.0), (0, 1, 1), False)[0]
+    assert rf >= rc
+    Q = 900.0 + rc
+    assert rf < rc + 16.0 * U * (Q + rc)
