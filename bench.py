@@ -542,6 +542,13 @@ def main():
                               "timed_run_energy_slope_per_1e4": drift_per_1e4(h2)}
             s2.close()
         line["variants"] = variants
+        # speed of the FP32-pair-term + surrogate form relative to plain FP64
+        # (linear EOS) and to FP64 with Newton on the same EOS; the drift legs
+        # give both precisions' drift at dt = 0.005
+        v32 = variants["fp32_pairs_learned_eos"]["value"]
+        line["fp32_surrogate_speedup"] = {
+            "vs_plain_fp64_linear_eos": v32 / variants["plain_fp64_linear_eos"]["value"],
+            "vs_fp64_newton_same_eos": v32 / variants["fp64_newton_learned_eos"]["value"]}
     if not args.no_legs:
         log("[bench] batched replicas: 256 systems, one captured graph, autotuned blocks")
         line["batched_replicas"] = batched_leg(dp, W)
