@@ -72,6 +72,11 @@ extern "C" {
                              /* order; then the other pairs by SER on the updated  */
                              /* state.  Results depend on the decomposition, as   */
                              /* the paper notes.  Vector model, stored increments */
+                             /* only.  SSA is sequential inside a domain, so its  */
+                             /* cost grows with the domain size (tens of          */
+                             /* particles per domain suit the GPU); the handle    */
+                             /* reserves room for n * cap / 2 intra-domain pairs  */
+                             /* of 40 bytes each (cap = the list capacity).       */
 
 /* Direction of friction and noise (Sec. 2.1). */
 #define DPDE_MODEL_VECTOR 0  /* along v_ij with a 3-d Gaussian G_ij (eq. DPDE,    */
