@@ -288,6 +288,41 @@ def test_batched_graph_replay(dp):
     g.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_learned_eos_replicas_match_single_systems(dp, eos_system, precision):
+    """Replicas stepped with the learned EOS (the surrogate evaluated inside
+    sweep 2) and FP64 or FP32 pair terms equal their single runs bit for
+    bit, with one set of network weights."""
+    eos_system.mlp_train(nsamples=200000, iters=300, batch=4096, lr=3e-3, seed=9)
+    w, norm = eos_system.mlp_get()
+    sizes, seeds = W.replica_sizes(4, 500, 3000, seed=80)
+    cfgs, qs, ps, es = [], [], [], []
+    for r, (nr, sd) in enumerate(zip(sizes, seeds)):
+        L = W.cubic_side(int(nr))
+        q, p, e = W.equilibrium_state(int(nr), [L] * 3, seed=4000 + r, eps0=25.0)
+        cfgs.append(dp.Config(n=int(nr), box=[L] * 3, seed=int(sd), replica=r, dt=0.005,
+                              eos=dp.EOS_EINSTEIN, theta_mode=dp.THETA_MLP,
+                              precision=precision))
+        qs.append(q); ps.append(p); es.append(e)
+    b = dp.System(cfgs, np.concatenate(qs), np.concatenate(ps), np.concatenate(es))
+    b.mlp_set(w, norm)
+    b.step(6)
+    qb, pb, eb, _ = _gpu_state(b)
+    enb = b.energies()
+    for r in range(len(cfgs)):
+        s = dp.System(cfgs[r], qs[r], ps[r], es[r])
+        s.mlp_set(w, norm)
+        s.step(6)
+        q1, p1, e1, _ = _gpu_state(s)
+        lo, hi = b.offsets[r], b.offsets[r + 1]
+        assert np.array_equal(qb[lo:hi], q1)
+        assert np.array_equal(pb[lo:hi], p1)
+        assert np.array_equal(eb[lo:hi], e1)
+        assert np.array_equal(enb[r], s.energies())
+        s.close()
+    b.close()
+
+
 # ---------------------------------------------------------------------------
 # SEM (Sec. 3.1.1): one step against the oracle's SEM.
 # ---------------------------------------------------------------------------
