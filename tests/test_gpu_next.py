@@ -253,3 +253,52 @@ def test_hybrid_conserves_energy(dp, precision):
     s.close()
     assert np.abs(h[:, 3] - E0).max() < 1e-12 * abs(E0)
     assert np.abs(h[:, 4:7]).max() < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Batched replicas with the next rows' options: every replica equals its own
+# single run bit for bit (per-replica E0 for the projection, per-replica
+# geometry for the LJ lattices).
+# ---------------------------------------------------------------------------
+def _batch_equals_singles(dp, cfgs, qs, ps, es, steps):
+    b = dp.System(cfgs, np.concatenate(qs), np.concatenate(ps), np.concatenate(es))
+    b.step(steps)
+    qb, pb, eb, _ = _gpu_state(b)
+    enb = b.energies()
+    for r in range(len(cfgs)):
+        s = dp.System(cfgs[r], qs[r], ps[r], es[r])
+        s.step(steps)
+        q1, p1, e1, _ = _gpu_state(s)
+        lo, hi = b.offsets[r], b.offsets[r + 1]
+        assert np.array_equal(qb[lo:hi], q1), r
+        assert np.array_equal(pb[lo:hi], p1), r
+        assert np.array_equal(eb[lo:hi], e1), r
+        assert np.array_equal(enb[r], s.energies()), r
+        s.close()
+    b.close()
+
+
+@pytest.mark.parametrize("kw", [dict(project=True), dict(project=True, scheme=1),
+                                dict(model=1), dict(model=1, precision=1)])
+def test_batched_next_rows_match_single_systems(dp, kw):
+    sizes, seeds = W.replica_sizes(4, 500, 3000, seed=81)
+    cfgs, qs, ps, es = [], [], [], []
+    for r, (nr, sd) in enumerate(zip(sizes, seeds)):
+        L = W.cubic_side(int(nr))
+        q, p, e = W.equilibrium_state(int(nr), [L] * 3, seed=5000 + r)
+        cfgs.append(dp.Config(n=int(nr), box=[L] * 3, seed=int(sd), replica=r, dt=0.01, **kw))
+        qs.append(q); ps.append(p); es.append(e)
+    _batch_equals_singles(dp, cfgs, qs, ps, es, 6)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_lj_replicas_match_single_systems(dp, precision):
+    cfgs, qs, ps, es = [], [], [], []
+    for r, side in enumerate((8, 9, 10)):
+        q, p, e, box = W.lattice_state(side, 0.8095, eps0=50.0, seed=6000 + r)
+        cfgs.append(dp.Config(n=side ** 3, box=list(box), seed=11 + r, replica=r, dt=0.002,
+                              cv=50.0, gamma=8.0, neighbor_cap=128, precision=precision,
+                              **LJ))
+        qs.append(q); ps.append(p); es.append(e)
+    _batch_equals_singles(dp, cfgs, qs, ps, es, 6)
+
