@@ -261,8 +261,15 @@ def test_hybrid_conserves_energy(dp, precision):
 # geometry for the LJ lattices).
 # ---------------------------------------------------------------------------
 def _batch_equals_singles(dp, cfgs, qs, ps, es, steps):
-    b = dp.System(cfgs, np.concatenate(qs), np.concatenate(ps), np.concatenate(es))
+    Q, P, E = np.concatenate(qs), np.concatenate(ps), np.concatenate(es)
+    # the same batch replayed from a captured graph (steps / 2 replays of 2)
+    g = dp.System(cfgs, Q, P, E)
+    g.step_graph(2, steps // 2)
+    eng = g.energies()
+    g.close()
+    b = dp.System(cfgs, Q, P, E)
     b.step(steps)
+    assert np.array_equal(eng, b.energies())
     qb, pb, eb, _ = _gpu_state(b)
     enb = b.energies()
     for r in range(len(cfgs)):
