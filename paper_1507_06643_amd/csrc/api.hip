@@ -532,18 +532,18 @@ void enqueue_fd_t(dpde_handle* h) {
   const uint32_t* dom = h->hybrid ? (const uint32_t*)h->dom : nullptr;
   if (h->hybrid) enqueue_hybrid_ssa<B>(h);
   if (h->phys.scheme == DPDE_SCHEME_SEM) {
-    launch(h, "pass_b_sem", k_pass_b<B, PR, 1, MD>, blocks(n * kSub, b), b, h->cur, h->nl, n,
+    launch(h, "pass_b_sem", k_pass_b<B, PR, 1, MD>, blocks(n * kSubSer, b), b, h->cur, h->nl, n,
            (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, 0, dom, h->status);
     launch(h, "apply_sem", k_apply_sem, blocks(n, h->aux_block), h->aux_block, h->cur, n, h->phys,
            (const Vec4*)h->dpi, (const double*)h->deps, inl, h->alt.r, h->status);
   } else {
-    launch(h, "pass_b_ser", k_pass_b<B, PR, 0, MD>, blocks(n * kSub, b), b, h->cur, h->nl, n,
+    launch(h, "pass_b_ser", k_pass_b<B, PR, 0, MD>, blocks(n * kSubSer, b), b, h->cur, h->nl, n,
            (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, store, dom, h->status);
     // the surrogate's 1/T_i is computed inside sweep 2 (learned-EOS modes)
     const MlpDev m = mlp_dev(h->mlp);
     const int mode = h->mlp.trained ? h->phys.theta_mode : 0;
     auto pass_c = [&](auto kern) {
-      launch(h, "pass_c_ser", kern, blocks(n * kSub, b), b, h->cur, h->nl, n, (const Geo*)h->geo,
+      launch(h, "pass_c_ser", kern, blocks(n * kSubSer, b), b, h->cur, h->nl, n, (const Geo*)h->geo,
              h->phys, d_step, (const Vec4*)h->dpi, (const H3*)h->hv, inl, m, mode, h->alt.r,
              h->status);
     };

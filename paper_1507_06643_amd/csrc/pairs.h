@@ -154,6 +154,10 @@ __device__ __forceinline__ void separation_mi(const Geo& g, bool mi, double xi, 
 // ---------------------------------------------------------------------------
 constexpr int kSub = 4;
 constexpr uint32_t kSubMask = (1u << kSub) - 1u;
+// The SER sweeps (passes B and C) use pairs of lanes: with ~12 neighbours
+// their pair terms keep more lanes busy per trip, while the filters over the
+// ~27 skin candidates (pass A, list build) are faster with four.
+constexpr int kSubSer = 2;
 constexpr int kListLds = 64;  // list entries per particle staged in LDS
 
 struct Lanes {
@@ -164,20 +168,22 @@ struct Lanes {
   int shift;     // position of the group's bits in a wave ballot
 };
 
+template <int KS = kSub>
 __device__ __forceinline__ Lanes lanes() {
   Lanes L;
   const int64_t t = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  L.i = t / kSub;
-  L.sub = threadIdx.x % kSub;
-  L.pib = threadIdx.x / kSub;
-  L.ppb = blockDim.x / kSub;
-  L.shift = (threadIdx.x % kWave) & ~(kSub - 1);
+  L.i = t / KS;
+  L.sub = threadIdx.x % KS;
+  L.pib = threadIdx.x / KS;
+  L.ppb = blockDim.x / KS;
+  L.shift = (threadIdx.x % kWave) & ~(KS - 1);
   return L;
 }
 
+template <int KS = kSub>
 __device__ __forceinline__ double group_sum(double x) {
 #pragma unroll
-  for (int off = 1; off < kSub; off <<= 1) x += __shfl_xor(x, off, kWave);
+  for (int off = 1; off < KS; off <<= 1) x += __shfl_xor(x, off, kWave);
   return x;
 }
 
@@ -693,7 +699,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
     const uint64_t* __restrict__ d_step, Vec4* __restrict__ dpi, H3* __restrict__ hv,
     double* __restrict__ deps, int store, const uint32_t* __restrict__ dom, uint32_t* status) {
-  const Lanes L = lanes();
+  const Lanes L = lanes<kSubSer>();
   if (L.i >= n) return;  // uniform in the group
   if (status_set(status)) return;
   const int64_t i = L.i;
@@ -710,7 +716,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
   double ax = 0.0, ay = 0.0, az = 0.0, de = 0.0;
   // no software pipeline: the registers a prefetched record would hold buy
   // one more wave per SIMD, which hides the gather latency better
-  for (uint32_t k = L.sub; k < nn; k += kSub) {
+  for (uint32_t k = L.sub; k < nn; k += kSubSer) {
     const int64_t e = (int64_t)k * st + i;
     const uint32_t j = nl.idx[e];
     const Rec b = R[j];
@@ -730,10 +736,10 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
             0.5 * P.sigma * o.w * o.gdotv * P.sqrt_dt;
     }
   }
-  ax = group_sum(ax);
-  ay = group_sum(ay);
-  az = group_sum(az);
-  if constexpr (SCHEME == 1) de = group_sum(de);
+  ax = group_sum<kSubSer>(ax);
+  ay = group_sum<kSubSer>(ay);
+  az = group_sum<kSubSer>(az);
+  if constexpr (SCHEME == 1) de = group_sum<kSubSer>(de);
   if (L.sub == 0) {
     dpi[i] = Vec4{ax, ay, az, 0.0};
     hv[i] = H3{fma(ax, P.inv_2m, a.px * P.inv_mass), fma(ay, P.inv_2m, a.py * P.inv_mass),
@@ -771,10 +777,10 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
     const uint64_t* __restrict__ d_step, const Vec4* __restrict__ dpi,
     const H3* __restrict__ hv, int eos_inline, MlpDev m, int mlp_mode, Rec* __restrict__ out,
     uint32_t* status) {
-  __shared__ float net_x[kPairBlockMax / kSub];
-  __shared__ float net_y[kPairBlockMax / kSub];
+  __shared__ float net_x[kPairBlockMax / kSubSer];
+  __shared__ float net_y[kPairBlockMax / kSubSer];
   __shared__ uint32_t st_flag;
-  const Lanes L = lanes();
+  const Lanes L = lanes<kSubSer>();
   const bool live = L.i < n;  // uniform in the group
   if constexpr (THETA) {
     if (threadIdx.x == 0) st_flag = *status;
@@ -805,12 +811,12 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
       hy = hv[jn].y;
       hz = hv[jn].z;
     }
-    for (uint32_t k = L.sub; k < nn; k += kSub) {
+    for (uint32_t k = L.sub; k < nn; k += kSubSer) {
       const int64_t e = (int64_t)k * st + i;
       const uint32_t j = jn;
       const double ux = hi.x - hx, uy = hi.y - hy, uz = hi.z - hz;
-      if (k + kSub < nn) {
-        jn = nl.idx[e + kSub * st];
+      if (k + kSubSer < nn) {
+        jn = nl.idx[e + kSubSer * st];
         hx = hv[jn].x;
         hy = hv[jn].y;
         hz = hv[jn].z;
@@ -829,7 +835,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
       }
       de += -0.5 * (ex * ux + ey * uy + ez * uz);
     }
-    de = group_sum(de);
+    de = group_sum<kSubSer>(de);
   }
   const double e = live ? s.eps[i] + de : 1.0;
   // The record (with the old 1/T_i) is written before the network, so that
@@ -856,9 +862,9 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
     if (mlp_mode != 0) {  // uniform
       if (L.sub == 0) net_x[L.pib] = mlp_input(m, e);
       __syncthreads();
-      // waves 0 and 1 take 32 particles each
+      // wave w takes particles 32 w .. 32 w + 31 of the block
       const int w = threadIdx.x / kWave, col = threadIdx.x % 32;
-      if (w < 2 && 32 * w < L.ppb) {  // uniform in the wave
+      if (32 * w < L.ppb) {  // uniform in the wave
         const int p = 32 * w + col;
         const float yw = mlp_wave32_bf16(m.wb, p < L.ppb ? net_x[p] : 0.0f);
         if (threadIdx.x % kWave < 32) net_y[p] = yw;
