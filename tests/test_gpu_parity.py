@@ -235,6 +235,34 @@ def test_step_parity_mass_and_ragged(dp):
     assert _step_parity(dp, n, box, dt=0.004, mass=2.5, gamma=3.0, kT_ref=1.3, a=18.0) < TOL
 
 
+def test_two_particles_and_n_below_two(dp):
+    """The smallest systems: one interacting pair, and two particles out of
+    range of each other (no pair: momenta and internal energies stay exactly
+    as they were, positions drift).  n = 1 is rejected."""
+    box = [4.0] * 3
+    p = np.array([[0.3, -0.2, 0.1], [-0.3, 0.2, -0.1]])
+    e = np.array([100.0, 97.0])
+    for q, pair in ((np.array([[1.0, 1.0, 1.0], [1.5, 1.2, 1.1]]), True),
+                    (np.array([[0.5, 0.5, 0.5], [2.5, 2.5, 2.5]]), False)):
+        sysm = dp.System(_cfg(dp, 2, box, dt=0.01), q, p, e)
+        S = O.State(_oparams(2, box, dt=0.01), q, p, e)
+        for _ in range(5):
+            rc, _ = S.step(1)
+            assert rc == 0
+            sysm.step(1)
+            qg, pg, eg, _ = _gpu_state(sysm)
+            errs = _state_errors(box, (1, 1, 1), (qg, pg, eg), (S.q, S.p, S.eps), 100.0)
+            assert max(errs) < TOL, (pair, errs)
+        if pair:
+            assert np.abs(pg - p).max() > 1e-3
+        else:
+            assert np.array_equal(pg, p) and np.array_equal(eg, e)
+        sysm.close()
+    with pytest.raises(dp.DpdeError) as ex:
+        dp.System(_cfg(dp, 1, box), q[:1], p[:1], e[:1])
+    assert ex.value.code == dp._lib.DPDE_EINVAL
+
+
 # ---------------------------------------------------------------------------
 # Conservation and determinism on the GPU.
 # ---------------------------------------------------------------------------
