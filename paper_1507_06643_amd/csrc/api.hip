@@ -46,7 +46,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int kHistBytes = 64 << 20;
-constexpr int64_t kStatTile = 1024;
+constexpr int64_t kStatTile = 2048;
 
 struct ProfileRec {
   const char* name;

@@ -921,7 +921,7 @@ __global__ void k_inv_temperature(PState s, int64_t n, Phys P, uint32_t* status)
 // memory order (list rebuild schedule, batching, resume).
 // Record: U, K, sum eps, E, Px, Py, Pz, T_kin, T_int, step.
 // ---------------------------------------------------------------------------
-constexpr int kStatThreads = 256;
+constexpr int kStatThreads = 512;
 // U, K, sum eps, Px, Py, Pz, sum 1/T, |grad U|^2, Laplacian U, out-of-range count
 constexpr int kStatVals = 10;
 constexpr int kStatBad = 9;
@@ -1034,10 +1034,11 @@ __global__ __launch_bounds__(kStatFinalThreads) void k_stats_final(
       if (hrow) hrow[k] = o[k];
     }
     if (finish) {
-      __threadfence();
-      // one replica: this block is the last one
+      // one replica: this block is the last one, and the end of the kernel
+      // publishes its writes (no device-wide fence needed)
+      if (gridDim.x > 1u) __threadfence();
       if (gridDim.x == 1u || atomicAdd(ticket, 1u) == gridDim.x - 1u) {
-        __threadfence();
+        if (gridDim.x > 1u) __threadfence();
         step_end(now, d_step, d_hist_count, ctl, builds, advance);
         atomicExch(ticket, 0u);
       }
