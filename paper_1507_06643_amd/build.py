@@ -9,7 +9,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "api.hip")
 LIB = os.path.join(HERE, "libdpde.so")
-HEADERS = [os.path.join(HERE, "csrc", f) for f in ("common.h", "bin.h", "pairs.h", "eos.h", "mlp.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
