@@ -387,9 +387,16 @@ def cpu_baseline(W, n, steps, eos, dt, eps0):
     t0 = time.perf_counter()
     rc, _ = S.step(steps)
     dt_run = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": n * steps / dt_run, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} full steps of the same N={n} system after oracle init "
-                      f"({t_init:.1f} s), single thread, {dt_run:.1f} s", "rc": rc}
+                      f"({t_init:.1f} s), single thread, {dt_run:.1f} s", "rc": rc,
+            "cpu_model": model, "host_cpus_available": len(os.sched_getaffinity(0))}
 
 
 def main():
