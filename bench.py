@@ -570,6 +570,15 @@ def main():
     if not args.no_cpu:
         log(f"[bench] CPU oracle: {args.cpu_steps} steps at N={n}")
         line["cpu_baseline"] = cpu_baseline(W, n, args.cpu_steps, 1, dt, eps0)
+    # the paper's only timing of SER (its benchmark table in the section on
+    # equilibrium simulations): context, not a target -- another potential,
+    # another workload and one core of an unstated CPU
+    line["paper_context"] = {
+        "value": 1.0 / 7.85e-5, "unit": "particle-steps/s per core",
+        "hardware": "one CPU core, model not stated",
+        "workload": "SER with projection, splined LJ, density 0.8095, C_v 10, sigma 2, "
+                    "N = 144,000 over 8 processors",
+    }
     print(json.dumps(line), flush=True)
 
 
