@@ -89,3 +89,14 @@ def test_box_rule_reported():
     dummy = C.c_void_p(16)  # never dereferenced: the box check fails first
     rc = lib.dpde_init(C.byref(P), dummy, dummy, dummy, None, C.byref(h))
     assert rc == L.DPDE_EBOX, lib.dpde_last_error()
+
+
+def test_build_script_loads_without_the_built_library():
+    """build() must work in a fresh checkout, where libdpde.so does not exist
+    yet: it loads the HIP build script by path, and that import does not pull
+    in the package (whose import loads the library)."""
+    code = ("import sys, __graft_entry__ as g; "
+            "m = g._load_file('_b', 'paper_1507_06643_amd/build.py'); "
+            "assert callable(m.build) and m.LIB.endswith('libdpde.so'); "
+            "assert 'paper_1507_06643_amd' not in sys.modules")
+    subprocess.run(["python3", "-c", code], cwd=ROOT, check=True)
