@@ -341,7 +341,7 @@ def shock_leg(dp, W, steps=5000, graph_steps=100, nslab=20):
             "final_profile": profile(qg[:, 0], pg, eg)}
 
 
-def next_rows_leg(dp, W, n=N_1M, steps=100, warmup=20):
+def next_rows_leg(dp, W, n=N_1M, steps=100, warmup=20, only=None):
     """Throughput at N = 1M of the schemes beyond plain SER: SEM with the
     internal-energy projection (Sec. 4.2), friction and noise along e_ij,
     the splined LJ at the paper's density (eq. Ep), and Hybrid with 32^3
@@ -355,12 +355,16 @@ def next_rows_leg(dp, W, n=N_1M, steps=100, warmup=20):
         ("hybrid_32cubed_domains", dict(scheme=dp.SCHEME_HYBRID, ndom=(32, 32, 32), dt=0.005)),
     ]
     for name, kw in cases:
+        if only is not None and name != only:
+            continue
         log(f"[bench] next rows: {name}")
         s = dp.System(dp.Config(n=n, box=[L] * 3, **kw), q, p, e)
         secs, h = timed(s, steps, warmup)
         out[name] = {"value": n * steps / secs, "ms_per_step": 1e3 * secs / steps,
                      "timed_run_energy_slope_per_1e4": drift_per_1e4(h)}
         s.close()
+    if only is not None and only != "lj_density_0.8095":
+        return out
     side = int(round(n ** (1.0 / 3.0)))
     ql, pl, el, box = W.lattice_state(side, 0.8095, eps0=50.0, seed=20260105)
     log(f"[bench] next rows: lj_density_0.8095 (N={side ** 3})")
@@ -416,6 +420,11 @@ def main():
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the batched-replica and shock legs")
     ap.add_argument("--drift-seeds", type=int, default=8)
+    ap.add_argument("--next-row", default=None,
+                    choices=["sem_projected", "projected_model_ser", "hybrid_32cubed_domains",
+                             "lj_density_0.8095"],
+                    help="only time one of the next-row workloads at N = 1M and print its "
+                         "figures (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -441,6 +450,9 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.next_row:
+        print(json.dumps(next_rows_leg(dp, W, only=args.next_row)), flush=True)
+        return
     n = args.n
     dt = 0.005
     log(f"[bench] learned-EOS workload N={n}: init")
