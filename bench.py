@@ -425,6 +425,9 @@ def main():
                              "lj_density_0.8095"],
                     help="only time one of the next-row workloads at N = 1M and print its "
                          "figures (profiling runs)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only time the batched-replica workload and print its figures "
+                         "(profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -452,6 +455,9 @@ def main():
     torch.cuda.set_device(0)
     if args.next_row:
         print(json.dumps(next_rows_leg(dp, W, only=args.next_row)), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps(batched_leg(dp, W)), flush=True)
         return
     n = args.n
     dt = 0.005
