@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace dpde {
 
@@ -34,6 +35,14 @@ struct Geo {
   int32_t pad_dom;
   int64_t dom_base;    // global index of the replica's domain 0
 };
+
+// A kernel's view of its replica's geometry: batched kernels (one replica
+// per particle, so the fields differ across a wave) hold a copy in registers,
+// because through a reference the compiler reloads the fields after every
+// global store in their pair loops; single-system kernels keep a reference,
+// whose uniform fields load into scalar registers.
+template <bool BATCH>
+using GeoRef = std::conditional_t<BATCH, Geo, const Geo&>;
 
 // Physical parameters shared by all replicas of a handle.
 struct Phys {

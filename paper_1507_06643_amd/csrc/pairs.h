@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
   const int64_t i = L.i;
   const Rec* __restrict__ R = s.r;
   const double xi = R[i].qx, yi = R[i].qy, zi = R[i].qz;
-  const Geo& g = geo[BATCH ? R[i].rep : 0u];
+  const GeoRef<BATCH> g = geo[BATCH ? R[i].rep : 0u];
   // FP32 test radius: rs plus a bound on the rounding of the FP32 distance
   // (conversions of coordinates up to Q = max(|q|, box), their difference,
   // the minimum image and the squared sum stay below 8 2^-24 (Q + rs); twice
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
   const int64_t i = L.i;
   const Rec* __restrict__ R = s.r;
   const double xi = R[i].qx, yi = R[i].qy, zi = R[i].qz;
-  const Geo& g = geo[BATCH ? R[i].rep : 0u];
+  const GeoRef<BATCH> g = geo[BATCH ? R[i].rep : 0u];
   const uint32_t ns = sl.count[i];
   const uint32_t cap = (uint32_t)P.cap;
   const bool mi = !__all(away_from_faces(g, P, xi, yi, zi));  // uniform in the wave
@@ -706,7 +706,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
   const uint64_t step = *d_step;
   const Rec* __restrict__ R = s.r;
   const Rec a = R[i];
-  const Geo& g = geo[BATCH ? a.rep : 0u];
+  const GeoRef<BATCH> g = geo[BATCH ? a.rep : 0u];
   const bool mi = !__all(away_from_faces(g, P, a.qx, a.qy, a.qz));  // uniform in the wave
   const uint32_t nn = nl.count[i];
   const int64_t st = nl.stride;
@@ -798,7 +798,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
     const uint64_t step = *d_step;
     const Rec* __restrict__ R = s.r;
     a = R[i];
-    const Geo& g = geo[BATCH ? a.rep : 0u];
+    const GeoRef<BATCH> g = geo[BATCH ? a.rep : 0u];
     const bool mi = REGEN ? !__all(away_from_faces(g, P, a.qx, a.qy, a.qz)) : true;
     di = dpi[i];
     const H3 hi = hv[i];
