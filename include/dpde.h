@@ -313,6 +313,24 @@ int dpde_mlp_set(dpde_handle* h, const float* weights, const double* norm4);
 int dpde_mlp_grad(dpde_handle* h, const float* x, const float* t, int64_t n, float* loss,
                   float* grad);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight loops, harnesses that forbid hipMalloc): the same loss and
+ * gradient as dpde_mlp_grad, bit for bit, with the block partials, the summed
+ * gradient and the loss held in a fixed static device buffer of about 300 KB
+ * per GPU (64 block partials of DPDE_MLP_NPARAM floats), which each GPU the
+ * library runs on keeps until the process ends, instead of buffers the handle
+ * allocates on first use.  The call allocates nothing; the weights must exist
+ * (dpde_mlp_train or dpde_mlp_set).  1 <= n <= DPDE_MLP_GRAD_NOALLOC_MAX_N,
+ * else DPDE_EINVAL.  Every call on one GPU shares that buffer: calls that
+ * overlap on one GPU (several threads or streams) race and must be ordered by
+ * the caller.  x, t: device FP32 arrays of n; loss, grad: host, as in
+ * dpde_mlp_grad.
+ */
+#define DPDE_MLP_GRAD_NOALLOC_MAX_N ((int64_t)1 << 26)
+int dpde_mlp_grad_noalloc(dpde_handle* h, const float* x, const float* t, int64_t n, float* loss,
+                          float* grad);
+
 /* Network output y for normalised inputs x (device FP32 arrays of n) with the
  * BF16 inference kernel. */
 int dpde_mlp_eval(dpde_handle* h, const float* x, float* y, int64_t n);

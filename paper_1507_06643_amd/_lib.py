@@ -99,6 +99,8 @@ SIGNATURES = [
     ("dpde_mlp_get", C.c_int, [_vp, C.POINTER(C.c_float), _dp]),
     ("dpde_mlp_set", C.c_int, [_vp, C.POINTER(C.c_float), _dp]),
     ("dpde_mlp_grad", C.c_int, [_vp, _vp, _vp, _i64, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    ("dpde_mlp_grad_noalloc", C.c_int, [_vp, _vp, _vp, _i64, C.POINTER(C.c_float),
+                                        C.POINTER(C.c_float)]),
     ("dpde_mlp_eval", C.c_int, [_vp, _vp, _vp, _i64]),
     ("dpde_debug_cells", C.c_int, [_vp, _vp]),
     ("dpde_debug_pairs", C.c_int, [_vp, _vp, _i64, C.POINTER(_i64)]),

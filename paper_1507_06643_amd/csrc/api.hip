@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -754,6 +755,41 @@ int read_status(dpde_handle* h) {
   return DPDE_OK;
 }
 
+// ---- the surrogate gradient without allocation ------------------------------
+// One batch's block partials, summed gradient and loss in a fixed device
+// array instead of buffers allocated on first use.  In host code `scratch`
+// names a host-side stand-in: its device address on each GPU comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr int kNoAllocBlocks = 64;  // block partials of k_mlp_fwd_bwd (its grid is capped at 64)
+constexpr size_t kNoAllocGpart = (size_t)kNoAllocBlocks * kNParam * sizeof(float);
+constexpr size_t kNoAllocLpart = (size_t)kNoAllocBlocks * sizeof(double);
+constexpr size_t kNoAllocGsum = (size_t)kNParam * sizeof(float);
+constexpr size_t kNoAllocBytes =
+    ((kNoAllocGpart + kNoAllocLpart + kNoAllocGsum + sizeof(float)) + 255) / 256 * 256;
+static_assert(kNoAllocGpart % sizeof(double) == 0, "loss partials must stay 8-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (made current by the caller).
+int scratch_on(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(DPDE_EINVAL, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(DPDE_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device,
+                  hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[device]);
+  return DPDE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1113,6 +1149,36 @@ int dpde_mlp_grad(dpde_handle* h, const float* x, const float* t, int64_t n, flo
   std::string err;
   int rc = mlp_grad(h->mlp, h->stream, x, t, n, loss, grad, err);
   return rc ? fail(rc, "%s", err.c_str()) : DPDE_OK;
+}
+
+int dpde_mlp_grad_noalloc(dpde_handle* h, const float* x, const float* t, int64_t n, float* loss,
+                          float* grad) {
+  if (!h || !x || !t || !loss || !grad) return fail(DPDE_EINVAL, "NULL argument");
+  if (n <= 0 || n > DPDE_MLP_GRAD_NOALLOC_MAX_N)
+    return fail(DPDE_EINVAL, "n = %lld outside [1, %lld] for dpde_mlp_grad_noalloc", (long long)n,
+                (long long)DPDE_MLP_GRAD_NOALLOC_MAX_N);
+  if (!h->mlp.w) return fail(DPDE_EINVAL, "the surrogate has no weights");
+  HIPCHK(hipSetDevice(h->device));
+  unsigned char* base = nullptr;
+  int rc = scratch_on(h->device, &base);
+  if (rc) return rc;
+  float* gpart = reinterpret_cast<float*>(base);
+  double* lpart = reinterpret_cast<double*>(base + kNoAllocGpart);
+  float* gsum = reinterpret_cast<float*>(base + kNoAllocGpart + kNoAllocLpart);
+  float* lsum = reinterpret_cast<float*>(base + kNoAllocGpart + kNoAllocLpart + kNoAllocGsum);
+  // the launch shape of dpde_mlp_grad, so both give the same bits; every
+  // scratch word read below is written first by this call
+  const int gb = (int)std::min<int64_t>(kNoAllocBlocks, (n + kTrainThreads - 1) / kTrainThreads);
+  hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3(gb), dim3(kTrainThreads), 0, h->stream,
+                     (const float*)h->mlp.w, x, t, n, (int64_t)0, n, 1.0f / (float)n, gpart, lpart);
+  hipLaunchKernelGGL(k_mlp_reduce_adam, dim3(1), dim3(1024), 0, h->stream, (const float*)gpart,
+                     (const double*)lpart, gb, n, h->mlp.w, h->mlp.adam_m, h->mlp.adam_v,
+                     h->mlp.wb, 0.0f, 1.0f, 1.0f, 0, gsum, lsum);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(grad, gsum, kNParam * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(loss, lsum, sizeof(float), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DPDE_OK;
 }
 
 int dpde_mlp_eval(dpde_handle* h, const float* x, float* y, int64_t n) {

@@ -251,6 +251,18 @@ class System:
                                         g.ctypes.data_as(C.POINTER(C.c_float))))
         return loss.value, g
 
+    def mlp_grad_noalloc(self, x, t):
+        """dpde_mlp_grad_noalloc: the gradient with the library's static buffer."""
+        xd = _dev(x, torch.float32)
+        td = _dev(t, torch.float32)
+        loss = C.c_float(0.0)
+        g = np.zeros(L.MLP_NPARAM, dtype=np.float32)
+        torch.cuda.synchronize()
+        L.check(self._lib.dpde_mlp_grad_noalloc(self.h, _ptr(xd), _ptr(td), xd.numel(),
+                                                C.byref(loss),
+                                                g.ctypes.data_as(C.POINTER(C.c_float))))
+        return loss.value, g
+
     def mlp_eval(self, x):
         xd = _dev(x, torch.float32)
         y = torch.empty_like(xd)
