@@ -45,6 +45,8 @@ extern "C" {
 #define DPDE_EEOS (-6)       /* temperature inversion failed                      */
 #define DPDE_EOVERFLOW (-7)  /* a particle has more neighbours than the list cap  */
 #define DPDE_ENONFINITE (-8) /* a non-finite value appeared in the state          */
+#define DPDE_ERANGE (-9)     /* a pair term outside the fixed-point range of the  */
+                             /* SER sums (|dp_ij| or |e_ij| >= 32 in one step)    */
 
 /* Precision of the pair terms. */
 #define DPDE_FP64 0          /* everything in FP64                                */
@@ -245,6 +247,41 @@ int dpde_step_graph(dpde_handle* h, int64_t nsteps, int64_t reps);
 
 /* Kernel launch shape: block size of the pair passes (64, 128, 256, 512 or 1024). */
 int dpde_set_tuning(dpde_handle* h, int32_t pair_block, int32_t aux_block);
+
+/*
+ * Launch shapes of the step kernels and the form of the SER sweeps.  No
+ * choice changes the trajectory beyond rounding: every launch shape gives
+ * the same bits, and the two pair forms agree to rounding (their
+ * per-particle sums are added in different arithmetic), so the shape can be
+ * tuned on the live system.
+ *   pair_block  threads per block of the lane-group pair passes (64..256)
+ *   aux_block   threads per block of the per-particle passes (64..1024)
+ *   pairs       form of the SER sweeps (eqs. SER_p, SER_eint_discretization):
+ *     DPDE_PAIRS_BOTH_SIDES     every pair term evaluated on both of its
+ *                               particles' lanes and added in FP64 in
+ *                               neighbour-identifier order;
+ *     DPDE_PAIRS_ONCE_PER_TILE  a pair joining two particles of one tile of
+ *                               128 consecutive particles (cell order)
+ *                               evaluated once for both, a pair joining two
+ *                               tiles once per particle; the per-particle
+ *                               sums exact in 64-bit fixed point (grid 2^-46,
+ *                               a term of magnitude >= 32 fails the step with
+ *                               DPDE_ERANGE), rounded once.  The default; SEM
+ *                               and Hybrid run the first form.
+ * Either form gives trajectories that do not depend on the memory order, the
+ * skin, the rebuild schedule or the batching.  dpde_set_tuning sets the first
+ * two fields only.
+ */
+#define DPDE_PAIRS_BOTH_SIDES 0
+#define DPDE_PAIRS_ONCE_PER_TILE 1
+typedef struct dpde_shape {
+  int32_t pair_block;
+  int32_t aux_block;
+  int32_t pairs;
+  int32_t reserved; /* 0 */
+} dpde_shape;
+int dpde_get_shape(dpde_handle* h, dpde_shape* out);
+int dpde_set_shape(dpde_handle* h, const dpde_shape* shape);
 
 /* Autotuner: time every candidate (pair-kernel block of 64/128/256 threads x
  * per-particle block of 128/256/512) over `steps` steps of this system and keep

@@ -12,7 +12,7 @@ import torch  # noqa: F401
 from . import _lib
 from ._lib import (DpdeError, EOS_EINSTEIN, EOS_LINEAR, FP32, FP64, MODEL_PROJECTED,
                    MODEL_VECTOR, POT_LJ, POT_SOFT, SCHEME_HYBRID, SCHEME_SEM, SCHEME_SER, THETA_MLP,
-                   THETA_MLP_NEWTON, THETA_NEWTON)
+                   PAIRS_BOTH_SIDES, PAIRS_ONCE_PER_TILE, THETA_MLP_NEWTON, THETA_NEWTON)
 
 _lib.load()
 
@@ -21,4 +21,4 @@ from .system import Config, System, debug_rng  # noqa: E402
 __all__ = ["Config", "System", "debug_rng", "DpdeError", "FP32", "FP64", "EOS_LINEAR",
            "MODEL_VECTOR", "MODEL_PROJECTED", "POT_SOFT", "POT_LJ",
            "EOS_EINSTEIN", "THETA_NEWTON", "THETA_MLP", "THETA_MLP_NEWTON", "SCHEME_SER",
-           "SCHEME_SEM"]
+           "SCHEME_SEM", "PAIRS_BOTH_SIDES", "PAIRS_ONCE_PER_TILE"]

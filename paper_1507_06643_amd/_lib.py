@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libdpde.so")
 
 DPDE_OK, DPDE_EINVAL, DPDE_EBOX, DPDE_ENOMEM, DPDE_EHIP = 0, -1, -2, -3, -4
 DPDE_ENEG_EINT, DPDE_EEOS, DPDE_EOVERFLOW, DPDE_ENONFINITE = -5, -6, -7, -8
+DPDE_ERANGE = -9
 FP64, FP32 = 0, 1
 EOS_LINEAR, EOS_EINSTEIN = 0, 1
 THETA_NEWTON, THETA_MLP, THETA_MLP_NEWTON = 0, 1, 2
@@ -29,6 +30,7 @@ ERROR_NAMES = {
     DPDE_EINVAL: "DPDE_EINVAL", DPDE_EBOX: "DPDE_EBOX", DPDE_ENOMEM: "DPDE_ENOMEM",
     DPDE_EHIP: "DPDE_EHIP", DPDE_ENEG_EINT: "DPDE_ENEG_EINT", DPDE_EEOS: "DPDE_EEOS",
     DPDE_EOVERFLOW: "DPDE_EOVERFLOW", DPDE_ENONFINITE: "DPDE_ENONFINITE",
+    DPDE_ERANGE: "DPDE_ERANGE",
 }
 
 
@@ -50,6 +52,15 @@ class Params(C.Structure):
         ("flags", C.c_int32),
         ("ndom", C.c_int32 * 3),
     ]
+
+
+class Shape(C.Structure):
+    """Mirror of struct dpde_shape."""
+    _fields_ = [("pair_block", C.c_int32), ("aux_block", C.c_int32), ("pairs", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+PAIRS_BOTH_SIDES, PAIRS_ONCE_PER_TILE = 0, 1
 
 
 class MlpCfg(C.Structure):
@@ -90,6 +101,8 @@ SIGNATURES = [
     ("dpde_energies_batch", C.c_int, [_vp, _dp]),
     ("dpde_step_graph", C.c_int, [_vp, _i64, _i64]),
     ("dpde_set_tuning", C.c_int, [_vp, _i32, _i32]),
+    ("dpde_get_shape", C.c_int, [_vp, C.POINTER(Shape)]),
+    ("dpde_set_shape", C.c_int, [_vp, C.POINTER(Shape)]),
     ("dpde_autotune", C.c_int, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i32), _dp]),
     ("dpde_profile_enable", C.c_int, [_vp, _i32]),
     ("dpde_profile_read", C.c_int, [_vp, C.c_char_p, _dp, C.POINTER(_i64), _i32]),

@@ -71,6 +71,10 @@ struct dpde_handle {
   int64_t step = 0;
   int pair_block = 256;
   int aux_block = 256;
+  // SER sweeps with a pair inside a 128-particle tile evaluated once
+  // (k_pass_b_uniq, k_pass_c_uniq) rather than every pair term on both
+  // particles' lanes (k_pass_b, k_pass_c)
+  bool pairs_once = true;
 
   PState cur{}, alt{};
   double half_skin2 = 0.0, rs2 = 0.0;
@@ -413,6 +417,9 @@ int status_to_code(uint32_t st) {
   if (st & ST_NEG_EINT)
     return fail(DPDE_ENEG_EINT, "an internal energy (or temperature) became non-positive");
   if (st & ST_EOS) return fail(DPDE_EEOS, "temperature inversion failed");
+  if (st & ST_RANGE)
+    return fail(DPDE_ERANGE,
+                "a pair term left the range of the fixed-point sums (|dp_ij| or |e_ij| >= 32)");
   if (st & ST_OVERFLOW)
     return fail(DPDE_EOVERFLOW, "a particle has more neighbours than the list capacity");
   return DPDE_OK;
@@ -456,12 +463,20 @@ void enqueue_bin(dpde_handle* h, int kick) {
          256, n, h->skin, (const uint32_t*)h->slot, ctl, hs2, (const uint32_t*)h->status);
 }
 
+// The SER sweeps over the tile work lists (the default form): not for SEM,
+// whose update is not written as a sum of stored terms here, nor Hybrid,
+// whose SSA part reads the full lists.
+bool uniq_form(const dpde_handle* h) {
+  return h->pairs_once && h->phys.scheme == DPDE_SCHEME_SER && !h->hybrid;
+}
+
 void enqueue_forces(dpde_handle* h, int mode) {
   const int b = h->pair_block;
   const int64_t n = h->n;
+  const int uniq = uniq_form(h) ? 1 : 0;
   auto go = [&](auto kern) {
     launch(h, "pass_a_forces", kern, blocks(n * kSub, b), b, h->cur, n, (const Geo*)h->geo, h->phys, mode,
-           h->Fx, h->Fy, h->Fz, h->Ui, h->Li, h->skin, h->nl, h->status);
+           uniq, h->Fx, h->Fy, h->Fz, h->Ui, h->Li, h->skin, h->nl, h->status);
   };
   if (h->batch) {
     if (h->phys.precision == DPDE_FP32) go(k_pass_a<true, PREC_F32>);
@@ -538,22 +553,42 @@ void enqueue_fd_t(dpde_handle* h) {
     launch(h, "apply_sem", k_apply_sem, blocks(n, h->aux_block), h->aux_block, h->cur, n, h->phys,
            (const Vec4*)h->dpi, (const double*)h->deps, inl, h->alt.r, h->status);
   } else {
-    launch(h, "pass_b_ser", k_pass_b<B, PR, 0, MD>, blocks(n * kSubSer, b), b, h->cur, h->nl, n,
-           (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, store, dom, h->status);
+    const bool uq = uniq_form(h);
+    if (uq) {
+      launch(h, "pass_b_ser", k_pass_b_uniq<B, PR, MD>, blocks(n, kUniqTile), 2 * kUniqTile,
+             h->cur, h->nl, n, (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, store,
+             h->status);
+    } else {
+      launch(h, "pass_b_ser", k_pass_b<B, PR, 0, MD>, blocks(n * kSubSer, b), b, h->cur, h->nl,
+             n, (const Geo*)h->geo, h->phys, d_step, h->dpi, h->hv, h->deps, store, dom,
+             h->status);
+    }
     // the surrogate's 1/T_i is computed inside sweep 2 (learned-EOS modes)
     const MlpDev m = mlp_dev(h->mlp);
     const int mode = h->mlp.trained ? h->phys.theta_mode : 0;
-    auto pass_c = [&](auto kern) {
-      launch(h, "pass_c_ser", kern, blocks(n * kSubSer, b), b, h->cur, h->nl, n, (const Geo*)h->geo,
+    auto pass_c = [&](auto kern, unsigned grid, unsigned block) {
+      launch(h, "pass_c_ser", kern, grid, block, h->cur, h->nl, n, (const Geo*)h->geo,
              h->phys, d_step, (const Vec4*)h->dpi, (const H3*)h->hv, inl, m, mode, h->alt.r,
              h->status);
     };
+    const unsigned gu = blocks(n, kUniqTile), bu = 2 * kUniqTile;
+    const unsigned go = blocks(n * kSubSer, b), bo = (unsigned)b;
     if (h->regen) {
-      if (inl) pass_c(k_pass_c<B, PR, 1, MD, 0>);
-      else pass_c(k_pass_c<B, PR, 1, MD, 1>);
+      if (uq) {
+        if (inl) pass_c(k_pass_c_uniq<B, PR, 1, MD, 0>, gu, bu);
+        else pass_c(k_pass_c_uniq<B, PR, 1, MD, 1>, gu, bu);
+      } else {
+        if (inl) pass_c(k_pass_c<B, PR, 1, MD, 0>, go, bo);
+        else pass_c(k_pass_c<B, PR, 1, MD, 1>, go, bo);
+      }
     } else {
-      if (inl) pass_c(k_pass_c<B, PR, 0, MD, 0>);
-      else pass_c(k_pass_c<B, PR, 0, MD, 1>);
+      if (uq) {
+        if (inl) pass_c(k_pass_c_uniq<B, PR, 0, MD, 0>, gu, bu);
+        else pass_c(k_pass_c_uniq<B, PR, 0, MD, 1>, gu, bu);
+      } else {
+        if (inl) pass_c(k_pass_c<B, PR, 0, MD, 0>, go, bo);
+        else pass_c(k_pass_c<B, PR, 0, MD, 1>, go, bo);
+      }
     }
   }
   // the updated records were written to the spare record array: swap them in
@@ -956,6 +991,32 @@ int dpde_set_tuning(dpde_handle* h, int32_t pair_block, int32_t aux_block) {
   return DPDE_OK;
 }
 
+int dpde_get_shape(dpde_handle* h, dpde_shape* out) {
+  if (!h || !out) return fail(DPDE_EINVAL, "NULL argument");
+  out->pair_block = h->pair_block;
+  out->aux_block = h->aux_block;
+  out->pairs = h->pairs_once ? DPDE_PAIRS_ONCE_PER_TILE : DPDE_PAIRS_BOTH_SIDES;
+  out->reserved = 0;
+  return DPDE_OK;
+}
+
+int dpde_set_shape(dpde_handle* h, const dpde_shape* shape) {
+  if (!h || !shape) return fail(DPDE_EINVAL, "NULL argument");
+  if (shape->pairs != DPDE_PAIRS_BOTH_SIDES && shape->pairs != DPDE_PAIRS_ONCE_PER_TILE)
+    return fail(DPDE_EINVAL, "unknown pair form %d", shape->pairs);
+  const bool once0 = h->pairs_once;
+  h->pairs_once = shape->pairs == DPDE_PAIRS_ONCE_PER_TILE;
+  int rc = dpde_set_tuning(h, shape->pair_block, shape->aux_block);
+  if (rc) {
+    h->pairs_once = once0;
+    return rc;
+  }
+  // the lists of the current step follow the form: rebuild them
+  if (once0 != h->pairs_once) enqueue_forces(h, 0);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return read_status(h);
+}
+
 int dpde_autotune(dpde_handle* h, int32_t steps, int32_t* pair_block, int32_t* aux_block,
                   double* ms_per_step) {
   if (!h) return fail(DPDE_EINVAL, "handle is NULL");
@@ -1201,7 +1262,7 @@ int dpde_debug_pairs(dpde_handle* h, int32_t* lohi, int64_t cap, int64_t* npairs
   if (!h || !npairs || (cap > 0 && !lohi)) return fail(DPDE_EINVAL, "NULL argument");
   HIPCHK(hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream));
   launch(h, "debug_pairs", k_debug_pairs, blocks(h->n, 256), 256, h->cur, h->nl, h->n,
-         (const Geo*)h->geo, lohi, cap, h->counter);
+         (const Geo*)h->geo, uniq_form(h) ? 1 : 0, lohi, cap, h->counter);
   unsigned long long c = 0;
   HIPCHK(hipMemcpyAsync(&c, h->counter, sizeof(c), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));

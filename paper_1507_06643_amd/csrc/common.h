@@ -17,6 +17,7 @@ enum : uint32_t {
   ST_OVERFLOW = 2u,   // neighbour list capacity exceeded
   ST_NONFINITE = 4u,  // NaN/Inf in positions or momenta
   ST_EOS = 8u,        // temperature inversion failed
+  ST_RANGE = 16u,     // a pair term outside the range of the fixed-point pair sums
 };
 
 // Geometry and noise key of one system (replica).

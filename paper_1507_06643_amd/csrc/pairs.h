@@ -159,6 +159,7 @@ constexpr uint32_t kSubMask = (1u << kSub) - 1u;
 // ~27 skin candidates (pass A, list build) are faster with four.
 constexpr int kSubSer = 2;
 constexpr int kListLds = 64;  // list entries per particle staged in LDS
+constexpr int kUniqTile = 128;  // particles per tile (= block) of the unique-pair sweeps
 
 struct Lanes {
   int64_t i;     // particle
@@ -403,9 +404,14 @@ __global__ __launch_bounds__(256) void k_sort_skin(int64_t n, SkinList sl,
 // share L_i = sum_j (v'' + 2 v'/r) (eq. Tcon); mode 1 also applies
 // p += dt/2 F (end of velocity-Verlet).  v is the soft potential
 // (a rc/2)(1 - r/rc)^2 or the splined LJ of eq. Ep.
+//
+// With `uniq` the list written is the work list of the tile sweeps: a pair
+// joining two particles of one 128-particle tile is listed for its lower
+// identifier only (k_pass_b_uniq, k_pass_c_uniq).  The forces always run over
+// every pair with r < rc, in list order.
 template <bool BATCH, int PREC>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
-    PState s, int64_t n, const Geo* __restrict__ geo, Phys P, int mode,
+    PState s, int64_t n, const Geo* __restrict__ geo, Phys P, int mode, int uniq,
     double* __restrict__ Fx, double* __restrict__ Fy, double* __restrict__ Fz,
     double* __restrict__ Ui, double* __restrict__ Li, SkinList sl, NList nl, uint32_t* status) {
   __shared__ uint32_t lst[kListLds * (kPairBlockMax / kSub)];
@@ -419,9 +425,10 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
   const uint32_t ns = sl.count[i];
   const uint32_t cap = (uint32_t)P.cap;
   const bool mi = !__all(away_from_faces(g, P, xi, yi, zi));  // uniform in the wave
-  uint32_t nn = 0;
+  uint32_t nn = 0, nw = 0;  // pairs with r < rc; entries of the list written
   double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, lap = 0.0;
   const float inv_rc_f = (float)P.inv_rc, a_f = (float)P.a;
+  const uint32_t ui = (uint32_t)i;
   uint32_t jn = (uint32_t)L.sub < ns ? sl.idx[(int64_t)L.sub * sl.stride + i] : 0u;
   double qnx = 0.0, qny = 0.0, qnz = 0.0;
   if ((uint32_t)L.sub < ns) {
@@ -448,11 +455,21 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
     }
     const uint32_t bits = group_ballot(L, take);
     const uint32_t c = __popc(bits);
-    if (take) {
-      const uint32_t pos = nn + __popc(bits & ((1u << L.sub) - 1u));
+    // a pair inside a tile is listed for one of its particles only: for the
+    // lower memory index when the two indices differ in parity, else for the
+    // higher one, so that about half of every particle's pairs inside its
+    // tile stay in its list whatever its rank (the sweeps' lanes stay evenly
+    // loaded); which side evaluates a pair does not change any sum
+    const bool mine = ((ui ^ j) & 1u) ? (ui < j) : (ui > j);
+    const bool same_tile = (ui ^ j) < (uint32_t)kUniqTile;  // tiles start at multiples of 128
+    const bool keep = take && !(uniq && same_tile && !mine);
+    const uint32_t wbits = uniq ? group_ballot(L, keep) : bits;
+    if (keep) {
+      const uint32_t pos = nw + __popc(wbits & ((1u << L.sub) - 1u));
       if (pos < (uint32_t)kListLds) lst[pos * L.ppb + L.pib] = j;
       else if (pos < cap) nl.idx[(int64_t)pos * nl.stride + i] = j;
     }
+    nw += __popc(wbits);
     // the pair at list position p is summed by lane p mod kSub (as in passes
     // B and C), whichever lane tested it: lane sub owns rank r of this trip
     const uint32_t r = (uint32_t)(L.sub - (int)nn) & (uint32_t)(kSub - 1);
@@ -516,13 +533,13 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
   lap = group_sum(lap);
   if (nn > cap) {
     if (L.sub == 0) atomicOr(status, ST_OVERFLOW);
-    nn = cap;
+    nw = nw < cap ? nw : cap;
   }
-  const uint32_t staged = nn < (uint32_t)kListLds ? nn : (uint32_t)kListLds;
+  const uint32_t staged = nw < (uint32_t)kListLds ? nw : (uint32_t)kListLds;
   for (uint32_t k = L.sub; k < staged; k += kSub)
     nl.idx[(int64_t)k * nl.stride + i] = lst[k * L.ppb + L.pib];
   if (L.sub == 0) {
-    nl.count[i] = nn;
+    nl.count[i] = nw;
     Fx[i] = fx;
     Fy[i] = fy;
     Fz[i] = fz;
@@ -749,6 +766,125 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_b(
 }
 
 // ---------------------------------------------------------------------------
+// The SER sweeps with each pair inside a tile evaluated once.
+//
+// Tiles are 128 consecutive particles of the cell order (one block of the
+// sweeps, two lanes per particle).  With cells of side rc + skin about half
+// of all pairs join two particles of one tile.  Pass A leaves such a pair in
+// the list of one of its particles only, so the sweeps evaluate it once:
+// that particle adds the pair term to its own sum and, with an LDS atomic,
+// to the partner's (negated in sweep 1, as dp_ji = -dp_ij exactly; unchanged
+// in sweep 2, as the reinjection term is symmetric).  A pair joining two
+// tiles stays in both lists and is evaluated for each particle, as before.
+//
+// The per-particle sums are exact integer sums of the terms rounded once to
+// the grid 2^-46 (sums of 64-bit integers do not depend on the order of their
+// terms).  A particle's sum is therefore the same bits whichever lane, wave
+// or tile contributes each term, so trajectories still do not depend on the
+// memory order, the neighbour-list skin, the rebuild schedule or the
+// batching.  The conversion is exact-range for |term| < 32 (a momentum or
+// energy increment of one pair in one step); a larger term stops the step
+// with DPDE_ERANGE.
+// ---------------------------------------------------------------------------
+// Fixed-point pair sums.  x 2^46 is exact, and adding M = 1.5 2^52 rounds it
+// to an integer held in the low mantissa bits while |x| < 32: the bit
+// pattern of x 2^46 + M minus that of M is round(x 2^46).  A lane adds the
+// raw bit patterns and subtracts count * M once at the end.  The range is
+// tracked as the largest high word of |x| (a NaN or infinity exceeds it too).
+constexpr long long kFixMagicBits = 0x4338000000000000ll;  // bits of 1.5 2^52
+constexpr uint32_t kFixRangeHi = 0x40400000u;               // high word of 32.0
+
+__device__ __forceinline__ long long pair_fix_raw(double x) {
+  return __double_as_longlong(fma(x, 0x1p46, 0x1.8p52));
+}
+
+__device__ __forceinline__ void pair_fix_range(double x, uint32_t& hi_max) {
+  hi_max = max(hi_max, (uint32_t)(__double_as_longlong(x) >> 32) & 0x7FFFFFFFu);
+}
+
+__device__ __forceinline__ double pair_fix_value(long long v) { return (double)v * 0x1p-46; }
+
+// The tile of particle j relative to the tile starting at tb, or >= 128.
+__device__ __forceinline__ uint32_t in_tile(uint32_t j, int64_t tb) {
+  return j - (uint32_t)tb;
+}
+
+// Block status flag made uniform: one read, shared through LDS.
+__device__ __forceinline__ bool block_status_set(const uint32_t* status, uint32_t* flag) {
+  if (threadIdx.x == 0) *flag = *status;
+  __syncthreads();
+  return *flag != 0u;
+}
+
+template <bool BATCH, int PREC, int MODEL>
+__global__ __launch_bounds__(2 * kUniqTile) void k_pass_b_uniq(
+    PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
+    const uint64_t* __restrict__ d_step, Vec4* __restrict__ dpi, H3* __restrict__ hv, int store,
+    uint32_t* status) {
+  // two's-complement sums in unsigned words (the atomic add is modular)
+  __shared__ unsigned long long acc[3][kUniqTile];
+  __shared__ uint32_t st_flag;
+  for (int c = threadIdx.x; c < 3 * kUniqTile; c += blockDim.x) acc[c / kUniqTile][c % kUniqTile] = 0;
+  if (block_status_set(status, &st_flag)) return;  // uniform in the block
+  const int64_t tb = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kUniqTile;
+  const int pl = threadIdx.x >> 1, sub = threadIdx.x & 1;
+  const int64_t i = tb + pl;
+  const bool live = i < n;
+  long long X0 = 0, X1 = 0, X2 = 0;  // raw sums of fixed-point bit patterns
+  long long terms = 0;
+  uint32_t hi_max = 0u;
+  Rec a{};
+  if (live) {
+    const uint64_t step = *d_step;
+    const Rec* __restrict__ R = s.r;
+    a = R[i];
+    const GeoRef<BATCH> g = geo[BATCH ? a.rep : 0u];
+    const bool mi = !__all(away_from_faces(g, P, a.qx, a.qy, a.qz));
+    const uint32_t nn = nl.count[i];
+    const int64_t st = nl.stride;
+    for (uint32_t k = sub; k < nn; k += 2) {
+      const int64_t e = (int64_t)k * st + i;
+      const uint32_t j = nl.idx[e];
+      const Rec b = R[j];
+      double vx, vy, vz;
+      PairOut o;
+      pair_from_records<PREC, MODEL>(P, g, mi, a, b, step, vx, vy, vz, o);
+      if (store) store_dp<PREC>(nl, e, o.dp[0], o.dp[1], o.dp[2]);
+      const long long f0 = pair_fix_raw(o.dp[0]), f1 = pair_fix_raw(o.dp[1]),
+                      f2 = pair_fix_raw(o.dp[2]);
+      pair_fix_range(o.dp[0], hi_max);
+      pair_fix_range(o.dp[1], hi_max);
+      pair_fix_range(o.dp[2], hi_max);
+      X0 += f0;
+      X1 += f1;
+      X2 += f2;
+      ++terms;
+      const uint32_t rel = in_tile(j, tb);
+      if (rel < (uint32_t)kUniqTile) {  // the partner's share of a pair inside the tile
+        atomicAdd(&acc[0][rel], (unsigned long long)(kFixMagicBits - f0));
+        atomicAdd(&acc[1][rel], (unsigned long long)(kFixMagicBits - f1));
+        atomicAdd(&acc[2][rel], (unsigned long long)(kFixMagicBits - f2));
+      }
+    }
+  }
+  X0 -= terms * kFixMagicBits;
+  X1 -= terms * kFixMagicBits;
+  X2 -= terms * kFixMagicBits;
+  X0 += __shfl_xor(X0, 1, kWave);
+  X1 += __shfl_xor(X1, 1, kWave);
+  X2 += __shfl_xor(X2, 1, kWave);
+  if (hi_max >= kFixRangeHi) atomicOr(status, ST_RANGE);
+  __syncthreads();
+  if (!live || sub) return;
+  const double ax = pair_fix_value((long long)((unsigned long long)X0 + acc[0][pl]));
+  const double ay = pair_fix_value((long long)((unsigned long long)X1 + acc[1][pl]));
+  const double az = pair_fix_value((long long)((unsigned long long)X2 + acc[2][pl]));
+  dpi[i] = Vec4{ax, ay, az, 0.0};
+  hv[i] = H3{fma(ax, P.inv_2m, a.px * P.inv_mass), fma(ay, P.inv_2m, a.py * P.inv_mass),
+             fma(az, P.inv_2m, a.pz * P.inv_mass)};
+}
+
+// ---------------------------------------------------------------------------
 // Inverse temperature of the updated internal energy.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double inv_temperature(const Phys& P, double eps, uint32_t* status) {
@@ -871,6 +1007,128 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
       }
       __syncthreads();
       y = net_y[L.pib];
+    }
+    if (need_t) {
+      int it;
+      const double th = theta_from_net(P, m, mlp_mode, e, y, it);
+      if (!(th > 0.0) || !isfinite(th)) atomicOr(status, ST_EOS);
+      out[i].invT = 1.0 / th;
+    }
+  }
+}
+
+// Pass C over the tile's unique pairs: the reinjection term
+//   e_ij = -1/2 dp_ij . (h_i - h_j),   h = (p + dp/2)/m
+// is symmetric in (i, j), so a pair inside the tile adds the same e_ij to both
+// internal energies (eq. SER_eint_discretization); then p <- p + dp,
+// eps <- eps + d eps and the next 1/T_i as in k_pass_c (THETA = 1: the
+// surrogate network inside the pass).
+template <bool BATCH, int PREC, int REGEN, int MODEL, int THETA>
+__global__ __launch_bounds__(2 * kUniqTile) void k_pass_c_uniq(
+    PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
+    const uint64_t* __restrict__ d_step, const Vec4* __restrict__ dpi,
+    const H3* __restrict__ hv, int eos_inline, MlpDev m, int mlp_mode, Rec* __restrict__ out,
+    uint32_t* status) {
+  __shared__ unsigned long long acc[kUniqTile];  // two's-complement sums (modular adds)
+  __shared__ float net_x[kUniqTile];
+  __shared__ float net_y[kUniqTile];
+  __shared__ uint32_t st_flag;
+  for (int c = threadIdx.x; c < kUniqTile; c += blockDim.x) acc[c] = 0;
+  if (block_status_set(status, &st_flag)) return;  // uniform in the block
+  const int64_t tb = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kUniqTile;
+  const int pl = threadIdx.x >> 1, sub = threadIdx.x & 1;
+  const int64_t i = tb + pl;
+  const bool live = i < n;
+  long long X = 0;  // raw sum of fixed-point bit patterns
+  long long terms = 0;
+  uint32_t hi_max = 0u;
+  Rec a{};
+  Vec4 di{};
+  if (live) {
+    const uint64_t step = *d_step;
+    const Rec* __restrict__ R = s.r;
+    a = R[i];
+    const GeoRef<BATCH> g = geo[BATCH ? a.rep : 0u];
+    const bool mi = REGEN ? !__all(away_from_faces(g, P, a.qx, a.qy, a.qz)) : true;
+    di = dpi[i];
+    const H3 hi = hv[i];
+    const uint32_t nn = nl.count[i];
+    const int64_t st = nl.stride;
+    uint32_t jn = (uint32_t)sub < nn ? nl.idx[(int64_t)sub * st + i] : 0u;
+    double hx = 0.0, hy = 0.0, hz = 0.0;
+    if ((uint32_t)sub < nn) {
+      hx = hv[jn].x;
+      hy = hv[jn].y;
+      hz = hv[jn].z;
+    }
+    for (uint32_t k = sub; k < nn; k += 2) {
+      const int64_t e = (int64_t)k * st + i;
+      const uint32_t j = jn;
+      const double ux = hi.x - hx, uy = hi.y - hy, uz = hi.z - hz;
+      if (k + 2 < nn) {
+        jn = nl.idx[e + 2 * st];
+        hx = hv[jn].x;
+        hy = hv[jn].y;
+        hz = hv[jn].z;
+      }
+      double ex, ey, ez;
+      if constexpr (REGEN) {
+        const Rec b = R[j];
+        double vx, vy, vz;
+        PairOut o;
+        pair_from_records<PREC, MODEL>(P, g, mi, a, b, step, vx, vy, vz, o);
+        ex = o.dp[0];
+        ey = o.dp[1];
+        ez = o.dp[2];
+      } else {
+        load_dp<PREC>(nl, e, ex, ey, ez);
+      }
+      const double eij = -0.5 * (ex * ux + ey * uy + ez * uz);
+      const long long f = pair_fix_raw(eij);
+      pair_fix_range(eij, hi_max);
+      X += f;
+      ++terms;
+      const uint32_t rel = in_tile(j, tb);
+      if (rel < (uint32_t)kUniqTile) atomicAdd(&acc[rel], (unsigned long long)(f - kFixMagicBits));
+    }
+  }
+  X -= terms * kFixMagicBits;
+  X += __shfl_xor(X, 1, kWave);
+  if (hi_max >= kFixRangeHi) atomicOr(status, ST_RANGE);
+  __syncthreads();
+  const double de =
+      live ? pair_fix_value((long long)((unsigned long long)X + acc[pl])) : 0.0;
+  const double e = live ? s.eps[i] + de : 1.0;
+  // The record (with the old 1/T_i) is written before the network, so that
+  // only e and i stay live across it; the new 1/T_i follows.
+  const bool own = live && sub == 0;
+  bool need_t = false;
+  if (own) {
+    Rec o = a;
+    o.px = a.px + di.x;
+    o.py = a.py + di.y;
+    o.pz = a.pz + di.z;
+    s.eps[i] = e;
+    if (!(e > 0.0)) {
+      atomicOr(status, ST_NEG_EINT);
+    } else if constexpr (THETA) {
+      need_t = true;
+    } else if (eos_inline) {
+      o.invT = inv_temperature(P, e, status);
+    }
+    out[i] = o;
+  }
+  if constexpr (THETA) {
+    float y = 0.0f;
+    if (mlp_mode != 0) {  // uniform
+      if (sub == 0) net_x[pl] = mlp_input(m, e);
+      __syncthreads();
+      // wave w takes particles 32 w .. 32 w + 31 of the tile
+      const int w = threadIdx.x / kWave, col = threadIdx.x % 32;
+      const float yw = mlp_wave32_bf16(m.wb, net_x[32 * w + col]);
+      if (threadIdx.x % kWave < 32) net_y[32 * w + col] = yw;
+      __syncthreads();
+      y = net_y[pl];
     }
     if (need_t) {
       int it;
@@ -1090,8 +1348,12 @@ __global__ void k_debug_cells(PState s, int64_t n, const Geo* __restrict__ geo, 
   out[g.first + rc.id] = cx + g.nc[0] * (cy + g.nc[1] * cz);
 }
 
+// Every pair of the lists once, as (lower id, higher id) rows.  A pair
+// joining two tiles is in both lists (taken from the lower identifier); with
+// the tile work lists (uniq) a pair inside a tile is in one list only.
 __global__ void k_debug_pairs(PState s, NList nl, int64_t n, const Geo* __restrict__ geo,
-                              int32_t* out, int64_t cap, unsigned long long* counter) {
+                              int uniq, int32_t* out, int64_t cap,
+                              unsigned long long* counter) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const Rec& a = s.r[i];
@@ -1099,11 +1361,12 @@ __global__ void k_debug_pairs(PState s, NList nl, int64_t n, const Geo* __restri
   for (uint32_t k = 0; k < nl.count[i]; ++k) {
     const uint32_t j = nl.idx[(int64_t)k * nl.stride + i];
     const uint32_t idj = s.r[j].id;
-    if (a.id < idj) {
+    const bool once = uniq && (((uint32_t)i ^ j) < (uint32_t)kUniqTile);
+    if (once || a.id < idj) {
       const unsigned long long slot = atomicAdd(counter, 1ull);
       if ((int64_t)slot < cap) {
-        out[2 * slot] = (int32_t)(g.first + a.id);
-        out[2 * slot + 1] = (int32_t)(g.first + idj);
+        out[2 * slot] = (int32_t)(g.first + (a.id < idj ? a.id : idj));
+        out[2 * slot + 1] = (int32_t)(g.first + (a.id < idj ? idj : a.id));
       }
     }
   }

@@ -137,6 +137,18 @@ class System:
     def set_tuning(self, pair_block: int, aux_block: int = 256):
         L.check(self._lib.dpde_set_tuning(self.h, int(pair_block), int(aux_block)))
 
+    def get_shape(self) -> dict:
+        sh = L.Shape()
+        L.check(self._lib.dpde_get_shape(self.h, C.byref(sh)))
+        return {"pair_block": sh.pair_block, "aux_block": sh.aux_block, "pairs": sh.pairs}
+
+    def set_shape(self, pair_block=None, aux_block=None, pairs=None):
+        cur = self.get_shape()
+        sh = L.Shape(int(pair_block if pair_block is not None else cur["pair_block"]),
+                     int(aux_block if aux_block is not None else cur["aux_block"]),
+                     int(pairs if pairs is not None else cur["pairs"]), 0)
+        L.check(self._lib.dpde_set_shape(self.h, C.byref(sh)))
+
     def autotune(self, steps: int = 20):
         """Pick the fastest block sizes (state restored); returns (pair, aux, ms/step)."""
         pb, ab, ms = C.c_int32(0), C.c_int32(0), C.c_double(0.0)

@@ -228,6 +228,8 @@ def test_hybrid_with_fine_domains_equals_ser(dp):
     fine = [int(np.ceil(L / 0.05))] * 3
     a = dp.System(dp.Config(n=n, box=[L] * 3, scheme=2, ndom=fine), q, p, e)
     b = dp.System(dp.Config(n=n, box=[L] * 3, scheme=0), q, p, e)
+    # the SER sweeps in the form Hybrid runs (FP64 sums in identifier order)
+    b.set_shape(pairs=dp.PAIRS_BOTH_SIDES)
     a.step(3)
     b.step(3)
     qa, pa, ea, _ = _gpu_state(a)

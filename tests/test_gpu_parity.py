@@ -360,10 +360,125 @@ def test_stored_increments_equal_regenerated_noise(dp):
         a.close()
 
 
+def _run_form(dp, cfgs, q, p, e, pairs, steps):
+    s = dp.System(cfgs, q, p, e)
+    s.set_shape(pairs=pairs)
+    assert s.get_shape()["pairs"] == pairs
+    s.step(steps)
+    out = _gpu_state(s), s.history()
+    s.close()
+    return out
+
+
+def _forms_agree(box, periodic, a, b, ha, hb, eps_scale):
+    eq, ep, ee = _state_errors(box, periodic, a[:3], b[:3], eps_scale)
+    assert max(eq, ep, ee) < 1e-12, (eq, ep, ee)
+    assert a[3] == b[3]
+    # observables: energies to rounding, momentum sums to rounding
+    assert np.allclose(ha[:, :4], hb[:, :4], rtol=1e-12, atol=0)
+    assert np.abs(ha[:, 4:7] - hb[:, 4:7]).max() < 1e-9
+
+
+@pytest.mark.parametrize("case", ["fp64", "fp32", "projected", "lj_long_lists", "free_x",
+                                  "regenerated"])
+def test_pair_forms_agree(dp, case):
+    """The SER sweeps with each pair inside a 128-particle tile evaluated once
+    (fixed-point per-particle sums) and with every pair term evaluated on both
+    particles' lanes (FP64 sums in identifier order) give the same trajectory
+    to rounding: the same pair terms (exact negatives), summed in two
+    arithmetics.  The LJ case has ~53 neighbours per particle (lists longer
+    than the LDS staging of pass A); n is not a multiple of the tile."""
+    from paper_1507_06643_amd import _lib as L
+    kw, n, dens = {}, 4001, 3.0
+    if case == "fp32":
+        kw = dict(precision=dp.FP32)
+    elif case == "projected":
+        kw = dict(model=dp.MODEL_PROJECTED)
+    elif case == "lj_long_lists":
+        kw = dict(potential=dp.POT_LJ, rc=2.5, eps_lj=1.0, r_lj=1.0, dt=0.002, cv=50.0,
+                  neighbor_cap=128)
+        dens = 0.8095
+    L_ = W.cubic_side(n, dens)
+    box, per = [L_] * 3, (1, 1, 1)
+    if case == "free_x":
+        box, per = [3 * L_, L_ / 1.8, L_ / 1.8], (0, 1, 1)
+    q, p, e = W.equilibrium_state(n, box, seed=83, eps0=kw.get("cv", 100.0))
+    if case == "lj_long_lists":
+        # a jittered lattice (no overlapping LJ cores) with 95 sites left empty
+        ql, _, _, box = W.lattice_state(16, dens, seed=84)
+        q = ql[:n]
+    cfg = _cfg(dp, n, box, periodic=list(per), **kw)
+    steps = 4
+    if case == "regenerated":
+        import ctypes as C
+        import torch
+        lib = L.load()
+        out = []
+        for pairs in (dp.PAIRS_BOTH_SIDES, dp.PAIRS_ONCE_PER_TILE):
+            P = cfg.to_c()
+            P.flags = L.DPDE_FLAG_REGENERATE_NOISE
+            h = C.c_void_p()
+            qd, pd, ed = (torch.as_tensor(x, device="cuda").contiguous() for x in (q, p, e))
+            torch.cuda.synchronize()
+            L.check(lib.dpde_init(C.byref(P), C.c_void_p(qd.data_ptr()),
+                                  C.c_void_p(pd.data_ptr()), C.c_void_p(ed.data_ptr()), None,
+                                  C.byref(h)))
+            sh = L.Shape(256, 256, pairs, 0)
+            L.check(lib.dpde_set_shape(h, C.byref(sh)))
+            L.check(lib.dpde_step(h, steps))
+            qo, po, eo = torch.empty_like(qd), torch.empty_like(pd), torch.empty_like(ed)
+            st = C.c_int64(0)
+            L.check(lib.dpde_get_state(h, C.c_void_p(qo.data_ptr()), C.c_void_p(po.data_ptr()),
+                                       C.c_void_p(eo.data_ptr()), C.byref(st)))
+            out.append((qo.cpu().numpy(), po.cpu().numpy(), eo.cpu().numpy(), st.value))
+            lib.dpde_free(h)
+        eq, ep, ee = _state_errors(box, per, out[0][:3], out[1][:3], e.mean())
+        assert max(eq, ep, ee) < 1e-12, (eq, ep, ee)
+        return
+    (sa, ha) = _run_form(dp, cfg, q, p, e, dp.PAIRS_BOTH_SIDES, steps)
+    (sb, hb) = _run_form(dp, cfg, q, p, e, dp.PAIRS_ONCE_PER_TILE, steps)
+    _forms_agree(box, per, sa, sb, ha, hb, e.mean())
+
+
+def test_pair_forms_agree_batched(dp):
+    """The same for uneven batched replicas (tiles straddle replica borders)."""
+    sizes = [517, 1203, 200, 2900]
+    cfgs, qs, ps, es = [], [], [], []
+    for r, nr in enumerate(sizes):
+        L = W.cubic_side(nr)
+        q, p, e = W.equilibrium_state(nr, [L] * 3, seed=700 + r)
+        cfgs.append(_cfg(dp, nr, [L] * 3, seed=11 + r, replica=r))
+        qs.append(q); ps.append(p); es.append(e)
+    q, p, e = np.vstack(qs), np.vstack(ps), np.concatenate(es)
+    (sa, ha) = _run_form(dp, cfgs, q, p, e, dp.PAIRS_BOTH_SIDES, 4)
+    (sb, hb) = _run_form(dp, cfgs, q, p, e, dp.PAIRS_ONCE_PER_TILE, 4)
+    ep = np.abs(sa[1] - sb[1]).max()
+    ee = np.abs(sa[2] - sb[2]).max() / np.abs(sa[2]).mean()
+    assert max(ep, ee) < 1e-12, (ep, ee)
+    assert np.allclose(ha[:, :, :4], hb[:, :, :4], rtol=1e-12, atol=0)
+
+
+def test_pair_term_range_is_reported(dp):
+    """A pair increment beyond the range of the fixed-point sums fails the
+    step with DPDE_ERANGE rather than wrapping: one particle at 2e4 lands
+    among its new neighbours with a friction increment gamma_ij chi v dt of
+    up to 4.5 * 2e4 * 0.01 = 900."""
+    n = 2000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=85)
+    p[0] = [2e4, 0.0, 0.0]
+    s = dp.System(_cfg(dp, n, [L] * 3, a=0.0, skin=0.0), q, p, e)
+    assert s.get_shape()["pairs"] == dp.PAIRS_ONCE_PER_TILE
+    rc = s.step_raw(1)
+    assert rc == dp._lib.DPDE_ERANGE
+    s.close()
+
+
 def test_dense_region_uses_the_list_fallback(dp):
-    """A blob at ~11x the density puts more than 1024 stencil candidates in
-    some cells: their particles take the per-particle list build, the rest
-    the per-cell one; pairs and one step still match the oracle."""
+    """A blob at ~11x the density gives some particles several hundred
+    neighbours (lists of capacity 512, beyond the register sort widths, which
+    take the in-place insertion sort, and beyond the wave-tile sweep, which
+    falls back to lane pairs); pairs and one step still match the oracle."""
     rng = np.random.default_rng(17)
     L = 20.0
     base = 3 * int(L ** 3)
