@@ -438,3 +438,112 @@ def test_mlp_backprop_matches_finite_differences():
         wm = w.copy(); wm[k] -= h
         fd = (O.mlp_loss_grad(wp, x, t)[0] - O.mlp_loss_grad(wm, x, t)[0]) / (2 * h)
         assert g[k] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# SEM internal-energy update (Sec. 3.1.1, eq. SEM_fd; App. B).  Euler-Maruyama
+# has the exact drift, so at a frozen configuration the mean over noise draws
+# of d eps_i is 1/2 sum_j (gamma_ij |v_ij|^2 - d sigma^2/m) chi_ij dt with
+# d = 3 noise dimensions; its fluctuating part -1/2 sigma w_ij v_ij.G_ij
+# sqrt(dt) has variance 1/4 sum_j sigma^2 chi_ij |v_ij|^2 dt and covariance
+# -1/2 sum_j sigma^2 chi_ij v_ij dt with dp_i (whose noise is +sigma w G_ij
+# sqrt(dt)): the sign of the noise term.  The same statistics run on copies
+# of the oracle with a planted mistake (a dropped 1/2, d = 1, a flipped noise
+# sign, a noise term twice too large), built here on the CPU, and must fail.
+# ---------------------------------------------------------------------------
+_SEM_MUTATIONS = {
+    "drift_half_dropped": ("double e = 0.5 * (gij * vsq - 3.0 * sigma",
+                           "double e = 1.0 * (gij * vsq - 3.0 * sigma"),
+    "one_noise_dimension": ("(gij * vsq - 3.0 * sigma * sigma / P->mass)",
+                            "(gij * vsq - 1.0 * sigma * sigma / P->mass)"),
+    "noise_sign_flipped": ("- 0.5 * sigma * w * vG * sqdt;", "+ 0.5 * sigma * w * vG * sqdt;"),
+    "noise_half_dropped": ("- 0.5 * sigma * w * vG * sqdt;", "- 1.0 * sigma * w * vG * sqdt;"),
+}
+
+
+def _oracle_fd_from(lib):
+    import ctypes as C
+
+    import oracle.oracle as OO
+    dp = C.POINTER(C.c_double)
+    lib.or_fd.argtypes = [C.POINTER(O.OrParams), dp, dp, dp, dp]
+
+    def fd(P, q, p, e):
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        p1 = np.array(p, dtype=np.float64, copy=True)
+        e1 = np.array(e, dtype=np.float64, copy=True)
+        d = np.zeros_like(p1)
+        rc = lib.or_fd(C.byref(P), OO._d(q), OO._d(p1), OO._d(e1), OO._d(d))
+        return rc, p1, e1, d
+    return fd
+
+
+def _mutated_oracle(tmp_path, name):
+    import ctypes as C
+    import subprocess
+    old, new = _SEM_MUTATIONS[name]
+    import oracle.build as OB
+    src = open(OB.SRC).read()
+    assert src.count(old) == 1, name
+    path = tmp_path / f"oracle_{name}.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / f"liboracle_{name}.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-o",
+                    str(so), str(path), "-lm"], check=True)
+    return _oracle_fd_from(C.CDLL(str(so)))
+
+
+def _sem_energy_law(fd, M=2000):
+    """Largest |z| of the mean, variance and dp-covariance of d eps_i under
+    SEM at a frozen configuration against the values stated above."""
+    n = 120
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=23, eps0=100.0)
+    e = e * np.random.default_rng(3).uniform(0.8, 1.2, size=n)
+    dt, gamma, kT, cv = 2e-3, 4.5, 1.0, 100.0
+    sigma2 = 2 * gamma * kT
+    des = np.zeros((M, n))
+    dps = np.zeros((M, n, 3))
+    for s in range(M):
+        P = O.make_params(n, [L] * 3, dt=dt, step=s, seed=4321, scheme=1)
+        rc, p1, e1, d = fd(P, q, p, e)
+        assert rc == 0
+        des[s] = e1 - e
+        dps[s] = d
+    pr, r = _pair_geometry(q, [L] * 3)
+    chi = (1 - r) ** 2
+    invT = cv / e
+    gij = 0.5 * gamma * kT * (invT[pr[:, 0]] + invT[pr[:, 1]])
+    vij = p[pr[:, 0]] - p[pr[:, 1]]
+    v2 = (vij * vij).sum(1)
+    mean = np.zeros(n)
+    var = np.zeros(n)
+    cov = np.zeros((n, 3))
+    term = 0.5 * (gij * v2 - 3 * sigma2) * chi * dt
+    for a, sgn in ((0, 1.0), (1, -1.0)):
+        np.add.at(mean, pr[:, a], term)
+        np.add.at(var, pr[:, a], 0.25 * sigma2 * chi * v2 * dt)
+        np.add.at(cov, pr[:, a], -0.5 * sigma2 * dt * (chi[:, None] * sgn * vij))
+    sel = var > 1e-8
+    zm = (des.mean(0)[sel] - mean[sel]) / np.sqrt(var[sel] / M)
+    vhat = des.var(0)[sel]
+    zv = (vhat / var[sel] - 1) / math.sqrt(2 / M)
+    dev = des - des.mean(0)
+    chat = np.einsum("sn,snc->nc", dev, dps - dps.mean(0)) / M
+    # covariance estimate error ~ sqrt(var_e var_p / M)
+    vp = dps.var(0)
+    zc = (chat[sel] - cov[sel]) / np.sqrt(var[sel][:, None] * vp[sel] / M + 1e-300)
+    return max(np.abs(zm).max(), np.abs(zv).max(), np.abs(zc).max()), zm, zv, zc
+
+
+def test_sem_internal_energy_law():
+    """The oracle's SEM d eps_i: mean, variance and covariance with dp_i."""
+    zmax, zm, zv, zc = _sem_energy_law(O.fd)
+    assert zmax < 5.5, zmax
+    assert abs(zm.mean()) < 0.2 and abs(zc.mean()) < 0.2
+
+
+@pytest.mark.parametrize("name", sorted(_SEM_MUTATIONS))
+def test_sem_internal_energy_law_catches_planted_mistakes(tmp_path, name):
+    zmax, _, _, _ = _sem_energy_law(_mutated_oracle(tmp_path, name))
+    assert zmax > 8.0, (name, zmax)
