@@ -415,7 +415,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default block sizes (profiling runs: no tuning trials)")
     ap.add_argument("--profile-steps", type=int, default=10)
-    ap.add_argument("--mlp-iters", type=int, default=3000)
+    ap.add_argument("--mlp-iters", type=int, default=20000)
     ap.add_argument("--no-drift", action="store_true", help="skip the energy-drift legs")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the batched-replica and shock legs")

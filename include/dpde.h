@@ -377,6 +377,11 @@ int dpde_mlp_eval(dpde_handle* h, const float* x, float* y, int64_t n);
 /* Linear cell index (within its replica) of every particle, by ID (device int32 n). */
 int dpde_debug_cells(dpde_handle* h, int32_t* cell_of_id);
 
+/* 1/T_i of every particle as the last step left it (device FP64 n, ID order):
+ * the inverse temperature of eq. DPDE_internalEOS that the next step's
+ * friction gamma_ij uses (eq. DPDE_fd). */
+int dpde_debug_inv_temperature(dpde_handle* h, double* inv_t);
+
 /* Neighbour pairs (lo id, hi id) with r^2 < rc^2 of the current positions
  * (device int32 cap x 2, unordered); *npairs (host) receives the count,
  * which may exceed cap (then only cap pairs are written). */

@@ -1258,6 +1258,15 @@ int dpde_debug_cells(dpde_handle* h, int32_t* cell_of_id) {
   return DPDE_OK;
 }
 
+int dpde_debug_inv_temperature(dpde_handle* h, double* inv_t) {
+  if (!h || !inv_t) return fail(DPDE_EINVAL, "NULL argument");
+  launch(h, "debug_inv_temperature", k_store_inv_temperature, blocks(h->n, 256), 256, h->cur,
+         (const Geo*)h->geo, h->n, inv_t);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  return DPDE_OK;
+}
+
 int dpde_debug_pairs(dpde_handle* h, int32_t* lohi, int64_t cap, int64_t* npairs) {
   if (!h || !npairs || (cap > 0 && !lohi)) return fail(DPDE_EINVAL, "NULL argument");
   HIPCHK(hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream));

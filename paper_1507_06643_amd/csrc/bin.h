@@ -127,6 +127,15 @@ __global__ void k_store_vec3(PState s, const Geo* __restrict__ geo, int64_t n,
   out[3 * row] = x[i]; out[3 * row + 1] = y[i]; out[3 * row + 2] = z[i];
 }
 
+// 1/T_i of every particle into out (identifier order).
+__global__ void k_store_inv_temperature(PState s, const Geo* __restrict__ geo, int64_t n,
+                                        double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Rec& rc = s.r[i];
+  out[geo[rc.rep].first + (int64_t)rc.id] = rc.invT;
+}
+
 constexpr int kAuxMaxThreads = 1024;  // largest block of the per-particle kernels
 
 // First half of velocity-Verlet (Sec. 3.1): p += dt/2 F, q += dt p / m, then

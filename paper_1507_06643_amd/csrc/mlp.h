@@ -4,8 +4,9 @@
 // y = W3 . h2 + b3, theta = exp(out_c + out_s y); 32 hidden units per layer,
 // weights packed W1[32] b1[32] W2[32][32] b2[32] W3[32] b3 (1153 values).
 //
-// Inference uses BF16 weights and FP32 accumulation; the 32x32 layer runs on
-// the matrix cores as H2^T = W2 H1^T with one v_mfma_f32_32x32x16_bf16 per
+// Inference: the 32x32 layer runs on the matrix cores in BF16 with FP32
+// accumulation (the input and output layers, on the vector units, use the
+// FP32 weights) as H2^T = W2 H1^T with one v_mfma_f32_32x32x16_bf16 per
 // (32 particles x 16 inputs) block: the weights are the A operand (constant),
 // each lane builds its B-operand column of tanh(W1 x + b1) for the particle it
 // serves, and the accumulator leaves every lane with 16 hidden units of one
@@ -76,9 +77,13 @@ __device__ __forceinline__ float fast_tanh(float x) {
 }
 
 // ---- inference: every lane of the wave must call; returns this lane's y ---------
+// The 32x32 layer is the matrix-core product: W2 and the hidden activations
+// enter it in BF16.  The input and output layers (vectors, evaluated on the
+// vector units) keep the FP32 master weights.
 // 32 particles: lane l serves particle l % 32 (both half-waves pass that
 // particle's x) and every lane gets that particle's y.
-__device__ __forceinline__ float mlp_wave32_bf16(const uint16_t* __restrict__ wb, float xp) {
+__device__ __forceinline__ float mlp_wave32(const float* __restrict__ wf,
+                                            const uint16_t* __restrict__ wb, float xp) {
   const int l = threadIdx.x % kWave;
   const int half = l >> 5, col = l & 31;
   bf16x8 a[2];
@@ -94,8 +99,7 @@ __device__ __forceinline__ float mlp_wave32_bf16(const uint16_t* __restrict__ wb
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = ks * 16 + 8 * half + e;
-      const float h = fast_tanh(bf16_bits_to_f32(wb[OFF_W1 + k]) * xp +
-                                bf16_bits_to_f32(wb[OFF_B1 + k]));
+      const float h = fast_tanh(wf[OFF_W1 + k] * xp + wf[OFF_B1 + k]);
       b[e] = __builtin_bit_cast(__bf16, f32_to_bf16_bits(h));
     }
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b, acc, 0, 0, 0);
@@ -104,24 +108,26 @@ __device__ __forceinline__ float mlp_wave32_bf16(const uint16_t* __restrict__ wb
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int u = 8 * (r >> 2) + 4 * half + (r & 3);
-    s += bf16_bits_to_f32(wb[OFF_W3 + u]) * fast_tanh(acc[r] + bf16_bits_to_f32(wb[OFF_B2 + u]));
+    s += wf[OFF_W3 + u] * fast_tanh(acc[r] + wf[OFF_B2 + u]);
   }
   s += __shfl_xor(s, 32, kWave);
-  return s + bf16_bits_to_f32(wb[OFF_B3]);
+  return s + wf[OFF_B3];
 }
 
 // 64 particles: lane l passes the x of particle l and gets its y.
-__device__ __forceinline__ float mlp_wave_bf16(const uint16_t* __restrict__ wb, float x) {
+__device__ __forceinline__ float mlp_wave(const float* __restrict__ wf,
+                                          const uint16_t* __restrict__ wb, float x) {
   const int l = threadIdx.x % kWave;
   const int half = l >> 5, col = l & 31;
   float y[2];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb) y[mb] = mlp_wave32_bf16(wb, __shfl(x, 32 * mb + col, kWave));
+  for (int mb = 0; mb < 2; ++mb) y[mb] = mlp_wave32(wf, wb, __shfl(x, 32 * mb + col, kWave));
   return half ? y[1] : y[0];
 }
 
 struct MlpDev {
-  const uint16_t* wb;
+  const float* wf;     // FP32 master weights (input and output layers)
+  const uint16_t* wb;  // BF16 copy (the matrix-core layer W2)
   double in_c, in_s, out_c, out_s, eps_lo, eps_hi;
 };
 
@@ -157,7 +163,7 @@ __global__ __launch_bounds__(256) void k_theta(const double* __restrict__ eps, d
   const bool valid = i < n;
   const double e = valid ? eps[i] : 1.0;
   float y = 0.0f;
-  if (P.eos != 0 && mode != 0) y = mlp_wave_bf16(m.wb, mlp_input(m, e));  // uniform
+  if (P.eos != 0 && mode != 0) y = mlp_wave(m.wf, m.wb, mlp_input(m, e));  // uniform
   int it;
   const double th = theta_from_net(P, m, mode, e, y, it);
   if (!valid) return;
@@ -178,13 +184,14 @@ __global__ void k_eos_energy(const double* __restrict__ theta, double* __restric
   if (i < n) eps[i] = eos_energy_dev(P, theta[i]);
 }
 
-// y for normalised inputs (test hook for the BF16 matrix-core path).
-__global__ __launch_bounds__(256) void k_mlp_eval(const uint16_t* __restrict__ wb,
+// y for normalised inputs (test hook for the inference path).
+__global__ __launch_bounds__(256) void k_mlp_eval(const float* __restrict__ wf,
+                                                  const uint16_t* __restrict__ wb,
                                                   const float* __restrict__ x, float* __restrict__ y,
                                                   int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const float xi = i < n ? x[i] : 0.0f;
-  const float v = mlp_wave_bf16(wb, xi);
+  const float v = mlp_wave(wf, wb, xi);
   if (i < n) y[i] = v;
 }
 
@@ -382,7 +389,7 @@ inline int mlp_ensure_weights(MlpState& s) {
 }
 
 inline MlpDev mlp_dev(const MlpState& s) {
-  return MlpDev{s.wb, s.norm[0], s.norm[1], s.norm[2], s.norm[3], s.eps_lo, s.eps_hi};
+  return MlpDev{s.w, s.wb, s.norm[0], s.norm[1], s.norm[2], s.norm[3], s.eps_lo, s.eps_hi};
 }
 
 // Copy the normalisation into the physics block used by the step kernels.
@@ -482,7 +489,7 @@ inline int mlp_eval(MlpState& s, hipStream_t st, const float* x, float* y, int64
   if (!s.wb) { err = "the surrogate has no weights"; return DPDE_EINVAL; }
   if (n <= 0) return DPDE_OK;
   hipLaunchKernelGGL(k_mlp_eval, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                     (const uint16_t*)s.wb, x, y, n);
+                     (const float*)s.w, (const uint16_t*)s.wb, x, y, n);
   if (hipStreamSynchronize(st) != hipSuccess) { err = "inference kernel failed"; return DPDE_EHIP; }
   return DPDE_OK;
 }

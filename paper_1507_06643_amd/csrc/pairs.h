@@ -1002,7 +1002,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
       const int w = threadIdx.x / kWave, col = threadIdx.x % 32;
       if (32 * w < L.ppb) {  // uniform in the wave
         const int p = 32 * w + col;
-        const float yw = mlp_wave32_bf16(m.wb, p < L.ppb ? net_x[p] : 0.0f);
+        const float yw = mlp_wave32(m.wf, m.wb, p < L.ppb ? net_x[p] : 0.0f);
         if (threadIdx.x % kWave < 32) net_y[p] = yw;
       }
       __syncthreads();
@@ -1125,7 +1125,7 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_c_uniq(
       __syncthreads();
       // wave w takes particles 32 w .. 32 w + 31 of the tile
       const int w = threadIdx.x / kWave, col = threadIdx.x % 32;
-      const float yw = mlp_wave32_bf16(m.wb, net_x[32 * w + col]);
+      const float yw = mlp_wave32(m.wf, m.wb, net_x[32 * w + col]);
       if (threadIdx.x % kWave < 32) net_y[32 * w + col] = yw;
       __syncthreads();
       y = net_y[pl];

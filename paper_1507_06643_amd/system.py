@@ -288,6 +288,11 @@ class System:
         L.check(self._lib.dpde_debug_cells(self.h, _ptr(out)))
         return out
 
+    def debug_inv_temperature(self):
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        L.check(self._lib.dpde_debug_inv_temperature(self.h, _ptr(out)))
+        return out
+
     def debug_pairs(self, cap=None):
         cap = cap if cap is not None else 40 * self.n
         out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
