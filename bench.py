@@ -163,32 +163,81 @@ def drift_vs_oracle(dp, W, seeds, n=1000, steps=1000, dt=0.01):
             "oracle_seconds": t_cpu}
 
 
-def drift_gpu(dp, W, n=65536, steps=10000, seeds=(1, 2, 3, 4), dts=(0.005, 0.01),
-              precisions=("fp64", "fp32")):
-    """Equilibrium drift on the GPU at N=65,536 (density 3), 10^4 steps."""
+GOLDEN_DRIFT = os.path.join(ROOT, "tests", "golden", "oracle_drift_n65536.json")
+
+
+def _eps_theta1(dp, W):
+    """eps(theta = 1) of the Einstein EOS from the library's own EOS kernel."""
+    import torch
+    nh = 200
+    Lh = W.cubic_side(nh)
+    qh, ph, eh = W.equilibrium_state(nh, [Lh] * 3, eps0=10.0, seed=1)
+    helper = dp.System(dp.Config(n=nh, box=[Lh] * 3, eos=dp.EOS_EINSTEIN), qh, ph, eh)
+    eps0 = float(helper.eos_energy(torch.ones(1, dtype=torch.float64)).cpu()[0])
+    helper.close()
+    return eps0
+
+
+def drift_gpu(dp, W, n=65536, steps=10000, seeds=(1, 2, 3, 4), mlp_iters=20000):
+    """Equilibrium energy drift and temperatures on the GPU at N = 65,536
+    (density 3): 10^4 steps after 1000 relaxation steps, the protocol of the
+    stored oracle runs (same initial states and noise seeds), with the linear
+    EOS (FP64 and FP32 pair terms, dt 0.005 and 0.01) and the Einstein EOS at
+    dt 0.005 (FP64 with Newton, FP64 with the surrogate, FP32 with the
+    surrogate).  Each FP64 result is set against the oracle's, in combined
+    standard errors of the seed means."""
     L = W.cubic_side(n)
+    golden = json.load(open(GOLDEN_DRIFT))["results"] if os.path.exists(GOLDEN_DRIFT) else {}
+    eps_e = _eps_theta1(dp, W)
+    legs = [("fp64_linear_dt0.005", dp.EOS_LINEAR, dp.THETA_NEWTON, dp.FP64, 0.005, "linear_dt0.005"),
+            ("fp64_linear_dt0.01", dp.EOS_LINEAR, dp.THETA_NEWTON, dp.FP64, 0.01, "linear_dt0.01"),
+            ("fp32_linear_dt0.005", dp.EOS_LINEAR, dp.THETA_NEWTON, dp.FP32, 0.005, None),
+            ("fp32_linear_dt0.01", dp.EOS_LINEAR, dp.THETA_NEWTON, dp.FP32, 0.01, None),
+            ("fp64_newton_einstein_dt0.005", dp.EOS_EINSTEIN, dp.THETA_NEWTON, dp.FP64, 0.005,
+             "einstein_dt0.005"),
+            ("fp64_mlp_einstein_dt0.005", dp.EOS_EINSTEIN, dp.THETA_MLP, dp.FP64, 0.005, None),
+            ("fp32_mlp_einstein_dt0.005", dp.EOS_EINSTEIN, dp.THETA_MLP, dp.FP32, 0.005, None)]
+    weights = None
     out = {}
-    for prec in precisions:
-        for dt in dts:
-            dr, tk, ti = [], [], []
-            for sd in seeds:
-                q, p, e = W.equilibrium_state(n, [L] * 3, eps0=100.0, seed=2000 + sd)
-                s = dp.System(dp.Config(n=n, box=[L] * 3, dt=dt, seed=sd,
-                                        precision=dp.FP32 if prec == "fp32" else dp.FP64), q, p, e)
-                # relax the random initial packing before measuring
-                s.step(1000)
-                s.history()
-                E0 = s.energies()
-                s.step(steps)
-                h = s.history()
-                s.close()
-                dr.append(drift_fit(np.concatenate([[E0[3]], h[:, 3]])))
-                tk.append(h[:, 7].mean())
-                ti.append(h[:, 8].mean())
-            out[f"{prec}_dt{dt}"] = {"drift_per_1e4": list(mean_se(dr)), "Tkin": list(mean_se(tk)),
-                                     "Tint": list(mean_se(ti))}
+    for name, eos, tm, prec, dt, gkey in legs:
+        dr, tk, ti = [], [], []
+        for sd in seeds:
+            eps0 = eps_e if eos == dp.EOS_EINSTEIN else 100.0
+            q, p, e = W.equilibrium_state(n, [L] * 3, eps0=eps0, seed=2000 + sd)
+            s = dp.System(dp.Config(n=n, box=[L] * 3, dt=dt, seed=sd, eos=eos, theta_mode=tm,
+                                    precision=prec), q, p, e)
+            if tm != dp.THETA_NEWTON:
+                if weights is None:
+                    s.mlp_train(nsamples=10**6, iters=mlp_iters, batch=4096, lr=3e-3)
+                    weights = s.mlp_get()
+                else:
+                    s.mlp_set(*weights)
+            # relax the random initial packing before measuring
+            s.step_graph(100, 10)
+            s.history()
+            E0 = s.energies()
+            s.step_graph(100, steps // 100)
+            h = s.history()
+            s.close()
+            dr.append(drift_fit(np.concatenate([[E0[3]], h[:, 3]])))
+            tk.append(h[:, 7].mean())
+            ti.append(h[:, 8].mean())
+        r = {"drift_per_1e4": list(mean_se(dr)), "Tkin": list(mean_se(tk)),
+             "Tint": list(mean_se(ti)), "dt": dt}
+        if gkey and gkey in golden:
+            g = golden[gkey]
+            r["oracle_drift_per_1e4"] = g["drift_per_1e4"]
+            r["oracle_Tkin"] = g["Tkin"]
+            r["oracle_Tint"] = g["Tint"]
+            r["drift_diff_over_combined_se"] = abs(r["drift_per_1e4"][0] - g["drift_per_1e4"][0]) / \
+                max(1e-300, math.hypot(r["drift_per_1e4"][1], g["drift_per_1e4"][1]))
+        out[name] = r
+        log(f"[bench]   drift {name}: {r['drift_per_1e4'][0]:.3e} +- {r['drift_per_1e4'][1]:.1e}")
     return {"workload": f"N={n} density 3, {steps} steps after 1000 relaxation steps, "
-                        f"{len(seeds)} seeds", "results": out}
+                        f"{len(seeds)} seeds (noise seeds {list(seeds)}, initial states seeded "
+                        f"2000 + seed), drift = 10^4 x slope of (E_n - E_0)/|E_0|",
+            "oracle": "tests/golden/oracle_drift_n65536.json (CPU FP64 oracle, same protocol)",
+            "results": out}
 
 
 def kernel_profile(sysm, steps):
@@ -204,20 +253,36 @@ def mean_neighbours(sysm, n):
     return 2.0 * len(pr) / n
 
 
-def pair_kernel_bytes(name, nbar, nskin=None, fp32=False):
-    """Algorithmic HBM bytes per particle of the pair kernels: every
-    per-particle array read or written once, neighbour-list words 4 B each;
-    neighbour gathers are re-reads served on chip and not counted.  Pass A
-    reads the skin list (nskin entries) and writes the exact list."""
-    lst = 4.0 + 4.0 * nbar  # count + entries
-    if name.startswith("pass_a"):
-        skin = 4.0 + 4.0 * (nskin if nskin is not None else nbar)
-        return 24 + 24 + (24 + 24 + 8) + skin + lst  # q, p, skin list | F, p, U, list
-    if name.startswith("pass_b"):
-        return 24 + 24 + 8 + 4 + lst + 24         # q, p, 1/T, id, list | dp
-    if name.startswith("pass_c"):
-        return 24 + 24 + 8 + 4 + lst + 24 + 8 + (24 + 8 + 8)  # ... dp, eps | p, eps, 1/T
+# Algorithmic HBM bytes per particle of the pair kernels: every per-particle
+# array the step of the method reads or writes, once (q, p, 1/T, id, eps, F,
+# dp_i at 8 B per double, 4 B per id); neighbour gathers, neighbour lists and
+# the stored increments dp_ij are this implementation's choices and are not
+# counted.
+ALGO_BYTES = {
+    "pass_a": 24 + 24 + 24 + 24,          # q, p' in | F, p~ out  (96)
+    "pass_b": 24 + 24 + 8 + 4 + 24,       # q, p~, 1/T, id in | dp_i out  (84)
+    "pass_c": 24 + 24 + 8 + 4 + 24 + 8 + 24 + 8 + 8,  # q, p~, 1/T, id, dp_i, eps | p, eps, 1/T (132)
+}
+
+
+def pair_kernel_bytes(name, nbar=None, nskin=None, fp32=False):
+    for k, v in ALGO_BYTES.items():
+        if name.startswith(k):
+            return float(v)
     return None
+
+
+def pair_kernel_list_bytes(name, nwork, nskin):
+    """The same plus the neighbour-list words (4 B per entry and per count):
+    the skin list read and the work list written by pass A, the work list read
+    by the sweeps."""
+    b = pair_kernel_bytes(name)
+    if b is None:
+        return None
+    work = 4.0 + 4.0 * nwork
+    if name.startswith("pass_a"):
+        return b + 4.0 + 4.0 * nskin + work
+    return b + work
 
 
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "learned_eos_n1m_traffic.txt")
@@ -380,26 +445,60 @@ def next_rows_leg(dp, W, n=N_1M, steps=100, warmup=20, only=None):
     return out
 
 
-def cpu_baseline(W, n, steps, eos, dt, eps0):
+def oracle_worker(n, steps, eos, dt, eps0, seed):
+    """One single-threaded oracle run (a child process of cpu_baseline):
+    prints its step rate as one JSON line."""
     import oracle as O
+    import workloads as W
     L = W.cubic_side(n)
-    q, p, e = W.equilibrium_state(n, [L] * 3, eps0=eps0, seed=20260101)
+    q, p, e = W.equilibrium_state(n, [L] * 3, eps0=eps0, seed=seed)
     P = O.make_params(n, [L] * 3, dt=dt, eos=eos)
     t0 = time.perf_counter()
     S = O.State(P, q, p, e)
     t_init = time.perf_counter() - t0
     t0 = time.perf_counter()
     rc, _ = S.step(steps)
-    dt_run = time.perf_counter() - t0
+    t_run = time.perf_counter() - t0
+    print(json.dumps({"rate": n * steps / t_run, "seconds": t_run, "init_seconds": t_init,
+                      "rc": rc}), flush=True)
+
+
+def cpu_baseline(n, steps, eos, dt, eps0, max_procs=16):
+    """The CPU oracle on every host core available to this process (at most
+    max_procs): one single-threaded oracle process per core, each running
+    `steps` steps of its own copy of the workload after its initialisation;
+    the throughput is the sum of their step rates.  The oracle is the same
+    plain C code the tests pin (not tuned for speed)."""
+    import subprocess
+    cores = max(1, min(max_procs, len(os.sched_getaffinity(0))))
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-worker",
+           json.dumps([n, steps, eos, dt, eps0])]
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen(cmd + [str(20260101 + k)], stdout=subprocess.PIPE, env=env,
+                              text=True) for k in range(cores)]
+    outs = []
+    for pr in procs:
+        so, _ = pr.communicate()
+        if pr.returncode != 0:
+            raise RuntimeError(f"oracle worker failed with {pr.returncode}")
+        outs.append(json.loads(so.strip().splitlines()[-1]))
+    wall = time.perf_counter() - t0
     model = None
     try:
         with open("/proc/cpuinfo") as f:
             model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
     except OSError:
         pass
-    return {"value": n * steps / dt_run, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} full steps of the same N={n} system after oracle init "
-                      f"({t_init:.1f} s), single thread, {dt_run:.1f} s", "rc": rc,
+    rates = [o["rate"] for o in outs]
+    return {"value": float(sum(rates)), "unit": "particle-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{cores} single-threaded oracle processes in parallel (one per core), "
+                      f"each {steps} steps of its own N={n} learned-EOS system (Newton "
+                      f"inversion, dt={dt}) after initialisation; step rates summed "
+                      f"(per process {min(rates):.3g}-{max(rates):.3g} particle-steps/s, "
+                      f"{wall:.0f} s wall)",
+            "per_core_rate": float(np.mean(rates)), "rc": [o["rc"] for o in outs],
             "cpu_model": model, "host_cpus_available": len(os.sched_getaffinity(0))}
 
 
@@ -430,7 +529,13 @@ def main():
                          "(profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--oracle-worker", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("worker_seed", nargs="?", type=int, default=20260101, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_worker:
+        n_w, steps_w, eos_w, dt_w, eps_w = json.loads(args.oracle_worker)
+        oracle_worker(n_w, steps_w, eos_w, dt_w, eps_w, args.worker_seed)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU slab decomposition is a design, not built)", file=sys.stderr)
@@ -474,8 +579,10 @@ def main():
     else:
         pb, ab, _ = sysm.autotune(20)
     log(f"[bench] blocks: pair {pb}, per-particle {ab}")
-    log(f"[bench] timing {args.steps} steps (100-step graph replays) after {args.warmup} warm-up")
-    secs, hist = timed_graph(sysm, args.steps, args.warmup)
+    graph_len = max(2, min(100, args.steps - args.steps % 2))
+    log(f"[bench] timing {args.steps} steps ({graph_len}-step graph replays) after "
+        f"{args.warmup} warm-up")
+    secs, hist = timed_graph(sysm, args.steps, args.warmup, g=graph_len)
     value = n * args.steps / secs
     ms_step = 1e3 * secs / args.steps
     log(f"[bench] {value:.4e} particle-steps/s ({ms_step:.3f} ms/step)")
@@ -483,44 +590,49 @@ def main():
     eager_ms = 1e3 * secs_e / 100
     prof = kernel_profile(sysm, args.profile_steps)
     nbar = mean_neighbours(sysm, n)
+    nwork = sysm.mean_work_list()
     # skin-list length from the density of the uniform fluid: pairs within rc + skin
     nskin = nbar * ((cfg.rc + cfg.skin) / cfg.rc) ** 3
     b0 = sysm.list_builds()
     sysm.step(100)
     builds_per_step = (sysm.list_builds() - b0) / 100.0
-    # kernel names as rocprofv3 reports them (batch, precision, scheme/regen, model
-    # and, for sweep 2, the surrogate fused in: this workload's learned EOS)
-    symbols = {"pass_a_forces": "k_pass_a<false, 0>", "pass_b_ser": "k_pass_b<false, 0, 0, 0>",
-               "pass_c_ser": "k_pass_c<false, 0, 0, 0, 1>"}
+    # kernel names as rocprofv3 reports them (batch, precision, model and, for
+    # sweep 2, the surrogate fused in: this workload's learned EOS)
+    symbols = {"pass_a_forces": "k_pass_a<false, 0>", "pass_b_ser": "k_pass_b_uniq<false, 0, 0>",
+               "pass_c_ser": "k_pass_c_uniq<false, 0, 0, 0, 1>"}
+    unique_pairs = 0.5 * nbar * n
     pair_roofs = {}
     for k in [k for k in prof if k in symbols]:
-        bpp_k = pair_kernel_bytes(k, nbar, nskin)
+        bpp_k = pair_kernel_bytes(k)
         t_k = prof[k]["avg_ms"] * 1e-3
         tr = counter_traffic(symbols[k])
         vi = counter_valu(symbols[k])
-        r = {"avg_launch_ms": prof[k]["avg_ms"], "algorithmic_bytes": bpp_k * n,
-             "hbm_GBps": bpp_k * n / t_k / 1e9, "hbm_frac": bpp_k * n / t_k / 1e9 / HBM_PEAK_GBS,
+        r = {"avg_launch_ms": prof[k]["avg_ms"], "algorithmic_bytes_per_particle": bpp_k,
+             "algorithmic_bytes": bpp_k * n, "hbm_GBps": bpp_k * n / t_k / 1e9,
+             "hbm_frac": bpp_k * n / t_k / 1e9 / HBM_PEAK_GBS,
+             "with_lists_bytes_per_particle": pair_kernel_list_bytes(k, nwork, nskin),
+             "with_lists_hbm_frac": pair_kernel_list_bytes(k, nwork, nskin) * n / t_k / 1e9 /
+             HBM_PEAK_GBS,
              "counter_bytes": None if tr is None else tr[0] + tr[1],
              "counter_GBps": None if tr is None else (tr[0] + tr[1]) / t_k / 1e9,
              "issued_valu_frac": None if vi is None else vi * 64 / t_k / ALU_PEAK_LANE_OPS}
         if k.startswith("pass_b"):
-            ops = PAIR_TERM_LANE_OPS * nbar * n
-            r.update({"algorithmic_lane_ops": ops, "alu_lane_ops_per_s": ops / t_k,
-                      "alu_frac": ops / t_k / ALU_PEAK_LANE_OPS})
+            # secondary: the noise and increment of every unique pair, once
+            ops = PAIR_TERM_LANE_OPS * unique_pairs
+            r.update({"unique_pairs": unique_pairs, "algorithmic_lane_ops": ops,
+                      "alu_lane_ops_per_s": ops / t_k, "alu_frac": ops / t_k / ALU_PEAK_LANE_OPS})
         pair_roofs[k] = r
     dom = max(pair_roofs, key=lambda k: pair_roofs[k]["avg_launch_ms"])
     d = pair_roofs[dom]
+    roof = {"kernel": dom, "symbol": symbols[dom], "bound": "hbm", "achieved": d["hbm_GBps"],
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["hbm_frac"],
+            "traffic": d["counter_bytes"], "bytes_per_particle": d["algorithmic_bytes_per_particle"],
+            "n": n, "avg_launch_ms": d["avg_launch_ms"], "mean_neighbours": nbar,
+            "mean_work_list": nwork, "skin_list_estimate": nskin, "pair_kernels": pair_roofs}
     if "alu_frac" in d:
-        # the sweep-1 kernel is bound by VALU work (counter-measured issue rate)
-        roof = {"kernel": dom, "bound": "alu", "achieved": d["alu_lane_ops_per_s"],
-                "peak": ALU_PEAK_LANE_OPS, "unit": "lane-op/s", "frac": d["alu_frac"],
-                "traffic": d["counter_bytes"], "lane_ops_per_pair_term": PAIR_TERM_LANE_OPS}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": d["hbm_GBps"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": d["hbm_frac"], "traffic": d["counter_bytes"]}
-    roof.update({"bytes_per_particle": pair_kernel_bytes(dom, nbar, nskin),
-                 "mean_neighbours": nbar, "skin_list_estimate": nskin,
-                 "avg_launch_ms": prof[dom]["avg_ms"], "pair_kernels": pair_roofs})
+        roof["secondary_alu"] = {"achieved": d["alu_lane_ops_per_s"], "peak": ALU_PEAK_LANE_OPS,
+                                 "unit": "lane-op/s", "frac": d["alu_frac"],
+                                 "lane_ops_per_unique_pair": PAIR_TERM_LANE_OPS}
     line = {
         "metric": "particle-steps/s at N=1M",
         "value": value,
@@ -538,7 +650,7 @@ def main():
                                "via BF16 surrogate + Newton fallback, dt=0.005, FP64 pair terms",
                    "n": n, "dt": dt, "precision": "fp64", "theta": "mlp+newton-fallback",
                    "skin": cfg.skin, "list_builds_per_step": builds_per_step,
-                   "execution": "replays of a captured 100-step graph",
+                   "execution": f"replays of a captured {graph_len}-step graph",
                    "blocks": [pb, ab], "autotuned": not args.no_autotune},
         "eager_ms_per_step": eager_ms,
         "roofline": roof,
@@ -573,7 +685,8 @@ def main():
         v32 = variants["fp32_pairs_learned_eos"]["value"]
         line["fp32_surrogate_speedup"] = {
             "vs_plain_fp64_linear_eos": v32 / variants["plain_fp64_linear_eos"]["value"],
-            "vs_fp64_newton_same_eos": v32 / variants["fp64_newton_learned_eos"]["value"]}
+            "vs_fp64_newton_same_eos": v32 / variants["fp64_newton_learned_eos"]["value"],
+            "vs_fp64_surrogate_same_eos": v32 / value}
     if not args.no_legs:
         log("[bench] batched replicas: 256 systems, one captured graph, autotuned blocks")
         line["batched_replicas"] = batched_leg(dp, W)
@@ -584,10 +697,20 @@ def main():
         log("[bench] energy drift: GPU vs oracle, N=1000")
         line["drift_vs_oracle"] = drift_vs_oracle(dp, W, list(range(1, args.drift_seeds + 1)))
         log("[bench] energy drift: GPU, N=65536, 10^4 steps")
-        line["drift_gpu"] = drift_gpu(dp, W)
+        line["drift_gpu"] = drift_gpu(dp, W, mlp_iters=args.mlp_iters)
+        sp = line.get("fp32_surrogate_speedup")
+        res = line["drift_gpu"]["results"]
+        if sp is not None:
+            # the speedup stated next to the drift of both forms on the same
+            # EOS and dt, and their difference in combined standard errors
+            a, b = res["fp32_mlp_einstein_dt0.005"], res["fp64_newton_einstein_dt0.005"]
+            sp["drift_per_1e4_fp32_surrogate"] = a["drift_per_1e4"]
+            sp["drift_per_1e4_fp64_newton"] = b["drift_per_1e4"]
+            sp["drift_diff_over_combined_se"] = abs(a["drift_per_1e4"][0] - b["drift_per_1e4"][0]) / \
+                max(1e-300, math.hypot(a["drift_per_1e4"][1], b["drift_per_1e4"][1]))
     if not args.no_cpu:
         log(f"[bench] CPU oracle: {args.cpu_steps} steps at N={n}")
-        line["cpu_baseline"] = cpu_baseline(W, n, args.cpu_steps, 1, dt, eps0)
+        line["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, 1, dt, eps0)
     # the paper's only timing of SER (its benchmark table in the section on
     # equilibrium simulations): context, not a target -- another potential,
     # another workload and one core of an unstated CPU

@@ -382,6 +382,12 @@ int dpde_debug_cells(dpde_handle* h, int32_t* cell_of_id);
  * friction gamma_ij uses (eq. DPDE_fd). */
 int dpde_debug_inv_temperature(dpde_handle* h, double* inv_t);
 
+/* Length of every particle's pair list of the current step (device int32 n,
+ * ID order): its neighbours within rc, less the pairs inside its tile that
+ * the partner's list carries when the sweeps evaluate such pairs once
+ * (DPDE_PAIRS_ONCE_PER_TILE). */
+int dpde_debug_list_lengths(dpde_handle* h, int32_t* lengths);
+
 /* Neighbour pairs (lo id, hi id) with r^2 < rc^2 of the current positions
  * (device int32 cap x 2, unordered); *npairs (host) receives the count,
  * which may exceed cap (then only cap pairs are written). */

@@ -117,6 +117,7 @@ SIGNATURES = [
     ("dpde_mlp_eval", C.c_int, [_vp, _vp, _vp, _i64]),
     ("dpde_debug_cells", C.c_int, [_vp, _vp]),
     ("dpde_debug_inv_temperature", C.c_int, [_vp, _vp]),
+    ("dpde_debug_list_lengths", C.c_int, [_vp, _vp]),
     ("dpde_debug_pairs", C.c_int, [_vp, _vp, _i64, C.POINTER(_i64)]),
     ("dpde_debug_rng", C.c_int, [C.c_uint64, C.c_uint32, _i64, _vp, _vp, _i64, _vp, _vp, _vp]),
 ]

@@ -1267,6 +1267,15 @@ int dpde_debug_inv_temperature(dpde_handle* h, double* inv_t) {
   return DPDE_OK;
 }
 
+int dpde_debug_list_lengths(dpde_handle* h, int32_t* lengths) {
+  if (!h || !lengths) return fail(DPDE_EINVAL, "NULL argument");
+  launch(h, "debug_list_lengths", k_store_list_length, blocks(h->n, 256), 256, h->cur,
+         (const Geo*)h->geo, h->n, (const uint32_t*)h->nl.count, lengths);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  return DPDE_OK;
+}
+
 int dpde_debug_pairs(dpde_handle* h, int32_t* lohi, int64_t cap, int64_t* npairs) {
   if (!h || !npairs || (cap > 0 && !lohi)) return fail(DPDE_EINVAL, "NULL argument");
   HIPCHK(hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream));

@@ -136,6 +136,15 @@ __global__ void k_store_inv_temperature(PState s, const Geo* __restrict__ geo, i
   out[geo[rc.rep].first + (int64_t)rc.id] = rc.invT;
 }
 
+// Length of every particle's list of the step into out (identifier order).
+__global__ void k_store_list_length(PState s, const Geo* __restrict__ geo, int64_t n,
+                                    const uint32_t* __restrict__ count, int32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Rec& rc = s.r[i];
+  out[geo[rc.rep].first + (int64_t)rc.id] = (int32_t)count[i];
+}
+
 constexpr int kAuxMaxThreads = 1024;  // largest block of the per-particle kernels
 
 // First half of velocity-Verlet (Sec. 3.1): p += dt/2 F, q += dt p / m, then

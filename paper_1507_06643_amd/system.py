@@ -293,6 +293,14 @@ class System:
         L.check(self._lib.dpde_debug_inv_temperature(self.h, _ptr(out)))
         return out
 
+    def debug_list_lengths(self):
+        out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        L.check(self._lib.dpde_debug_list_lengths(self.h, _ptr(out)))
+        return out
+
+    def mean_work_list(self) -> float:
+        return float(self.debug_list_lengths().double().mean().item())
+
     def debug_pairs(self, cap=None):
         cap = cap if cap is not None else 40 * self.n
         out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
