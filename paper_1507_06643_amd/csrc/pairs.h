@@ -816,6 +816,38 @@ __device__ __forceinline__ bool block_status_set(const uint32_t* status, uint32_
   return *flag != 0u;
 }
 
+// A wave of the tile sweeps serves 32 particles, two lanes each.  The first
+// kTileRegular entries of every list go through the lane-pair loop; the
+// entries beyond them, few and unevenly spread over the particles, are dealt
+// evenly over all 64 lanes of the wave, so the wave does not wait for its
+// longest list.
+constexpr int kTileRegular = 8;
+
+// The particle (0..31 within the wave) of overflow item x: the last p with
+// first[p] <= x, first[] ascending in LDS.
+__device__ __forceinline__ int overflow_owner(const uint32_t* first, uint32_t x) {
+  int lo = 0, hi = 31;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Exclusive prefix of v over the wave and the wave total.
+__device__ __forceinline__ uint32_t wave_prefix(uint32_t v, uint32_t& total) {
+  const int lane = threadIdx.x % kWave;
+  uint32_t incl = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t up = (uint32_t)__shfl_up((int)incl, off, kWave);
+    if (lane >= off) incl += up;
+  }
+  total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+  return incl - v;
+}
+
 template <bool BATCH, int PREC, int MODEL>
 __global__ __launch_bounds__(2 * kUniqTile) void k_pass_b_uniq(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
@@ -823,48 +855,86 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_b_uniq(
     uint32_t* status) {
   // two's-complement sums in unsigned words (the atomic add is modular)
   __shared__ unsigned long long acc[3][kUniqTile];
+  __shared__ uint32_t first_s[2 * kUniqTile / kWave][32];
   __shared__ uint32_t st_flag;
   for (int c = threadIdx.x; c < 3 * kUniqTile; c += blockDim.x) acc[c / kUniqTile][c % kUniqTile] = 0;
   if (block_status_set(status, &st_flag)) return;  // uniform in the block
   const int64_t tb = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kUniqTile;
   const int pl = threadIdx.x >> 1, sub = threadIdx.x & 1;
+  const int w = threadIdx.x / kWave;
+  uint32_t* first = first_s[w];
   const int64_t i = tb + pl;
   const bool live = i < n;
+  const uint64_t step = *d_step;
+  const Rec* __restrict__ R = s.r;
+  const int64_t st = nl.stride;
   long long X0 = 0, X1 = 0, X2 = 0;  // raw sums of fixed-point bit patterns
   long long terms = 0;
   uint32_t hi_max = 0u;
   Rec a{};
+  uint32_t nn = 0;
+  bool away = true;
   if (live) {
-    const uint64_t step = *d_step;
-    const Rec* __restrict__ R = s.r;
     a = R[i];
+    nn = nl.count[i];
     const GeoRef<BATCH> g = geo[BATCH ? a.rep : 0u];
-    const bool mi = !__all(away_from_faces(g, P, a.qx, a.qy, a.qz));
-    const uint32_t nn = nl.count[i];
-    const int64_t st = nl.stride;
-    for (uint32_t k = sub; k < nn; k += 2) {
-      const int64_t e = (int64_t)k * st + i;
-      const uint32_t j = nl.idx[e];
-      const Rec b = R[j];
-      double vx, vy, vz;
-      PairOut o;
-      pair_from_records<PREC, MODEL>(P, g, mi, a, b, step, vx, vy, vz, o);
-      if (store) store_dp<PREC>(nl, e, o.dp[0], o.dp[1], o.dp[2]);
-      const long long f0 = pair_fix_raw(o.dp[0]), f1 = pair_fix_raw(o.dp[1]),
-                      f2 = pair_fix_raw(o.dp[2]);
-      pair_fix_range(o.dp[0], hi_max);
-      pair_fix_range(o.dp[1], hi_max);
-      pair_fix_range(o.dp[2], hi_max);
-      X0 += f0;
-      X1 += f1;
-      X2 += f2;
-      ++terms;
-      const uint32_t rel = in_tile(j, tb);
-      if (rel < (uint32_t)kUniqTile) {  // the partner's share of a pair inside the tile
-        atomicAdd(&acc[0][rel], (unsigned long long)(kFixMagicBits - f0));
-        atomicAdd(&acc[1][rel], (unsigned long long)(kFixMagicBits - f1));
-        atomicAdd(&acc[2][rel], (unsigned long long)(kFixMagicBits - f2));
-      }
+    away = away_from_faces(g, P, a.qx, a.qy, a.qz);
+  }
+  const bool mi = !__all(away);  // uniform in the wave
+  // the pair term of entry k of particle ii (record ra): stored, its share
+  // added to the partner inside the tile; returns the raw fixed-point words
+  auto term = [&](const Rec& ra, int64_t ii, uint32_t k, long long& f0, long long& f1,
+                  long long& f2) {
+    const int64_t e = (int64_t)k * st + ii;
+    const uint32_t j = nl.idx[e];
+    const Rec b = R[j];
+    const GeoRef<BATCH> g = geo[BATCH ? ra.rep : 0u];
+    double vx, vy, vz;
+    PairOut o;
+    pair_from_records<PREC, MODEL>(P, g, mi, ra, b, step, vx, vy, vz, o);
+    if (store) store_dp<PREC>(nl, e, o.dp[0], o.dp[1], o.dp[2]);
+    f0 = pair_fix_raw(o.dp[0]);
+    f1 = pair_fix_raw(o.dp[1]);
+    f2 = pair_fix_raw(o.dp[2]);
+    pair_fix_range(o.dp[0], hi_max);
+    pair_fix_range(o.dp[1], hi_max);
+    pair_fix_range(o.dp[2], hi_max);
+    const uint32_t rel = in_tile(j, tb);
+    if (rel < (uint32_t)kUniqTile) {  // the partner's share of a pair inside the tile
+      atomicAdd(&acc[0][rel], (unsigned long long)(kFixMagicBits - f0));
+      atomicAdd(&acc[1][rel], (unsigned long long)(kFixMagicBits - f1));
+      atomicAdd(&acc[2][rel], (unsigned long long)(kFixMagicBits - f2));
+    }
+  };
+  const uint32_t nreg = nn < (uint32_t)kTileRegular ? nn : (uint32_t)kTileRegular;
+  for (uint32_t k = sub; k < nreg; k += 2) {
+    long long f0, f1, f2;
+    term(a, i, k, f0, f1, f2);
+    X0 += f0;
+    X1 += f1;
+    X2 += f2;
+    ++terms;
+  }
+  // the entries beyond kTileRegular, dealt over the wave
+  uint32_t total;
+  const uint32_t extra = (sub == 0 && nn > (uint32_t)kTileRegular) ? nn - kTileRegular : 0u;
+  const uint32_t pre = wave_prefix(extra, total);
+  if (total) {  // uniform in the wave
+    if (sub == 0) first[pl % 32] = pre;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (uint32_t x = threadIdx.x % kWave; x < total; x += kWave) {
+      const int p = overflow_owner(first, x);
+      const int slot = 32 * w + p;
+      const int64_t ii = tb + slot;
+      const uint32_t k = (uint32_t)kTileRegular + (x - first[p]);
+      const Rec ra = R[ii];
+      long long f0, f1, f2;
+      term(ra, ii, k, f0, f1, f2);
+      atomicAdd(&acc[0][slot], (unsigned long long)(f0 - kFixMagicBits));
+      atomicAdd(&acc[1][slot], (unsigned long long)(f1 - kFixMagicBits));
+      atomicAdd(&acc[2][slot], (unsigned long long)(f2 - kFixMagicBits));
     }
   }
   X0 -= terms * kFixMagicBits;
@@ -1032,64 +1102,104 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_c_uniq(
   __shared__ unsigned long long acc[kUniqTile];  // two's-complement sums (modular adds)
   __shared__ float net_x[kUniqTile];
   __shared__ float net_y[kUniqTile];
+  __shared__ uint32_t first_s[2 * kUniqTile / kWave][32];
   __shared__ uint32_t st_flag;
   for (int c = threadIdx.x; c < kUniqTile; c += blockDim.x) acc[c] = 0;
   if (block_status_set(status, &st_flag)) return;  // uniform in the block
   const int64_t tb = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kUniqTile;
   const int pl = threadIdx.x >> 1, sub = threadIdx.x & 1;
+  const int w = threadIdx.x / kWave;
+  uint32_t* first = first_s[w];
   const int64_t i = tb + pl;
   const bool live = i < n;
+  const uint64_t step = *d_step;
+  const Rec* __restrict__ R = s.r;
+  const int64_t st = nl.stride;
   long long X = 0;  // raw sum of fixed-point bit patterns
   long long terms = 0;
   uint32_t hi_max = 0u;
   Rec a{};
   Vec4 di{};
+  uint32_t nn = 0;
+  bool away = true;
   if (live) {
-    const uint64_t step = *d_step;
-    const Rec* __restrict__ R = s.r;
     a = R[i];
-    const GeoRef<BATCH> g = geo[BATCH ? a.rep : 0u];
-    const bool mi = REGEN ? !__all(away_from_faces(g, P, a.qx, a.qy, a.qz)) : true;
     di = dpi[i];
+    nn = nl.count[i];
+    if constexpr (REGEN) {
+      const GeoRef<BATCH> g = geo[BATCH ? a.rep : 0u];
+      away = away_from_faces(g, P, a.qx, a.qy, a.qz);
+    }
+  }
+  const bool mi = REGEN ? !__all(away) : true;  // uniform in the wave
+  // e_ij of entry k of particle ii (record ra, h_i = hi), given the
+  // partner's index j and h_j; its share added to the partner inside the tile
+  auto term = [&](const Rec& ra, const H3& hi, int64_t ii, uint32_t k, uint32_t j, double hx,
+                  double hy, double hz) -> long long {
+    const int64_t e = (int64_t)k * st + ii;
+    const double ux = hi.x - hx, uy = hi.y - hy, uz = hi.z - hz;
+    double ex, ey, ez;
+    if constexpr (REGEN) {
+      const Rec b = R[j];
+      const GeoRef<BATCH> g = geo[BATCH ? ra.rep : 0u];
+      double vx, vy, vz;
+      PairOut o;
+      pair_from_records<PREC, MODEL>(P, g, mi, ra, b, step, vx, vy, vz, o);
+      ex = o.dp[0];
+      ey = o.dp[1];
+      ez = o.dp[2];
+    } else {
+      load_dp<PREC>(nl, e, ex, ey, ez);
+    }
+    const double eij = -0.5 * (ex * ux + ey * uy + ez * uz);
+    const long long f = pair_fix_raw(eij);
+    pair_fix_range(eij, hi_max);
+    const uint32_t rel = in_tile(j, tb);
+    if (rel < (uint32_t)kUniqTile) atomicAdd(&acc[rel], (unsigned long long)(f - kFixMagicBits));
+    return f;
+  };
+  if (live) {
     const H3 hi = hv[i];
-    const uint32_t nn = nl.count[i];
-    const int64_t st = nl.stride;
-    uint32_t jn = (uint32_t)sub < nn ? nl.idx[(int64_t)sub * st + i] : 0u;
+    const uint32_t nreg = nn < (uint32_t)kTileRegular ? nn : (uint32_t)kTileRegular;
+    uint32_t jn = (uint32_t)sub < nreg ? nl.idx[(int64_t)sub * st + i] : 0u;
     double hx = 0.0, hy = 0.0, hz = 0.0;
-    if ((uint32_t)sub < nn) {
+    if ((uint32_t)sub < nreg) {
       hx = hv[jn].x;
       hy = hv[jn].y;
       hz = hv[jn].z;
     }
-    for (uint32_t k = sub; k < nn; k += 2) {
-      const int64_t e = (int64_t)k * st + i;
+    for (uint32_t k = sub; k < nreg; k += 2) {
       const uint32_t j = jn;
-      const double ux = hi.x - hx, uy = hi.y - hy, uz = hi.z - hz;
-      if (k + 2 < nn) {
-        jn = nl.idx[e + 2 * st];
+      const double cx = hx, cy = hy, cz = hz;
+      if (k + 2 < nreg) {
+        jn = nl.idx[(int64_t)(k + 2) * st + i];
         hx = hv[jn].x;
         hy = hv[jn].y;
         hz = hv[jn].z;
       }
-      double ex, ey, ez;
-      if constexpr (REGEN) {
-        const Rec b = R[j];
-        double vx, vy, vz;
-        PairOut o;
-        pair_from_records<PREC, MODEL>(P, g, mi, a, b, step, vx, vy, vz, o);
-        ex = o.dp[0];
-        ey = o.dp[1];
-        ez = o.dp[2];
-      } else {
-        load_dp<PREC>(nl, e, ex, ey, ez);
-      }
-      const double eij = -0.5 * (ex * ux + ey * uy + ez * uz);
-      const long long f = pair_fix_raw(eij);
-      pair_fix_range(eij, hi_max);
-      X += f;
+      X += term(a, hi, i, k, j, cx, cy, cz);
       ++terms;
-      const uint32_t rel = in_tile(j, tb);
-      if (rel < (uint32_t)kUniqTile) atomicAdd(&acc[rel], (unsigned long long)(f - kFixMagicBits));
+    }
+  }
+  // the entries beyond kTileRegular, dealt over the wave
+  uint32_t total;
+  const uint32_t extra = (sub == 0 && nn > (uint32_t)kTileRegular) ? nn - kTileRegular : 0u;
+  const uint32_t pre = wave_prefix(extra, total);
+  if (total) {  // uniform in the wave
+    if (sub == 0) first[pl % 32] = pre;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (uint32_t x = threadIdx.x % kWave; x < total; x += kWave) {
+      const int p = overflow_owner(first, x);
+      const int slot = 32 * w + p;
+      const int64_t ii = tb + slot;
+      const uint32_t k = (uint32_t)kTileRegular + (x - first[p]);
+      const uint32_t j = nl.idx[(int64_t)k * st + ii];
+      const H3 hj = hv[j];
+      const Rec ra = REGEN ? R[ii] : Rec{};
+      const long long f = term(ra, hv[ii], ii, k, j, hj.x, hj.y, hj.z);
+      atomicAdd(&acc[slot], (unsigned long long)(f - kFixMagicBits));
     }
   }
   X -= terms * kFixMagicBits;
