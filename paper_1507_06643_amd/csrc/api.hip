@@ -310,6 +310,16 @@ void physics(const dpde_params* P, Phys& ph) {
   ph.precision = P->precision;
   ph.scheme = P->scheme;
   ph.cap = P->neighbor_cap > 0 ? P->neighbor_cap : (P->skin > 0 ? 96 : 64);
+  // finest grid with a pair force a w r_hat (|.| <= a) and a potential share
+  // a rc w^2 / 4 at least a factor 2 inside the range 2^(51-g)
+  {
+    const double bound = std::max(P->a, 0.25 * P->a * P->rc);
+    int g = 46;
+    while (g > 30 && !(2.0 * bound < std::ldexp(1.0, 51 - g))) --g;
+    ph.fix_scale_f = std::ldexp(1.0, g);
+    ph.fix_inv_f = std::ldexp(1.0, -g);
+    ph.fix_range_f = (uint32_t)(1023 + 51 - g) << 20;
+  }
 }
 
 int alloc_pstate(dpde_handle* h, PState& s) {
@@ -426,6 +436,17 @@ int status_to_code(uint32_t st) {
 }
 
 // ---- the launch sequence -----------------------------------------------------
+// The tile form (the default): pairs inside a 128-particle tile evaluated
+// once, every per-particle pair sum in fixed point.  Not for SEM, whose update
+// is not written as a sum of stored terms here, nor Hybrid, whose SSA part
+// reads full, identifier-ordered lists; and only for the soft potential with
+// a < 1024, whose pair force and potential stay inside the range of pass A's
+// fixed-point sums (the splined LJ force grows without bound as r -> 0).
+bool uniq_form(const dpde_handle* h) {
+  return h->pairs_once && h->phys.scheme == DPDE_SCHEME_SER && !h->hybrid &&
+         h->phys.potential == DPDE_POT_SOFT && h->phys.a < 1024.0;
+}
+
 // Kick and drift; on list-build steps (decided on the device) the binning,
 // the reorder and the skin lists.  Buffer roles are the same either way.
 void enqueue_bin(dpde_handle* h, int kick) {
@@ -455,28 +476,39 @@ void enqueue_bin(dpde_handle* h, int kick) {
   launch(h, "copy_back", k_copy_back, blocks(n, b), b, h->alt, h->cur, n, ctl, hs2,
          (const uint32_t*)h->status);
   const int pb = h->pair_block;
+  const int uniq = uniq_form(h) ? 1 : 0;
   launch(h, "build_skin", h->batch ? k_build_skin<true> : k_build_skin<false>,
          blocks(n * kSub, pb), pb,
          h->cur, (const QIdF*)h->qid, (const uint32_t*)h->cell_start, n, (const Geo*)h->geo,
-         std::sqrt(h->rs2), h->box_max, h->skin, ctl, hs2, h->status);
-  launch(h, "sort_skin", h->skin.cap > 96 ? k_sort_skin<128> : k_sort_skin<64>, blocks(n, 256),
-         256, n, h->skin, (const uint32_t*)h->slot, ctl, hs2, (const uint32_t*)h->status);
-}
-
-// The SER sweeps over the tile work lists (the default form): not for SEM,
-// whose update is not written as a sum of stored terms here, nor Hybrid,
-// whose SSA part reads the full lists.
-bool uniq_form(const dpde_handle* h) {
-  return h->pairs_once && h->phys.scheme == DPDE_SCHEME_SER && !h->hybrid;
+         std::sqrt(h->rs2), h->box_max, h->skin, ctl, hs2, uniq, h->status);
+  // the tile form adds every pair term in fixed point: its lists need no order
+  if (!uniq)
+    launch(h, "sort_skin", h->skin.cap > 96 ? k_sort_skin<128> : k_sort_skin<64>,
+           blocks(n, 256), 256, n, h->skin, (const uint32_t*)h->slot, ctl, hs2,
+           (const uint32_t*)h->status);
 }
 
 void enqueue_forces(dpde_handle* h, int mode) {
   const int b = h->pair_block;
   const int64_t n = h->n;
-  const int uniq = uniq_form(h) ? 1 : 0;
+  if (uniq_form(h)) {
+    auto go = [&](auto kern) {
+      launch(h, "pass_a_forces", kern, blocks(n, kUniqTile), kSub * kUniqTile, h->cur, n,
+             (const Geo*)h->geo, h->phys, mode, h->Fx, h->Fy, h->Fz, h->Ui, h->Li, h->skin,
+             h->nl, h->status);
+    };
+    if (h->batch) {
+      if (h->phys.precision == DPDE_FP32) go(k_pass_a_uniq<true, PREC_F32>);
+      else go(k_pass_a_uniq<true, PREC_F64>);
+    } else {
+      if (h->phys.precision == DPDE_FP32) go(k_pass_a_uniq<false, PREC_F32>);
+      else go(k_pass_a_uniq<false, PREC_F64>);
+    }
+    return;
+  }
   auto go = [&](auto kern) {
     launch(h, "pass_a_forces", kern, blocks(n * kSub, b), b, h->cur, n, (const Geo*)h->geo, h->phys, mode,
-           uniq, h->Fx, h->Fy, h->Fz, h->Ui, h->Li, h->skin, h->nl, h->status);
+           h->Fx, h->Fy, h->Fz, h->Ui, h->Li, h->skin, h->nl, h->status);
   };
   if (h->batch) {
     if (h->phys.precision == DPDE_FP32) go(k_pass_a<true, PREC_F32>);
@@ -1011,8 +1043,16 @@ int dpde_set_shape(dpde_handle* h, const dpde_shape* shape) {
     h->pairs_once = once0;
     return rc;
   }
-  // the lists of the current step follow the form: rebuild them
-  if (once0 != h->pairs_once) enqueue_forces(h, 0);
+  // the lists follow the form: rebuild them and the forces from the current
+  // positions (no kick)
+  if (once0 != h->pairs_once) {
+    static const BuildCtl forced{0ull, 1u, 0u, 0ull};
+    static const BuildCtl cleared{0ull, 0u, 0u, 0ull};
+    HIPCHK(hipMemcpyAsync(h->ctl, &forced, sizeof(BuildCtl), hipMemcpyHostToDevice, h->stream));
+    enqueue_bin(h, 0);
+    enqueue_forces(h, 0);
+    HIPCHK(hipMemcpyAsync(h->ctl, &cleared, sizeof(BuildCtl), hipMemcpyHostToDevice, h->stream));
+  }
   HIPCHK(hipStreamSynchronize(h->stream));
   return read_status(h);
 }

@@ -65,6 +65,11 @@ struct Phys {
   int32_t model;            // 0: along v_ij (3-d G), 1: along e_ij (scalar xi)
   int32_t potential;        // 0: soft, 1: splined LJ
   int32_t project;          // eps projection after every step
+  // tile form, pass A: grid 2^-g of the force and potential sums, chosen so
+  // that |term| <= a (soft potential) stays below 2^(51-g) / 2
+  double fix_scale_f, fix_inv_f;
+  uint32_t fix_range_f;     // high word of 2^(51-g): the first |term| out of range
+  int32_t pad_fix;
 };
 
 // -------------------------------------------------------------------------

@@ -159,7 +159,19 @@ constexpr uint32_t kSubMask = (1u << kSub) - 1u;
 // ~27 skin candidates (pass A, list build) are faster with four.
 constexpr int kSubSer = 2;
 constexpr int kListLds = 64;  // list entries per particle staged in LDS
-constexpr int kUniqTile = 128;  // particles per tile (= block) of the unique-pair sweeps
+constexpr int kUniqTile = 128;  // particles per tile (= block) of the unique-pair passes
+
+// In the tile form a pair joining two particles of one tile (128 consecutive
+// memory indices) is listed for one of them only: for the lower memory index
+// when the two indices differ in parity, else for the higher one, so that
+// about half of every particle's pairs inside its tile stay in its list
+// whatever its place in the tile (the lanes of the passes stay evenly
+// loaded).  Which side evaluates a pair changes no sum: every per-particle sum
+// of the tile form is an exact fixed-point sum.
+__device__ __forceinline__ bool tile_listed(uint32_t i, uint32_t j) {
+  if ((i ^ j) >= (uint32_t)kUniqTile) return true;  // different tiles: both lists
+  return ((i ^ j) & 1u) ? (i < j) : (i > j);
+}
 
 struct Lanes {
   int64_t i;     // particle
@@ -266,11 +278,14 @@ struct SkinList {
   int32_t pad;
 };
 
+// With `uniq` (the tile form) the list keeps only the pairs tile_listed
+// assigns to this particle, holds memory indices, and is not sorted: the
+// passes that read it add their pair terms in fixed point, in any order.
 template <bool BATCH>
 __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
     PState s, const QIdF* __restrict__ qid, const uint32_t* __restrict__ start, int64_t n,
     const Geo* __restrict__ geo, double rs, double box_max, SkinList sl, const BuildCtl* ctl,
-    double half_skin2, uint32_t* status) {
+    double half_skin2, int uniq, uint32_t* status) {
   __shared__ uint32_t lst[kListLds * (kPairBlockMax / kSub)];
   if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;  // uniform
   const Lanes L = lanes();
@@ -296,11 +311,12 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
   // the list holds identifier rows (first + id) until k_sort_skin has
   // ordered them and turned them into memory indices
   const uint32_t first = (uint32_t)g.first;
-  auto sink = [&](bool take, uint32_t, uint32_t idj) {
+  auto sink = [&](bool take, uint32_t j, uint32_t idj) {
+    if (uniq) take = take && tile_listed((uint32_t)i, j);
     const uint32_t bits = group_ballot(L, take);
     if (take) {
       const uint32_t pos = nn + __popc(bits & ((1u << L.sub) - 1u));
-      const uint32_t row = first + idj;
+      const uint32_t row = uniq ? j : first + idj;
       if (pos < (uint32_t)kListLds) lst[pos * L.ppb + L.pib] = row;
       else if (pos < cap) sl.idx[(int64_t)pos * sl.stride + i] = row;
     }
@@ -404,14 +420,9 @@ __global__ __launch_bounds__(256) void k_sort_skin(int64_t n, SkinList sl,
 // share L_i = sum_j (v'' + 2 v'/r) (eq. Tcon); mode 1 also applies
 // p += dt/2 F (end of velocity-Verlet).  v is the soft potential
 // (a rc/2)(1 - r/rc)^2 or the splined LJ of eq. Ep.
-//
-// With `uniq` the list written is the work list of the tile sweeps: a pair
-// joining two particles of one 128-particle tile is listed for its lower
-// identifier only (k_pass_b_uniq, k_pass_c_uniq).  The forces always run over
-// every pair with r < rc, in list order.
 template <bool BATCH, int PREC>
 __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
-    PState s, int64_t n, const Geo* __restrict__ geo, Phys P, int mode, int uniq,
+    PState s, int64_t n, const Geo* __restrict__ geo, Phys P, int mode,
     double* __restrict__ Fx, double* __restrict__ Fy, double* __restrict__ Fz,
     double* __restrict__ Ui, double* __restrict__ Li, SkinList sl, NList nl, uint32_t* status) {
   __shared__ uint32_t lst[kListLds * (kPairBlockMax / kSub)];
@@ -425,10 +436,9 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
   const uint32_t ns = sl.count[i];
   const uint32_t cap = (uint32_t)P.cap;
   const bool mi = !__all(away_from_faces(g, P, xi, yi, zi));  // uniform in the wave
-  uint32_t nn = 0, nw = 0;  // pairs with r < rc; entries of the list written
+  uint32_t nn = 0;
   double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, lap = 0.0;
   const float inv_rc_f = (float)P.inv_rc, a_f = (float)P.a;
-  const uint32_t ui = (uint32_t)i;
   uint32_t jn = (uint32_t)L.sub < ns ? sl.idx[(int64_t)L.sub * sl.stride + i] : 0u;
   double qnx = 0.0, qny = 0.0, qnz = 0.0;
   if ((uint32_t)L.sub < ns) {
@@ -455,21 +465,11 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
     }
     const uint32_t bits = group_ballot(L, take);
     const uint32_t c = __popc(bits);
-    // a pair inside a tile is listed for one of its particles only: for the
-    // lower memory index when the two indices differ in parity, else for the
-    // higher one, so that about half of every particle's pairs inside its
-    // tile stay in its list whatever its rank (the sweeps' lanes stay evenly
-    // loaded); which side evaluates a pair does not change any sum
-    const bool mine = ((ui ^ j) & 1u) ? (ui < j) : (ui > j);
-    const bool same_tile = (ui ^ j) < (uint32_t)kUniqTile;  // tiles start at multiples of 128
-    const bool keep = take && !(uniq && same_tile && !mine);
-    const uint32_t wbits = uniq ? group_ballot(L, keep) : bits;
-    if (keep) {
-      const uint32_t pos = nw + __popc(wbits & ((1u << L.sub) - 1u));
+    if (take) {
+      const uint32_t pos = nn + __popc(bits & ((1u << L.sub) - 1u));
       if (pos < (uint32_t)kListLds) lst[pos * L.ppb + L.pib] = j;
       else if (pos < cap) nl.idx[(int64_t)pos * nl.stride + i] = j;
     }
-    nw += __popc(wbits);
     // the pair at list position p is summed by lane p mod kSub (as in passes
     // B and C), whichever lane tested it: lane sub owns rank r of this trip
     const uint32_t r = (uint32_t)(L.sub - (int)nn) & (uint32_t)(kSub - 1);
@@ -533,13 +533,13 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_a(
   lap = group_sum(lap);
   if (nn > cap) {
     if (L.sub == 0) atomicOr(status, ST_OVERFLOW);
-    nw = nw < cap ? nw : cap;
+    nn = cap;
   }
-  const uint32_t staged = nw < (uint32_t)kListLds ? nw : (uint32_t)kListLds;
+  const uint32_t staged = nn < (uint32_t)kListLds ? nn : (uint32_t)kListLds;
   for (uint32_t k = L.sub; k < staged; k += kSub)
     nl.idx[(int64_t)k * nl.stride + i] = lst[k * L.ppb + L.pib];
   if (L.sub == 0) {
-    nl.count[i] = nw;
+    nl.count[i] = nn;
     Fx[i] = fx;
     Fy[i] = fy;
     Fz[i] = fz;
@@ -804,6 +804,21 @@ __device__ __forceinline__ void pair_fix_range(double x, uint32_t& hi_max) {
 
 __device__ __forceinline__ double pair_fix_value(long long v) { return (double)v * 0x1p-46; }
 
+// The same on the grid 2^-G (|x| < 2^(51-G)): pass A's forces and potential
+// shares on 2^-40 (|term| < 2048), the Laplacian shares on 2^-30.
+template <int G>
+__device__ __forceinline__ long long fix_raw_g(double x) {
+  return __double_as_longlong(fma(x, __builtin_ldexp(1.0, G), 0x1.8p52));
+}
+template <int G>
+__device__ __forceinline__ double fix_value_g(long long v) {
+  return (double)v * __builtin_ldexp(1.0, -G);
+}
+template <int G>
+constexpr uint32_t fix_range_hi() {  // high word of 2^(51-G)
+  return (uint32_t)(1023 + 51 - G) << 20;
+}
+
 // The tile of particle j relative to the tile starting at tb, or >= 128.
 __device__ __forceinline__ uint32_t in_tile(uint32_t j, int64_t tb) {
   return j - (uint32_t)tb;
@@ -814,6 +829,260 @@ __device__ __forceinline__ bool block_status_set(const uint32_t* status, uint32_
   if (threadIdx.x == 0) *flag = *status;
   __syncthreads();
   return *flag != 0u;
+}
+
+// Conservative pair terms of one pair at squared distance r2 (r < rc), as
+// seen by particle i: f * d_ij with f = -v'(r)/r, the potential v(r) and the
+// Laplacian term v'' + 2 v'/r (eq. Tcon).  A coincident pair adds v(0) and
+// no force.
+template <int PREC>
+__device__ __forceinline__ void pair_conservative(const Phys& P, double dx, double dy, double dz,
+                                                  double r2, double& gx, double& gy, double& gz,
+                                                  double& v, double& lap) {
+  if constexpr (PREC == PREC_F64) {
+    const double ir = inv_sqrt_f64(r2);  // 0 at r = 0
+    const double rr = r2 * ir;
+    double f;
+    if (P.potential == 0) {
+      const double w = 1.0 - rr * P.inv_rc;
+      v = P.half_a_rc * w * w;
+      f = P.a * w * ir;  // -v'(r)/r
+      lap = ir > 0.0 ? P.a * P.inv_rc - 2.0 * P.a * w * ir : 0.0;
+    } else {
+      const double ir2 = ir * ir;
+      const double s2 = P.r_lj2 * ir2;
+      const double s6 = s2 * s2 * s2, s12 = s6 * s6;
+      v = P.lj4e * (s12 - s6) - P.lj_vc - P.lj_dvc * (rr - P.rc);
+      const double dv = -6.0 * P.lj4e * (2.0 * s12 - s6) * ir - P.lj_dvc;
+      f = -dv * ir;
+      lap = P.lj4e * (156.0 * s12 - 42.0 * s6) * ir2 + 2.0 * dv * ir;
+    }
+    gx = f * dx;
+    gy = f * dy;
+    gz = f * dz;
+  } else {
+    const float inv_rc_f = (float)P.inv_rc, a_f = (float)P.a;
+    const float rr = __builtin_sqrtf((float)r2);
+    const float ir = rr > 0.0f ? 1.0f / rr : 0.0f;
+    float f;
+    if (P.potential == 0) {
+      const float w = 1.0f - rr * inv_rc_f;
+      v = (double)((float)P.half_a_rc * w * w);
+      f = a_f * w * ir;
+      lap = (double)(rr > 0.0f ? a_f * inv_rc_f - 2.0f * a_f * w * ir : 0.0f);
+    } else {
+      const float ir2 = ir * ir;
+      const float s2 = (float)P.r_lj2 * ir2;
+      const float s6 = s2 * s2 * s2, s12 = s6 * s6;
+      const float e4 = (float)P.lj4e;
+      v = (double)(e4 * (s12 - s6) - (float)P.lj_vc - (float)P.lj_dvc * (rr - (float)P.rc));
+      const float dv = -6.0f * e4 * (2.0f * s12 - s6) * ir - (float)P.lj_dvc;
+      f = -dv * ir;
+      lap = (double)(e4 * (156.0f * s12 - 42.0f * s6) * ir2 + 2.0f * dv * ir);
+    }
+    gx = (double)(f * (float)dx);
+    gy = (double)(f * (float)dy);
+    gz = (double)(f * (float)dz);
+  }
+}
+
+// Pass A in the tile form: the tile's 128 particles, four lanes each, walk
+// their skin lists (which hold the pairs tile_listed assigns them); every
+// pair with r < rc goes to the work list of the step and its conservative
+// terms are added once, in fixed point, to both particles (the partner's
+// share through LDS when it lies in the tile; a pair joining two tiles is in
+// both lists and adds to its own particle only).  Forces and potential shares
+// (U_i = 1/2 sum_j v(r_ij)) on the grid 2^-g chosen from a (2^-46 for a < 16,
+// 2^-45 for a = 25): the form is used with the soft potential, whose pair
+// force and potential are bounded by a;
+// the Laplacian shares, which grow as 1/r, in two words: the term on the grid
+// 2^-20 and its remainder on 2^-50.  Mode 1 also applies p += dt/2 F (end of
+// velocity-Verlet).
+constexpr int kTileListLds = 32;  // work-list entries per particle staged in LDS
+constexpr int kTileSkinLds = 32;  // skin-list entries per particle staged in LDS
+
+template <bool BATCH, int PREC>
+__global__ __launch_bounds__(kSub * kUniqTile) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_pass_a_uniq(
+    PState s, int64_t n, const Geo* __restrict__ geo, Phys P, int mode,
+    double* __restrict__ Fx, double* __restrict__ Fy, double* __restrict__ Fz,
+    double* __restrict__ Ui, double* __restrict__ Li, SkinList sl, NList nl, uint32_t* status) {
+  constexpr int GH = 20, GR = 50;
+  const double fsc = P.fix_scale_f;  // forces and potential shares: grid 1/fsc
+  auto fix_f = [&](double x) { return __double_as_longlong(fma(x, fsc, 0x1.8p52)); };
+  __shared__ unsigned long long acc[6][kUniqTile];  // Fx Fy Fz U Lhi Llo, two's complement
+  __shared__ uint32_t lst[kTileListLds * kUniqTile];
+  __shared__ uint32_t skin[kTileSkinLds * kUniqTile];  // the tile's skin lists, entry-major
+  __shared__ uint32_t st_flag;
+  for (int c = threadIdx.x; c < 6 * kUniqTile; c += blockDim.x) acc[c / kUniqTile][c % kUniqTile] = 0;
+  if (block_status_set(status, &st_flag)) return;  // uniform in the block
+  const int64_t tb = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kUniqTile;
+  {
+    // the first kTileSkinLds entries of every skin list of the tile, loaded
+    // row by row (128 consecutive words per row), all loads in flight at once
+    constexpr int kPer = kTileSkinLds * kUniqTile / (kSub * kUniqTile);
+    uint32_t v[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int c = r * (kSub * kUniqTile) + threadIdx.x;
+      const int k = c / kUniqTile, t = c % kUniqTile;
+      const int64_t row = tb + t < n ? tb + t : n - 1;
+      v[r] = sl.idx[(int64_t)k * sl.stride + row];
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) skin[r * (kSub * kUniqTile) + threadIdx.x] = v[r];
+    __syncthreads();
+  }
+  const int pl = threadIdx.x / kSub, sub = threadIdx.x % kSub;
+  const int shift = (threadIdx.x % kWave) & ~(kSub - 1);
+  const int64_t i = tb + pl;
+  const bool live = i < n;
+  const Rec* __restrict__ R = s.r;
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  uint32_t ns = 0;
+  bool away = true;
+  if (live) {
+    xi = R[i].qx;
+    yi = R[i].qy;
+    zi = R[i].qz;
+    ns = sl.count[i];
+    const GeoRef<BATCH> g = geo[BATCH ? R[i].rep : 0u];
+    away = away_from_faces(g, P, xi, yi, zi);
+  }
+  const bool mi = !__all(away);  // uniform in the wave
+  const uint32_t cap = (uint32_t)P.cap;
+  long long XF0 = 0, XF1 = 0, XF2 = 0, XU = 0, XLh = 0, XLl = 0;  // raw fixed-point words
+  long long terms = 0;
+  uint32_t hi_f = 0u, hi_l = 0u;
+  uint32_t nn = 0;
+  if (live) {
+    const GeoRef<BATCH> g = geo[BATCH ? R[i].rep : 0u];
+    // one trip of the group over entries base + sub (uniform in the group)
+    auto trip = [&](uint32_t k, uint32_t j, double qjx, double qjy, double qjz) {
+      bool take = false;
+      double dx = 0.0, dy = 0.0, dz = 0.0, r2 = 0.0;
+      if (k < ns) {
+        separation_mi(g, mi, xi, yi, zi, qjx, qjy, qjz, dx, dy, dz);
+        r2 = dist2(dx, dy, dz);
+        take = r2 < P.rc2;
+      }
+      const uint32_t bits = (uint32_t)(__ballot(take) >> shift) & kSubMask;
+      if (take) {
+        const uint32_t pos = nn + __popc(bits & ((1u << sub) - 1u));
+        if (pos < (uint32_t)kTileListLds) lst[pos * kUniqTile + pl] = j;
+        else if (pos < cap) nl.idx[(int64_t)pos * nl.stride + i] = j;
+        double gx, gy, gz, v, lap;
+        pair_conservative<PREC>(P, dx, dy, dz, r2, gx, gy, gz, v, lap);
+        const long long f0 = fix_f(gx), f1 = fix_f(gy), f2 = fix_f(gz);
+        const long long fu = fix_f(0.5 * v);
+        // Laplacian term: 2^-20 grid, then the (exact) remainder on 2^-50
+        const long long fh = fix_raw_g<GH>(lap);
+        const double rem = lap - (double)(fh - kFixMagicBits) * 0x1p-20;
+        const long long fr = fix_raw_g<GR>(rem);
+        pair_fix_range(gx, hi_f);
+        pair_fix_range(gy, hi_f);
+        pair_fix_range(gz, hi_f);
+        pair_fix_range(0.5 * v, hi_f);
+        pair_fix_range(lap, hi_l);
+        XF0 += f0;
+        XF1 += f1;
+        XF2 += f2;
+        XU += fu;
+        XLh += fh;
+        XLl += fr;
+        ++terms;
+        const uint32_t rel = in_tile(j, tb);
+        if (rel < (uint32_t)kUniqTile) {  // the partner's share of a pair inside the tile
+          atomicAdd(&acc[0][rel], (unsigned long long)(kFixMagicBits - f0));
+          atomicAdd(&acc[1][rel], (unsigned long long)(kFixMagicBits - f1));
+          atomicAdd(&acc[2][rel], (unsigned long long)(kFixMagicBits - f2));
+          atomicAdd(&acc[3][rel], (unsigned long long)(fu - kFixMagicBits));
+          atomicAdd(&acc[4][rel], (unsigned long long)(fh - kFixMagicBits));
+          atomicAdd(&acc[5][rel], (unsigned long long)(fr - kFixMagicBits));
+        }
+      }
+      nn += __popc(bits);
+    };
+    // entries staged in LDS: the next trip's position is requested before
+    // this trip's pair terms
+    const uint32_t ns0 = ns < (uint32_t)kTileSkinLds ? ns : (uint32_t)kTileSkinLds;
+    uint32_t jn = (uint32_t)sub < ns0 ? skin[sub * kUniqTile + pl] : 0u;
+    double qnx = 0.0, qny = 0.0, qnz = 0.0;
+    if ((uint32_t)sub < ns0) {
+      qnx = R[jn].qx;
+      qny = R[jn].qy;
+      qnz = R[jn].qz;
+    }
+    uint32_t base = 0;
+    for (; base < ns0; base += kSub) {
+      const uint32_t k = base + sub;
+      const uint32_t j = jn;
+      const double qjx = qnx, qjy = qny, qjz = qnz;
+      if (k + kSub < ns0) {
+        jn = skin[(k + kSub) * kUniqTile + pl];
+        qnx = R[jn].qx;
+        qny = R[jn].qy;
+        qnz = R[jn].qz;
+      }
+      trip(k, j, qjx, qjy, qjz);
+    }
+    // longer lists: the rest from memory
+    for (; base < ns; base += kSub) {
+      const uint32_t k = base + sub;
+      uint32_t j = 0u;
+      double qjx = 0.0, qjy = 0.0, qjz = 0.0;
+      if (k < ns) {
+        j = sl.idx[(int64_t)k * sl.stride + i];
+        qjx = R[j].qx;
+        qjy = R[j].qy;
+        qjz = R[j].qz;
+      }
+      trip(k, j, qjx, qjy, qjz);
+    }
+  }
+  const long long m = terms * kFixMagicBits;
+  XF0 -= m;
+  XF1 -= m;
+  XF2 -= m;
+  XU -= m;
+  XLh -= m;
+  XLl -= m;
+#pragma unroll
+  for (int off = 1; off < kSub; off <<= 1) {
+    XF0 += __shfl_xor(XF0, off, kWave);
+    XF1 += __shfl_xor(XF1, off, kWave);
+    XF2 += __shfl_xor(XF2, off, kWave);
+    XU += __shfl_xor(XU, off, kWave);
+    XLh += __shfl_xor(XLh, off, kWave);
+    XLl += __shfl_xor(XLl, off, kWave);
+  }
+  if (hi_f >= P.fix_range_f || hi_l >= fix_range_hi<GH>()) atomicOr(status, ST_RANGE);
+  __syncthreads();
+  if (!live) return;
+  if (nn > cap) {
+    if (sub == 0) atomicOr(status, ST_OVERFLOW);
+    nn = cap;
+  }
+  const uint32_t staged = nn < (uint32_t)kTileListLds ? nn : (uint32_t)kTileListLds;
+  for (uint32_t k = sub; k < staged; k += kSub)
+    nl.idx[(int64_t)k * nl.stride + i] = lst[k * kUniqTile + pl];
+  if (sub == 0) {
+    const double fx = (double)(long long)((unsigned long long)XF0 + acc[0][pl]) * P.fix_inv_f;
+    const double fy = (double)(long long)((unsigned long long)XF1 + acc[1][pl]) * P.fix_inv_f;
+    const double fz = (double)(long long)((unsigned long long)XF2 + acc[2][pl]) * P.fix_inv_f;
+    nl.count[i] = nn;
+    Fx[i] = fx;
+    Fy[i] = fy;
+    Fz[i] = fz;
+    Ui[i] = (double)(long long)((unsigned long long)XU + acc[3][pl]) * P.fix_inv_f;
+    Li[i] = fix_value_g<GH>((long long)((unsigned long long)XLh + acc[4][pl])) +
+            fix_value_g<GR>((long long)((unsigned long long)XLl + acc[5][pl]));
+    if (mode) {
+      Rec* W = s.r;
+      W[i].px = W[i].px + P.half_dt * fx;
+      W[i].py = W[i].py + P.half_dt * fy;
+      W[i].pz = W[i].pz + P.half_dt * fz;
+    }
+  }
 }
 
 // A wave of the tile sweeps serves 32 particles, two lanes each.  The first
@@ -881,12 +1150,12 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_b_uniq(
     away = away_from_faces(g, P, a.qx, a.qy, a.qz);
   }
   const bool mi = !__all(away);  // uniform in the wave
-  // the pair term of entry k of particle ii (record ra): stored, its share
-  // added to the partner inside the tile; returns the raw fixed-point words
-  auto term = [&](const Rec& ra, int64_t ii, uint32_t k, long long& f0, long long& f1,
-                  long long& f2) {
+  // the pair term of entry k (partner j) of particle ii (record ra): stored,
+  // its share added to the partner inside the tile; returns the raw
+  // fixed-point words
+  auto term = [&](const Rec& ra, int64_t ii, uint32_t k, uint32_t j, long long& f0,
+                  long long& f1, long long& f2) {
     const int64_t e = (int64_t)k * st + ii;
-    const uint32_t j = nl.idx[e];
     const Rec b = R[j];
     const GeoRef<BATCH> g = geo[BATCH ? ra.rep : 0u];
     double vx, vy, vz;
@@ -907,9 +1176,20 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_b_uniq(
     }
   };
   const uint32_t nreg = nn < (uint32_t)kTileRegular ? nn : (uint32_t)kTileRegular;
-  for (uint32_t k = sub; k < nreg; k += 2) {
+  // this lane's regular entries sub, sub + 2, ...: every index load in flight
+  // at once (addresses clamped to the list, so no load needs a branch)
+  uint32_t jr[kTileRegular / 2];
+#pragma unroll
+  for (int q = 0; q < kTileRegular / 2; ++q) {
+    const uint32_t k = (uint32_t)(sub + 2 * q);
+    const uint32_t kc = k < nreg ? k : (nreg ? nreg - 1u : 0u);
+    jr[q] = nreg ? nl.idx[(int64_t)kc * st + i] : 0u;
+  }
+  for (int q = 0; q < kTileRegular / 2; ++q) {
+    const uint32_t k = (uint32_t)(sub + 2 * q);
+    if (k >= nreg) break;
     long long f0, f1, f2;
-    term(a, i, k, f0, f1, f2);
+    term(a, i, k, jr[q], f0, f1, f2);
     X0 += f0;
     X1 += f1;
     X2 += f2;
@@ -931,7 +1211,7 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_b_uniq(
       const uint32_t k = (uint32_t)kTileRegular + (x - first[p]);
       const Rec ra = R[ii];
       long long f0, f1, f2;
-      term(ra, ii, k, f0, f1, f2);
+      term(ra, ii, k, nl.idx[(int64_t)k * st + ii], f0, f1, f2);
       atomicAdd(&acc[0][slot], (unsigned long long)(f0 - kFixMagicBits));
       atomicAdd(&acc[1][slot], (unsigned long long)(f1 - kFixMagicBits));
       atomicAdd(&acc[2][slot], (unsigned long long)(f2 - kFixMagicBits));
@@ -1161,23 +1441,32 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_c_uniq(
   if (live) {
     const H3 hi = hv[i];
     const uint32_t nreg = nn < (uint32_t)kTileRegular ? nn : (uint32_t)kTileRegular;
-    uint32_t jn = (uint32_t)sub < nreg ? nl.idx[(int64_t)sub * st + i] : 0u;
+    // this lane's regular entries: every index load in flight at once, then
+    // each partner's h requested one entry ahead
+    uint32_t jr[kTileRegular / 2];
+#pragma unroll
+    for (int q = 0; q < kTileRegular / 2; ++q) {
+      const uint32_t k = (uint32_t)(sub + 2 * q);
+      const uint32_t kc = k < nreg ? k : (nreg ? nreg - 1u : 0u);
+      jr[q] = nreg ? nl.idx[(int64_t)kc * st + i] : 0u;
+    }
     double hx = 0.0, hy = 0.0, hz = 0.0;
     if ((uint32_t)sub < nreg) {
-      hx = hv[jn].x;
-      hy = hv[jn].y;
-      hz = hv[jn].z;
+      hx = hv[jr[0]].x;
+      hy = hv[jr[0]].y;
+      hz = hv[jr[0]].z;
     }
-    for (uint32_t k = sub; k < nreg; k += 2) {
-      const uint32_t j = jn;
+#pragma unroll
+    for (int q = 0; q < kTileRegular / 2; ++q) {
+      const uint32_t k = (uint32_t)(sub + 2 * q);
+      if (k >= nreg) break;
       const double cx = hx, cy = hy, cz = hz;
-      if (k + 2 < nreg) {
-        jn = nl.idx[(int64_t)(k + 2) * st + i];
-        hx = hv[jn].x;
-        hy = hv[jn].y;
-        hz = hv[jn].z;
+      if (q + 1 < kTileRegular / 2 && k + 2 < nreg) {
+        hx = hv[jr[q + 1]].x;
+        hy = hv[jr[q + 1]].y;
+        hz = hv[jr[q + 1]].z;
       }
-      X += term(a, hi, i, k, j, cx, cy, cz);
+      X += term(a, hi, i, k, jr[q], cx, cy, cz);
       ++terms;
     }
   }
