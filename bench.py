@@ -598,7 +598,7 @@ def main():
     builds_per_step = (sysm.list_builds() - b0) / 100.0
     # kernel names as rocprofv3 reports them (batch, precision, model and, for
     # sweep 2, the surrogate fused in: this workload's learned EOS)
-    symbols = {"pass_a_forces": "k_pass_a<false, 0>", "pass_b_ser": "k_pass_b_uniq<false, 0, 0>",
+    symbols = {"pass_a_forces": "k_pass_a_uniq<false, 0>", "pass_b_ser": "k_pass_b_uniq<false, 0, 0>",
                "pass_c_ser": "k_pass_c_uniq<false, 0, 0, 0, 1>"}
     unique_pairs = 0.5 * nbar * n
     pair_roofs = {}

@@ -151,7 +151,12 @@ typedef struct dpde_handle dpde_handle;
 
 /*
  * Create a system from initial state (device pointers, ID order; see above)
- * and compute F(q0), U(q0), T_i(eps0) and the initial energies.
+ * and compute F(q0), U(q0), T_i(eps0) and the initial energies.  The state
+ * is that of Sec. 2.1: positions q_i, momenta p_i and internal energies
+ * eps_i of the mesoparticles, with total energy
+ *   E = sum_{i<j} v(r_ij) + sum_i p_i^2/(2m) + sum_i eps_i
+ * conserved by the dynamics (eq. DPDE), and internal temperatures T_i =
+ * theta(eps_i) from the internal EOS (eq. DPDE_internalEOS).
  * hip_stream: hipStream_t the inputs were produced on (NULL = null stream).
  * Errors: DPDE_EINVAL / DPDE_EBOX on parameters, DPDE_EINVAL on non-finite
  * inputs, DPDE_ENEG_EINT on eps <= 0, DPDE_ENOMEM, DPDE_EHIP.
@@ -194,8 +199,9 @@ int dpde_energies(dpde_handle* h, double out[DPDE_REC_LEN]);
  */
 int dpde_history(dpde_handle* h, double* out, int64_t cap, int64_t* count);
 
-/* Current state into device buffers in ID order (q, p: n x 3; eps: n);
- * any pointer may be NULL.  *step (host) receives the step counter if non-NULL. */
+/* Current state (q_i, p_i, eps_i of Sec. 2.1) into device buffers in ID
+ * order (q, p: n x 3; eps: n); any pointer may be NULL.  *step (host)
+ * receives the step counter if non-NULL. */
 int dpde_get_state(dpde_handle* h, double* q, double* p, double* eps, int64_t* step);
 
 /* Replace the state (device pointers, ID order) and the step counter; forces,
@@ -268,9 +274,13 @@ int dpde_set_tuning(dpde_handle* h, int32_t pair_block, int32_t aux_block);
  *                               a term of magnitude >= 32 fails the step with
  *                               DPDE_ERANGE), rounded once.  The default; SEM
  *                               and Hybrid run the first form.
+ *   order_block  memory order of the particles: sorted by cell, the cells
+ *               taken in blocks of order_block^3 (compact blocks keep more of
+ *               a particle's neighbours inside its tile and its cache lines).
  * Either form gives trajectories that do not depend on the memory order, the
  * skin, the rebuild schedule or the batching.  dpde_set_tuning sets the first
- * two fields only.
+ * two fields only.  A change of form or order rebuilds the lists and the
+ * forces from the current state.
  */
 #define DPDE_PAIRS_BOTH_SIDES 0
 #define DPDE_PAIRS_ONCE_PER_TILE 1
@@ -278,7 +288,9 @@ typedef struct dpde_shape {
   int32_t pair_block;
   int32_t aux_block;
   int32_t pairs;
-  int32_t reserved; /* 0 */
+  int32_t order_block; /* 1..8: memory order of the cells, blocks of
+                          order_block^3 cells in row-major block order
+                          (1: row-major cells, the default) */
 } dpde_shape;
 int dpde_get_shape(dpde_handle* h, dpde_shape* out);
 int dpde_set_shape(dpde_handle* h, const dpde_shape* shape);

@@ -57,7 +57,7 @@ class Params(C.Structure):
 class Shape(C.Structure):
     """Mirror of struct dpde_shape."""
     _fields_ = [("pair_block", C.c_int32), ("aux_block", C.c_int32), ("pairs", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("order_block", C.c_int32)]
 
 
 PAIRS_BOTH_SIDES, PAIRS_ONCE_PER_TILE = 0, 1

@@ -47,6 +47,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int kHistBytes = 64 << 20;
+constexpr int kOrderBlockMax = 8;  // largest edge of the cell blocks of the memory order
 constexpr int64_t kStatTile = 2048;
 
 struct ProfileRec {
@@ -263,6 +264,7 @@ int geometry(const dpde_params* P, Geo& g) {
     g.scale[d] = (double)g.nc[d] / P->box[d];
     g.periodic[d] = P->periodic[d];
   }
+  g.oblk = 1;
   g.key0 = (uint32_t)P->seed;
   g.key1 = (uint32_t)(P->seed >> 32) ^ P->replica;
   for (int d = 0; d < 3; ++d) {
@@ -475,8 +477,8 @@ void enqueue_bin(dpde_handle* h, int kick) {
          (const uint32_t*)h->status);
   launch(h, "copy_back", k_copy_back, blocks(n, b), b, h->alt, h->cur, n, ctl, hs2,
          (const uint32_t*)h->status);
-  const int pb = h->pair_block;
   const int uniq = uniq_form(h) ? 1 : 0;
+  const int pb = h->pair_block;
   launch(h, "build_skin", h->batch ? k_build_skin<true> : k_build_skin<false>,
          blocks(n * kSub, pb), pb,
          h->cur, (const QIdF*)h->qid, (const uint32_t*)h->cell_start, n, (const Geo*)h->geo,
@@ -1028,7 +1030,7 @@ int dpde_get_shape(dpde_handle* h, dpde_shape* out) {
   out->pair_block = h->pair_block;
   out->aux_block = h->aux_block;
   out->pairs = h->pairs_once ? DPDE_PAIRS_ONCE_PER_TILE : DPDE_PAIRS_BOTH_SIDES;
-  out->reserved = 0;
+  out->order_block = h->geo_h[0].oblk;
   return DPDE_OK;
 }
 
@@ -1036,6 +1038,9 @@ int dpde_set_shape(dpde_handle* h, const dpde_shape* shape) {
   if (!h || !shape) return fail(DPDE_EINVAL, "NULL argument");
   if (shape->pairs != DPDE_PAIRS_BOTH_SIDES && shape->pairs != DPDE_PAIRS_ONCE_PER_TILE)
     return fail(DPDE_EINVAL, "unknown pair form %d", shape->pairs);
+  if (shape->order_block < 1 || shape->order_block > kOrderBlockMax)
+    return fail(DPDE_EINVAL, "order_block must be in [1, %d], got %d", kOrderBlockMax,
+                shape->order_block);
   const bool once0 = h->pairs_once;
   h->pairs_once = shape->pairs == DPDE_PAIRS_ONCE_PER_TILE;
   int rc = dpde_set_tuning(h, shape->pair_block, shape->aux_block);
@@ -1043,9 +1048,15 @@ int dpde_set_shape(dpde_handle* h, const dpde_shape* shape) {
     h->pairs_once = once0;
     return rc;
   }
-  // the lists follow the form: rebuild them and the forces from the current
-  // positions (no kick)
-  if (once0 != h->pairs_once) {
+  const bool reorder = shape->order_block != h->geo_h[0].oblk;
+  if (reorder) {
+    for (Geo& g : h->geo_h) g.oblk = shape->order_block;
+    HIPCHK(hipMemcpyAsync(h->geo, h->geo_h.data(), h->nrep * sizeof(Geo), hipMemcpyHostToDevice,
+                          h->stream));
+  }
+  // the order and the lists follow the shape: rebuild them and the forces
+  // from the current positions (no kick)
+  if (once0 != h->pairs_once || reorder) {
     static const BuildCtl forced{0ull, 1u, 0u, 0ull};
     static const BuildCtl cleared{0ull, 0u, 0u, 0ull};
     HIPCHK(hipMemcpyAsync(h->ctl, &forced, sizeof(BuildCtl), hipMemcpyHostToDevice, h->stream));

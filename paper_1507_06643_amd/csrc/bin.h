@@ -274,7 +274,7 @@ __global__ void k_bin_key(PState s, int64_t n, const Geo* __restrict__ geo,
     const int cx = cell_coord(rc.qx, g.scale[0], g.nc[0]);
     const int cy = cell_coord(rc.qy, g.scale[1], g.nc[1]);
     const int cz = cell_coord(rc.qz, g.scale[2], g.nc[2]);
-    c = (uint32_t)(g.cell_base + cx + (int64_t)g.nc[0] * (cy + (int64_t)g.nc[1] * cz));
+    c = (uint32_t)(g.cell_base + cell_key(g, cx, cy, cz));
     key[i] = c;
     idk[i] = rc.id;
   }

@@ -33,7 +33,7 @@ struct Geo {
   uint32_t key0, key1; // Philox key: seed low word, seed high word ^ replica
   double dscale[3];    // Hybrid domains per unit length: ndom / box
   int32_t ndom[3];     // Hybrid domains per dimension
-  int32_t pad_dom;
+  int32_t oblk;        // edge (in cells) of the cell blocks of the memory order
   int64_t dom_base;    // global index of the replica's domain 0
 };
 
@@ -290,6 +290,25 @@ __device__ __forceinline__ int cell_coord(double x, double scale, int nc) {
   c = (c >= 0.0) ? c : 0.0;  // also maps NaN to 0 so indices stay in range
   c = (c <= (double)(nc - 1)) ? c : (double)(nc - 1);
   return (int)c;
+}
+
+// Memory order of the cells (the particles are kept sorted by this key):
+// blocks of oblk^3 cells in row-major block order, row-major cells inside a
+// block, the blocks at the high faces cut to the box; oblk = 1 is the
+// row-major order of the cells.  The map is a bijection onto
+// [0, nc0 nc1 nc2), and cells that follow each other along x inside one
+// block have consecutive keys.  Compact blocks keep more of a particle's
+// neighbours in the particles stored next to it.
+__device__ __forceinline__ uint32_t cell_key(const Geo& g, int cx, int cy, int cz) {
+  const int64_t n0 = g.nc[0], n1 = g.nc[1];
+  const int B = g.oblk;
+  if (B == 1) return (uint32_t)(cx + n0 * (cy + n1 * cz));
+  const int bx = cx / B, by = cy / B, bz = cz / B;
+  const int sx = min(B, g.nc[0] - bx * B), sy = min(B, g.nc[1] - by * B),
+            sz = min(B, g.nc[2] - bz * B);
+  const int lx = cx - bx * B, ly = cy - by * B, lz = cz - bz * B;
+  return (uint32_t)(n0 * n1 * (bz * B) + n0 * sz * (by * B) + (int64_t)sy * sz * (bx * B) + lx +
+                    sx * (ly + sy * lz));
 }
 
 // -------------------------------------------------------------------------

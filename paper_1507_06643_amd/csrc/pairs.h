@@ -82,30 +82,6 @@ __device__ __forceinline__ bool wrap_cell(int& c, int nc, int periodic) {
   return true;
 }
 
-// Visit every particle j of the 27 cells around (cx, cy, cz).
-template <typename F>
-__device__ __forceinline__ void for_each_candidate(const Geo& g, const uint32_t* __restrict__ start,
-                                                   int cx, int cy, int cz, F&& f) {
-  const Row row = stencil_row(cx, g.nc[0], g.periodic[0]);
-  for (int dz = -1; dz <= 1; ++dz) {
-    int z = cz + dz;
-    if (!wrap_cell(z, g.nc[2], g.periodic[2])) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      int y = cy + dy;
-      if (!wrap_cell(y, g.nc[1], g.periodic[1])) continue;
-      const int64_t base = g.cell_base + (int64_t)g.nc[0] * (y + (int64_t)g.nc[1] * z);
-      {
-        const uint32_t jb = start[base + row.a0], je = start[base + row.b0 + 1];
-        for (uint32_t j = jb; j < je; ++j) f(j);
-      }
-      if (row.a1 <= row.b1) {
-        const uint32_t jb = start[base + row.a1], je = start[base + row.b1 + 1];
-        for (uint32_t j = jb; j < je; ++j) f(j);
-      }
-    }
-  }
-}
-
 // Separation q_i - q_j with the minimum image along periodic dimensions.
 __device__ __forceinline__ void separation(const Geo& g, double xi, double yi, double zi,
                                            double xj, double yj, double zj, double& dx,
@@ -171,6 +147,19 @@ constexpr int kUniqTile = 128;  // particles per tile (= block) of the unique-pa
 __device__ __forceinline__ bool tile_listed(uint32_t i, uint32_t j) {
   if ((i ^ j) >= (uint32_t)kUniqTile) return true;  // different tiles: both lists
   return ((i ^ j) & 1u) ? (i < j) : (i > j);
+}
+
+// Exclusive prefix of v over the wave and the wave total.
+__device__ __forceinline__ uint32_t wave_prefix(uint32_t v, uint32_t& total) {
+  const int lane = threadIdx.x % kWave;
+  uint32_t incl = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t up = (uint32_t)__shfl_up((int)incl, off, kWave);
+    if (lane >= off) incl += up;
+  }
+  total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+  return incl - v;
 }
 
 struct Lanes {
@@ -242,15 +231,30 @@ __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
     }
   };
   const Row row = stencil_row(cx, g.nc[0], g.periodic[0]);
+  const int B = g.oblk;
   for (int dz = -1; dz <= 1; ++dz) {
     int z = cz + dz;
     if (!wrap_cell(z, g.nc[2], g.periodic[2])) continue;
     for (int dy = -1; dy <= 1; ++dy) {
       int y = cy + dy;
       if (!wrap_cell(y, g.nc[1], g.periodic[1])) continue;
-      const int64_t base = g.cell_base + (int64_t)g.nc[0] * (y + (int64_t)g.nc[1] * z);
-      range(start[base + row.a0], start[base + row.b0 + 1]);
-      if (row.a1 <= row.b1) range(start[base + row.a1], start[base + row.b1 + 1]);
+      if (B == 1) {  // row-major cells: each x range is one run of memory
+        const int64_t base = g.cell_base + (int64_t)g.nc[0] * (y + (int64_t)g.nc[1] * z);
+        range(start[base + row.a0], start[base + row.b0 + 1]);
+        if (row.a1 <= row.b1) range(start[base + row.a1], start[base + row.b1 + 1]);
+      } else {
+        // blocked order: an x range is one run per cell block it crosses
+        auto xrun = [&](int a, int b) {
+          for (int x = a; x <= b;) {
+            const int e = min(b, (x / B) * B + B - 1);
+            const int64_t k0 = g.cell_base + cell_key(g, x, y, z);
+            range(start[k0], start[k0 + (e - x) + 1]);
+            x = e + 1;
+          }
+        };
+        xrun(row.a0, row.b0);
+        if (row.a1 <= row.b1) xrun(row.a1, row.b1);
+      }
     }
   }
 }
@@ -1102,19 +1106,6 @@ __device__ __forceinline__ int overflow_owner(const uint32_t* first, uint32_t x)
     else hi = mid - 1;
   }
   return lo;
-}
-
-// Exclusive prefix of v over the wave and the wave total.
-__device__ __forceinline__ uint32_t wave_prefix(uint32_t v, uint32_t& total) {
-  const int lane = threadIdx.x % kWave;
-  uint32_t incl = v;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const uint32_t up = (uint32_t)__shfl_up((int)incl, off, kWave);
-    if (lane >= off) incl += up;
-  }
-  total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
-  return incl - v;
 }
 
 template <bool BATCH, int PREC, int MODEL>

@@ -140,13 +140,14 @@ class System:
     def get_shape(self) -> dict:
         sh = L.Shape()
         L.check(self._lib.dpde_get_shape(self.h, C.byref(sh)))
-        return {"pair_block": sh.pair_block, "aux_block": sh.aux_block, "pairs": sh.pairs}
+        return {"pair_block": sh.pair_block, "aux_block": sh.aux_block, "pairs": sh.pairs,
+                "order_block": sh.order_block}
 
-    def set_shape(self, pair_block=None, aux_block=None, pairs=None):
+    def set_shape(self, pair_block=None, aux_block=None, pairs=None, order_block=None):
         cur = self.get_shape()
-        sh = L.Shape(int(pair_block if pair_block is not None else cur["pair_block"]),
-                     int(aux_block if aux_block is not None else cur["aux_block"]),
-                     int(pairs if pairs is not None else cur["pairs"]), 0)
+        pick = lambda v, k: int(v if v is not None else cur[k])
+        sh = L.Shape(pick(pair_block, "pair_block"), pick(aux_block, "aux_block"),
+                     pick(pairs, "pairs"), pick(order_block, "order_block"))
         L.check(self._lib.dpde_set_shape(self.h, C.byref(sh)))
 
     def autotune(self, steps: int = 20):

@@ -305,6 +305,40 @@ def test_batched_replicas_match_single_systems(dp):
     b.close()
 
 
+def test_batched_256_replicas_one_step_vs_oracle(dp):
+    """The batched workload itself (256 replicas, sizes uniform in
+    [500, 8000] at density 3, one seed per replica, dt = 0.01): after 3 steps
+    of the whole batch, one more batched step matches the oracle's step of the
+    smallest, the largest and the median-size replica from the same state at
+    1e-12 (Sec. 3.2.1: every replica is an independent system)."""
+    sizes, seeds = W.replica_sizes(256, 500, 8000, seed=20260103)
+    cfgs, qs, ps, es = [], [], [], []
+    for r, (nr, sd) in enumerate(zip(sizes, seeds)):
+        L = W.cubic_side(int(nr))
+        q, p, e = W.equilibrium_state(int(nr), [L] * 3, seed=30000 + r)
+        cfgs.append(dp.Config(n=int(nr), box=[L] * 3, dt=0.01, seed=int(sd), replica=r))
+        qs.append(q); ps.append(p); es.append(e)
+    b = dp.System(cfgs, np.concatenate(qs), np.concatenate(ps), np.concatenate(es))
+    b.step(3)
+    qb, pb, eb, st = _gpu_state(b)
+    b.step(1)
+    q1, p1, e1, _ = _gpu_state(b)
+    b.close()
+    order = np.argsort(sizes, kind="stable")
+    for r in (int(order[0]), int(order[-1]), int(order[len(order) // 2])):
+        lo, hi = b.offsets[r], b.offsets[r + 1]
+        n, L = int(sizes[r]), W.cubic_side(int(sizes[r]))
+        S = O.State(O.make_params(n, [L] * 3, dt=0.01, seed=int(seeds[r]), replica=r, step=st),
+                    qb[lo:hi], pb[lo:hi], eb[lo:hi])
+        rc, _ = S.step(1)
+        assert rc == 0
+        dq = q1[lo:hi] - S.q
+        dq -= L * np.rint(dq / L)
+        assert np.abs(dq).max() / L < 1e-12, (r, n)
+        assert np.abs(p1[lo:hi] - S.p).max() < 1e-12, (r, n)
+        assert np.abs(e1[lo:hi] - S.eps).max() / np.abs(S.eps).mean() < 1e-12, (r, n)
+
+
 def test_graph_replay_equals_eager(dp):
     n = 5000
     L = W.cubic_side(n)

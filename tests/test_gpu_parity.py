@@ -423,7 +423,7 @@ def test_pair_forms_agree(dp, case):
             L.check(lib.dpde_init(C.byref(P), C.c_void_p(qd.data_ptr()),
                                   C.c_void_p(pd.data_ptr()), C.c_void_p(ed.data_ptr()), None,
                                   C.byref(h)))
-            sh = L.Shape(256, 256, pairs, 0)
+            sh = L.Shape(256, 256, pairs, 1)
             L.check(lib.dpde_set_shape(h, C.byref(sh)))
             L.check(lib.dpde_step(h, steps))
             qo, po, eo = torch.empty_like(qd), torch.empty_like(pd), torch.empty_like(ed)
@@ -456,6 +456,55 @@ def test_pair_forms_agree_batched(dp):
     ee = np.abs(sa[2] - sb[2]).max() / np.abs(sa[2]).mean()
     assert max(ep, ee) < 1e-12, (ep, ee)
     assert np.allclose(ha[:, :, :4], hb[:, :, :4], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("pairs", [0, 1])
+def test_cell_block_order_leaves_trajectory_unchanged(dp, pairs):
+    """The memory order of the cells (row-major, or blocks of 2^3, 3^3, 5^3
+    cells, the blocks at the high faces cut short) changes which particles
+    share a tile and a cache line, not the result: the pair set is the
+    stencil's and every per-particle sum is order independent, so the states
+    after 6 steps are equal bit for bit.  Uneven batched replicas, one with a
+    free x boundary and cell counts that no block edge divides."""
+    sizes = [1517, 3203, 900]
+    cfgs, qs, ps, es = [], [], [], []
+    for r, nr in enumerate(sizes):
+        L = W.cubic_side(nr)
+        box, per = [L] * 3, [1, 1, 1]
+        if r == 1:
+            box, per = [2.2 * L, L / 1.45, L / 1.5], [0, 1, 1]
+        q, p, e = W.equilibrium_state(nr, box, seed=900 + r)
+        cfgs.append(_cfg(dp, nr, box, periodic=per, seed=21 + r, replica=r))
+        qs.append(q); ps.append(p); es.append(e)
+    q, p, e = np.vstack(qs), np.vstack(ps), np.concatenate(es)
+    ref = None
+    for ob in (1, 2, 3, 5):
+        s = dp.System(cfgs, q, p, e)
+        s.set_shape(pairs=pairs, order_block=ob)
+        assert s.get_shape()["order_block"] == ob
+        s.step(3)
+        s.set_shape(order_block=1 + ob % 3)  # a change of order mid-run
+        s.step(3)
+        out = _gpu_state(s), s.history()
+        s.close()
+        if ref is None:
+            ref = out
+            continue
+        for a, b in zip(ref[0][:3], out[0][:3]):
+            assert np.array_equal(a, b), ob
+        assert np.array_equal(ref[1], out[1]), ob
+
+
+def test_invalid_order_block_rejected(dp):
+    n = 1000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=86)
+    s = dp.System(_cfg(dp, n, [L] * 3), q, p, e)
+    for ob in (0, 9, -1):
+        with pytest.raises(RuntimeError):
+            s.set_shape(order_block=ob)
+    assert s.get_shape()["order_block"] == 1
+    s.close()
 
 
 def test_pair_term_range_is_reported(dp):

@@ -61,7 +61,43 @@ def test_kinetic_and_internal_temperatures_agree():
     se = math.hypot(tk.std(ddof=1), ti.std(ddof=1)) / math.sqrt(10)
     # weak order 1: the two estimators differ by O(dt); allow 5 se + 1 %
     assert abs(tk.mean() - ti.mean()) < 5 * se + 0.01 * ti.mean(), (tk.mean(), ti.mean())
-    # internal-energy marginal Gamma(C_v + 1, T): <eps> = (C_v + 1) T_int
+
+
+def test_internal_energy_marginal_is_gamma():
+    """The invariant measure (Sec. 2.1, eq. DPDE_invariant_measure_general)
+    with the linear EOS has entropy s(eps) = C_v ln eps, so the marginal of
+    each eps_i has density eps^C_v exp(-eps/T): a Gamma law of shape C_v + 1
+    and scale T.  Then <eps> = (C_v + 1) T and <1/eps> = 1/(C_v T): the mean
+    of eps over T_int = N / sum(C_v/eps_i) is C_v + 1 (C_v for a sharp law),
+    and Var(eps)/<eps>^2 = 1/(C_v + 1).  Started from that law at T = 1
+    (N = 65,536, C_v = 100, dt = 0.005), the dynamics keeps it; started from
+    the sharp eps_i = C_v, the ratio climbs toward C_v + 1 (its relaxation
+    time is ~20 time units)."""
+    import paper_1507_06643_amd as dp
+    n, dt, cv = 65536, 0.005, 100.0
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=78, eps0=cv)
+    eg = np.random.default_rng(79).gamma(cv + 1.0, 1.0, size=n)
+    ratios = {}
+    for name, e0 in (("gamma", eg), ("sharp", e)):
+        s = dp.System(dp.Config(n=n, box=[L] * 3, dt=dt, seed=6, cv=cv), q, p, e0)
+        s.step(1000)
+        s.history()
+        s.step(2000)
+        h = s.history()
+        eps = s.get_state()[2].cpu().numpy()
+        s.close()
+        ratios[name] = (h[:, 2] / n / h[:, 8]).reshape(10, -1).mean(1)
+        if name == "gamma":
+            # the stationary law: within a fifth of the 1 that tells C_v + 1
+            # from C_v, and the relative variance of the final eps_i within 5 %
+            # (its sampling error over 65,536 particles is below 1 %)
+            assert abs(ratios[name].mean() - (cv + 1.0)) < 0.2, ratios[name]
+            rv = eps.var() / eps.mean() ** 2
+            assert abs(rv * (cv + 1.0) - 1.0) < 0.05, rv * (cv + 1.0)
+    # from the sharp start: rising through the run, still below C_v + 1
+    r = ratios["sharp"]
+    assert r[0] > cv + 0.1 and np.all(np.diff(r) > 0) and r[-1] < cv + 1.0 + 0.2, r
 
 
 def test_lj_temperature_estimators_agree():
