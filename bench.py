@@ -340,7 +340,8 @@ def batched_leg(dp, W, nrep=256, steps=2000, graph_steps=100, tune_steps=10):
         cfgs.append(dp.Config(n=int(nr), box=[L] * 3, dt=0.01, seed=int(sd), replica=r))
         qs.append(q); ps.append(p); es.append(e)
     s = dp.System(cfgs, np.concatenate(qs), np.concatenate(ps), np.concatenate(es))
-    pb, ab, tune_ms = s.autotune(tune_steps)
+    _, _, tune_ms = s.autotune(tune_steps)
+    shape = s.get_shape()
     s.step_graph(graph_steps, 1)  # capture and warm up
     s.history()
     torch.cuda.synchronize()
@@ -357,7 +358,7 @@ def batched_leg(dp, W, nrep=256, steps=2000, graph_steps=100, tune_steps=10):
                         f"{graph_steps}-step graph, FP64",
             "value": ntot * steps / secs, "unit": "particle-steps/s",
             "ms_per_step": 1e3 * secs / steps,
-            "autotuned": {"pair_block": pb, "aux_block": ab, "trial_ms_per_step": tune_ms},
+            "autotuned": {"shape": shape, "trial_ms_per_step": tune_ms},
             "drift_per_1e4": [float(drifts.mean()), float(drifts.std(ddof=1) / np.sqrt(nrep))]}
 
 
@@ -511,6 +512,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--tuning-table",
+                    default=os.path.join(ROOT, "paper_1507_06643_amd", "tuning_gfx950.txt"),
+                    help="launch-shape table loaded before any system is made (if present)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default block sizes (profiling runs: no tuning trials)")
     ap.add_argument("--profile-steps", type=int, default=10)
@@ -558,6 +562,9 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    table = args.tuning_table if args.tuning_table and os.path.exists(args.tuning_table) else None
+    if table:
+        dp.tuning_load(table)
     if args.next_row:
         print(json.dumps(next_rows_leg(dp, W, only=args.next_row)), flush=True)
         return
@@ -574,11 +581,10 @@ def main():
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"[bench] surrogate trained in {t_train:.2f} s, final loss {curve[-1]:.3e}")
-    if args.no_autotune:
-        pb, ab = 256, 256
-    else:
-        pb, ab, _ = sysm.autotune(20)
-    log(f"[bench] blocks: pair {pb}, per-particle {ab}")
+    if not args.no_autotune:
+        sysm.autotune(20)
+    shape = sysm.get_shape()
+    log(f"[bench] launch shape: {shape} ({'autotuned' if not args.no_autotune else 'table' if table else 'default'})")
     graph_len = max(2, min(100, args.steps - args.steps % 2))
     log(f"[bench] timing {args.steps} steps ({graph_len}-step graph replays) after "
         f"{args.warmup} warm-up")
@@ -651,7 +657,8 @@ def main():
                    "n": n, "dt": dt, "precision": "fp64", "theta": "mlp+newton-fallback",
                    "skin": cfg.skin, "list_builds_per_step": builds_per_step,
                    "execution": f"replays of a captured {graph_len}-step graph",
-                   "blocks": [pb, ab], "autotuned": not args.no_autotune},
+                   "shape": shape, "autotuned": not args.no_autotune,
+                   "tuning_table": os.path.relpath(table, ROOT) if table else None},
         "eager_ms_per_step": eager_ms,
         "roofline": roof,
         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in prof.items()},

@@ -47,6 +47,7 @@ extern "C" {
 #define DPDE_ENONFINITE (-8) /* a non-finite value appeared in the state          */
 #define DPDE_ERANGE (-9)     /* a pair term outside the fixed-point range of the  */
                              /* SER sums (|dp_ij| or |e_ij| >= 32 in one step)    */
+#define DPDE_EIO (-10)       /* a tuning-table file could not be read or written  */
 
 /* Precision of the pair terms. */
 #define DPDE_FP64 0          /* everything in FP64                                */
@@ -295,15 +296,44 @@ typedef struct dpde_shape {
 int dpde_get_shape(dpde_handle* h, dpde_shape* out);
 int dpde_set_shape(dpde_handle* h, const dpde_shape* shape);
 
-/* Autotuner: time every candidate (pair-kernel block of 64/128/256 threads x
- * per-particle block of 128/256/512) over `steps` steps of this system and keep
- * the fastest (applied as by dpde_set_tuning; *ms_per_step = its time).  The
+/* Autotuner: time every launch shape over `steps` steps of this system and
+ * keep the fastest.  The candidates are the pair form (both forms where the
+ * tile form applies), the cell order (order_block 1..4), the lane-group
+ * block (64/128/256 threads: the list build and the both-sides passes) and
+ * the per-particle block (128/256/512).  The winner is applied as by
+ * dpde_set_shape, its pair and per-particle blocks and time per step are
+ * returned (read the full shape with dpde_get_shape), and it is recorded in
+ * the process's tuning table (below) for this system's size class.  The
  * state, step, list-build count and history are restored after every trial,
- * and results do not depend on the block sizes, so tuning leaves the
- * trajectory unchanged.  Allocates a snapshot (state and history) for the
- * duration of the call.  Not for use during graph capture. */
+ * so the run continues from where it was, as it would under the chosen shape
+ * (block sizes and cell order change no bit; the two pair forms agree to
+ * rounding).  Allocates a snapshot (state and history) for the duration of
+ * the call.  Not for use during graph capture. */
 int dpde_autotune(dpde_handle* h, int32_t steps, int32_t* pair_block, int32_t* aux_block,
                   double* ms_per_step);
+
+/*
+ * Tuning table: launch shapes by size class, kept by the library for the
+ * life of the process.  The key is (floor(log2 N), replica class, precision)
+ * with N the particles of the handle and replica class 0 for one system,
+ * 1 + floor(log2 nrep) for nrep >= 2 replicas.  dpde_autotune records its
+ * winner; dpde_init and dpde_init_batch start a handle with the recorded
+ * shape of its class, if any (the pair form applies where the tile form is
+ * available).  The table persists through a text file, one entry per line:
+ *   nclass rclass precision pair_block aux_block pairs order_block ms_per_step
+ * ('#' starts a comment line).  dpde_tuning_load merges a file into the
+ * table (an entry replaces one of the same key) and fails with DPDE_EIO if
+ * the file cannot be opened or a line does not parse, DPDE_EINVAL if a shape
+ * is out of range (the table is then unchanged).  dpde_tuning_save writes
+ * the table (DPDE_EIO on failure).  dpde_tuning_lookup gives the entry for
+ * (n, nrep, precision): *found = 1 and the shape and time, or *found = 0.
+ * Host-only calls: they need no device.
+ */
+int dpde_tuning_load(const char* path);
+int dpde_tuning_save(const char* path);
+int dpde_tuning_clear(void);
+int dpde_tuning_lookup(int64_t n, int32_t nrep, int32_t precision, dpde_shape* shape,
+                       double* ms_per_step, int32_t* found);
 
 /*
  * Per-kernel timing: when enabled, every kernel launch of dpde_step is

@@ -16,9 +16,11 @@ from ._lib import (DpdeError, EOS_EINSTEIN, EOS_LINEAR, FP32, FP64, MODEL_PROJEC
 
 _lib.load()
 
-from .system import Config, System, debug_rng  # noqa: E402
+from .system import (Config, System, debug_rng, tuning_clear, tuning_load,  # noqa: E402
+                     tuning_lookup, tuning_save)
 
 __all__ = ["Config", "System", "debug_rng", "DpdeError", "FP32", "FP64", "EOS_LINEAR",
            "MODEL_VECTOR", "MODEL_PROJECTED", "POT_SOFT", "POT_LJ",
            "EOS_EINSTEIN", "THETA_NEWTON", "THETA_MLP", "THETA_MLP_NEWTON", "SCHEME_SER",
-           "SCHEME_SEM", "PAIRS_BOTH_SIDES", "PAIRS_ONCE_PER_TILE"]
+           "SCHEME_SEM", "PAIRS_BOTH_SIDES", "PAIRS_ONCE_PER_TILE", "tuning_load",
+           "tuning_save", "tuning_clear", "tuning_lookup"]

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libdpde.so")
 DPDE_OK, DPDE_EINVAL, DPDE_EBOX, DPDE_ENOMEM, DPDE_EHIP = 0, -1, -2, -3, -4
 DPDE_ENEG_EINT, DPDE_EEOS, DPDE_EOVERFLOW, DPDE_ENONFINITE = -5, -6, -7, -8
 DPDE_ERANGE = -9
+DPDE_EIO = -10
 FP64, FP32 = 0, 1
 EOS_LINEAR, EOS_EINSTEIN = 0, 1
 THETA_NEWTON, THETA_MLP, THETA_MLP_NEWTON = 0, 1, 2
@@ -30,7 +31,7 @@ ERROR_NAMES = {
     DPDE_EINVAL: "DPDE_EINVAL", DPDE_EBOX: "DPDE_EBOX", DPDE_ENOMEM: "DPDE_ENOMEM",
     DPDE_EHIP: "DPDE_EHIP", DPDE_ENEG_EINT: "DPDE_ENEG_EINT", DPDE_EEOS: "DPDE_EEOS",
     DPDE_EOVERFLOW: "DPDE_EOVERFLOW", DPDE_ENONFINITE: "DPDE_ENONFINITE",
-    DPDE_ERANGE: "DPDE_ERANGE",
+    DPDE_ERANGE: "DPDE_ERANGE", DPDE_EIO: "DPDE_EIO",
 }
 
 
@@ -104,6 +105,11 @@ SIGNATURES = [
     ("dpde_get_shape", C.c_int, [_vp, C.POINTER(Shape)]),
     ("dpde_set_shape", C.c_int, [_vp, C.POINTER(Shape)]),
     ("dpde_autotune", C.c_int, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i32), _dp]),
+    ("dpde_tuning_load", C.c_int, [C.c_char_p]),
+    ("dpde_tuning_save", C.c_int, [C.c_char_p]),
+    ("dpde_tuning_clear", C.c_int, []),
+    ("dpde_tuning_lookup", C.c_int, [_i64, _i32, _i32, C.POINTER(Shape), _dp,
+                                     C.POINTER(_i32)]),
     ("dpde_profile_enable", C.c_int, [_vp, _i32]),
     ("dpde_profile_read", C.c_int, [_vp, C.c_char_p, _dp, C.POINTER(_i64), _i32]),
     ("dpde_theta", C.c_int, [_vp, _vp, _vp, _vp, _i64, _i32]),

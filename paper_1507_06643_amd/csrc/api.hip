@@ -749,6 +749,69 @@ void release(dpde_handle* h) {
   delete h;
 }
 
+// ---- tuning table -----------------------------------------------------------
+struct TuneKey {
+  int nclass, rclass, precision;
+  bool operator<(const TuneKey& o) const {
+    if (nclass != o.nclass) return nclass < o.nclass;
+    if (rclass != o.rclass) return rclass < o.rclass;
+    return precision < o.precision;
+  }
+};
+struct TuneEntry {
+  dpde_shape shape;
+  double ms;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+
+int floor_log2(int64_t v) {
+  int k = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++k;
+  }
+  return k;
+}
+
+TuneKey tune_key(int64_t n, int32_t nrep, int32_t precision) {
+  return TuneKey{floor_log2(n), nrep <= 1 ? 0 : 1 + floor_log2(nrep), precision};
+}
+
+bool shape_valid(const dpde_shape& sh) {
+  auto ok = [](int b, int mx) { return b >= 64 && b <= mx && (b % 64) == 0; };
+  return ok(sh.pair_block, kPairBlockMax) && ok(sh.aux_block, kAuxMaxThreads) &&
+         (sh.pairs == DPDE_PAIRS_BOTH_SIDES || sh.pairs == DPDE_PAIRS_ONCE_PER_TILE) &&
+         sh.order_block >= 1 && sh.order_block <= kOrderBlockMax;
+}
+
+// Shape fields of the handle (host side; the caller uploads the geometry
+// and rebuilds the lists where the order or the form changed).
+void put_shape(dpde_handle* h, const dpde_shape& sh) {
+  h->pair_block = sh.pair_block;
+  h->aux_block = sh.aux_block;
+  h->pairs_once = sh.pairs == DPDE_PAIRS_ONCE_PER_TILE;
+  for (Geo& g : h->geo_h) g.oblk = sh.order_block;
+  if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
+  if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+}
+
+dpde_shape get_shape(const dpde_handle* h) {
+  dpde_shape sh;
+  sh.pair_block = h->pair_block;
+  sh.aux_block = h->aux_block;
+  sh.pairs = h->pairs_once ? DPDE_PAIRS_ONCE_PER_TILE : DPDE_PAIRS_BOTH_SIDES;
+  sh.order_block = h->geo_h[0].oblk;
+  return sh;
+}
+
+int upload_geo(dpde_handle* h) {
+  HIPCHK(hipMemcpyAsync(h->geo, h->geo_h.data(), h->nrep * sizeof(Geo), hipMemcpyHostToDevice,
+                        h->stream));
+  return DPDE_OK;
+}
+
+
 int create(const dpde_params* params, int nrep, const int64_t* offsets, const double* q,
            const double* p, const double* eps, void* stream, dpde_handle** out) {
   if (!out) return fail(DPDE_EINVAL, "out is NULL");
@@ -801,6 +864,11 @@ int create(const dpde_params* params, int nrep, const int64_t* offsets, const do
   h->n = h->offsets[nrep];
   h->ncells = cells;
   h->hybrid = params[0].scheme == DPDE_SCHEME_HYBRID;
+  {  // a shape tuned earlier in this process (or loaded) for this size class
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(h->n, nrep, params[0].precision));
+    if (it != g_tune.end()) put_shape(h, it->second.shape);
+  }
   if (cells >= ((int64_t)1 << 31)) { release(h); return fail(DPDE_EINVAL, "too many cells"); }
   if (h->ndoms >= ((int64_t)1 << 31) / 2) { release(h); return fail(DPDE_EINVAL, "too many domains"); }
   if (hipGetDevice(&h->device) != hipSuccess) { release(h); return fail(DPDE_EHIP, "no HIP device"); }
@@ -1013,24 +1081,89 @@ int dpde_forces(dpde_handle* h, double* F, double* U) {
   return DPDE_OK;
 }
 
+int dpde_tuning_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  return DPDE_OK;
+}
+
+int dpde_tuning_lookup(int64_t n, int32_t nrep, int32_t precision, dpde_shape* shape,
+                       double* ms_per_step, int32_t* found) {
+  if (!found) return fail(DPDE_EINVAL, "found is NULL");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(tune_key(n, nrep, precision));
+  *found = it != g_tune.end();
+  if (*found) {
+    if (shape) *shape = it->second.shape;
+    if (ms_per_step) *ms_per_step = it->second.ms;
+  }
+  return DPDE_OK;
+}
+
+int dpde_tuning_save(const char* path) {
+  if (!path) return fail(DPDE_EINVAL, "path is NULL");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(DPDE_EIO, "cannot write %s", path);
+  std::fprintf(f, "# nclass rclass precision pair_block aux_block pairs order_block ms_per_step\n");
+  for (const auto& kv : g_tune)
+    std::fprintf(f, "%d %d %d %d %d %d %d %.6f\n", kv.first.nclass, kv.first.rclass,
+                 kv.first.precision, kv.second.shape.pair_block, kv.second.shape.aux_block,
+                 kv.second.shape.pairs, kv.second.shape.order_block, kv.second.ms);
+  const bool bad = std::ferror(f) != 0;
+  if (std::fclose(f) != 0 || bad) return fail(DPDE_EIO, "cannot write %s", path);
+  return DPDE_OK;
+}
+
+int dpde_tuning_load(const char* path) {
+  if (!path) return fail(DPDE_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(DPDE_EIO, "cannot read %s", path);
+  std::map<TuneKey, TuneEntry> got;
+  char line[512];
+  int lineno = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    ++lineno;
+    const char* c = line;
+    while (*c == ' ' || *c == '\t') ++c;
+    if (*c == '#' || *c == '\n' || *c == '\0') continue;
+    TuneKey k{};
+    TuneEntry e{};
+    char tail = 0;
+    const int m = std::sscanf(c, "%d %d %d %d %d %d %d %lf %c", &k.nclass, &k.rclass,
+                              &k.precision, &e.shape.pair_block, &e.shape.aux_block,
+                              &e.shape.pairs, &e.shape.order_block, &e.ms, &tail);
+    if (m != 8) {
+      std::fclose(f);
+      return fail(DPDE_EIO, "%s:%d: expected 8 fields", path, lineno);
+    }
+    if (!shape_valid(e.shape) || k.nclass < 0 || k.nclass > 62 || k.rclass < 0 ||
+        (k.precision != DPDE_FP64 && k.precision != DPDE_FP32)) {
+      std::fclose(f);
+      return fail(DPDE_EINVAL, "%s:%d: entry out of range", path, lineno);
+    }
+    got[k] = e;
+  }
+  std::fclose(f);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : got) g_tune[kv.first] = kv.second;
+  return DPDE_OK;
+}
+
 int dpde_set_tuning(dpde_handle* h, int32_t pair_block, int32_t aux_block) {
   if (!h) return fail(DPDE_EINVAL, "handle is NULL");
-  auto ok = [](int b, int mx) { return b >= 64 && b <= mx && (b % 64) == 0; };
-  if (!ok(pair_block, kPairBlockMax) || !ok(aux_block, kAuxMaxThreads))
+  dpde_shape sh = get_shape(h);
+  sh.pair_block = pair_block;
+  sh.aux_block = aux_block;
+  if (!shape_valid(sh))
     return fail(DPDE_EINVAL, "block sizes must be multiples of 64 within the kernel limits");
-  h->pair_block = pair_block;
-  h->aux_block = aux_block;
-  if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
-  if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+  put_shape(h, sh);
   return DPDE_OK;
 }
 
 int dpde_get_shape(dpde_handle* h, dpde_shape* out) {
   if (!h || !out) return fail(DPDE_EINVAL, "NULL argument");
-  out->pair_block = h->pair_block;
-  out->aux_block = h->aux_block;
-  out->pairs = h->pairs_once ? DPDE_PAIRS_ONCE_PER_TILE : DPDE_PAIRS_BOTH_SIDES;
-  out->order_block = h->geo_h[0].oblk;
+  *out = get_shape(h);
   return DPDE_OK;
 }
 
@@ -1041,24 +1174,17 @@ int dpde_set_shape(dpde_handle* h, const dpde_shape* shape) {
   if (shape->order_block < 1 || shape->order_block > kOrderBlockMax)
     return fail(DPDE_EINVAL, "order_block must be in [1, %d], got %d", kOrderBlockMax,
                 shape->order_block);
-  const bool once0 = h->pairs_once;
-  h->pairs_once = shape->pairs == DPDE_PAIRS_ONCE_PER_TILE;
-  int rc = dpde_set_tuning(h, shape->pair_block, shape->aux_block);
-  if (rc) {
-    h->pairs_once = once0;
-    return rc;
-  }
-  const bool reorder = shape->order_block != h->geo_h[0].oblk;
-  if (reorder) {
-    for (Geo& g : h->geo_h) g.oblk = shape->order_block;
-    HIPCHK(hipMemcpyAsync(h->geo, h->geo_h.data(), h->nrep * sizeof(Geo), hipMemcpyHostToDevice,
-                          h->stream));
-  }
+  if (!shape_valid(*shape))
+    return fail(DPDE_EINVAL, "block sizes must be multiples of 64 within the kernel limits");
+  const dpde_shape cur = get_shape(h);
+  put_shape(h, *shape);
   // the order and the lists follow the shape: rebuild them and the forces
   // from the current positions (no kick)
-  if (once0 != h->pairs_once || reorder) {
+  if (cur.pairs != shape->pairs || cur.order_block != shape->order_block) {
     static const BuildCtl forced{0ull, 1u, 0u, 0ull};
     static const BuildCtl cleared{0ull, 0u, 0u, 0ull};
+    int rc = upload_geo(h);
+    if (rc) return rc;
     HIPCHK(hipMemcpyAsync(h->ctl, &forced, sizeof(BuildCtl), hipMemcpyHostToDevice, h->stream));
     enqueue_bin(h, 0);
     enqueue_forces(h, 0);
@@ -1116,53 +1242,65 @@ int dpde_autotune(dpde_handle* h, int32_t steps, int32_t* pair_block, int32_t* a
       return fail(DPDE_EHIP, "autotune restore copy failed");
     return DPDE_OK;
   };
-  static const int32_t kPair[] = {64, 128, 256};
-  static const int32_t kAux[] = {128, 256, 512};
-  const int32_t pb0 = h->pair_block, ab0 = h->aux_block;
-  int32_t best_pb = pb0, best_ab = ab0;
+  // candidates: the pair form where the tile form applies, the cell order,
+  // the lane-group and per-particle blocks
+  const dpde_shape sh0 = get_shape(h);
+  std::vector<dpde_shape> cands;
+  const bool two_forms = [&] {
+    const bool keep = h->pairs_once;
+    h->pairs_once = true;
+    const bool u = uniq_form(h);
+    h->pairs_once = keep;
+    return u;
+  }();
+  for (int form : {DPDE_PAIRS_ONCE_PER_TILE, DPDE_PAIRS_BOTH_SIDES}) {
+    if (!two_forms && form != sh0.pairs) continue;
+    for (int ob = 1; ob <= 4; ++ob)
+      for (int pb : {64, 128, 256})
+        for (int ab : {128, 256, 512}) cands.push_back(dpde_shape{pb, ab, form, ob});
+  }
+  dpde_shape best_sh = sh0;
   double best = 1e300;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (!rc && (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess))
     rc = fail(DPDE_EHIP, "autotune event creation failed");
-  for (int32_t pb : kPair) {
-    for (int32_t ab : kAux) {
-      if (rc) break;
-      h->pair_block = pb;
-      h->aux_block = ab;
-      enqueue_step(h);  // warm-up (first launch of this shape)
-      (void)hipEventRecord(t0, h->stream);
-      for (int32_t s = 0; s < steps; ++s) enqueue_step(h);
-      (void)hipEventRecord(t1, h->stream);
-      if (hipEventSynchronize(t1) != hipSuccess) {
-        rc = fail(DPDE_EHIP, "autotune timing failed");
-        break;
-      }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, t0, t1);
-      rc = read_status(h);
-      if (rc) break;
-      if (ms / steps < best) {
-        best = ms / steps;
-        best_pb = pb;
-        best_ab = ab;
-      }
-      rc = restore();
+  for (const dpde_shape& sh : cands) {
+    if (rc) break;
+    // the shape, then the snapshot state binned and listed under it
+    put_shape(h, sh);
+    if ((rc = upload_geo(h)) || (rc = restore())) break;
+    enqueue_step(h);  // warm-up (first launch of this shape)
+    (void)hipEventRecord(t0, h->stream);
+    for (int32_t st = 0; st < steps; ++st) enqueue_step(h);
+    (void)hipEventRecord(t1, h->stream);
+    if (hipEventSynchronize(t1) != hipSuccess) {
+      rc = fail(DPDE_EHIP, "autotune timing failed");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    rc = read_status(h);
+    if (rc) break;
+    if (ms / steps < best) {
+      best = ms / steps;
+      best_sh = sh;
     }
   }
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
-  if (rc) {
-    h->pair_block = pb0;
-    h->aux_block = ab0;
-    (void)restore();
-    cleanup();
-    return rc;
-  }
+  // the winner (or, after a failure, the original shape) on the snapshot
+  put_shape(h, rc ? sh0 : best_sh);
+  int rc2 = upload_geo(h);
+  if (!rc2) rc2 = restore();
   cleanup();
-  rc = dpde_set_tuning(h, best_pb, best_ab);
   if (rc) return rc;
-  if (pair_block) *pair_block = best_pb;
-  if (aux_block) *aux_block = best_ab;
+  if (rc2) return rc2;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(h->n, h->nrep, h->phys.precision)] = TuneEntry{best_sh, best};
+  }
+  if (pair_block) *pair_block = best_sh.pair_block;
+  if (aux_block) *aux_block = best_sh.aux_block;
   if (ms_per_step) *ms_per_step = best;
   return DPDE_OK;
 }

@@ -6,6 +6,7 @@ structures); all arithmetic of the method runs in the HIP kernels.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from dataclasses import dataclass, field
 from typing import Optional, Sequence
 
@@ -151,7 +152,9 @@ class System:
         L.check(self._lib.dpde_set_shape(self.h, C.byref(sh)))
 
     def autotune(self, steps: int = 20):
-        """Pick the fastest block sizes (state restored); returns (pair, aux, ms/step)."""
+        """Pick the fastest launch shape (state restored) and record it in the
+        library's tuning table; returns (pair block, aux block, ms/step) (the
+        full shape: get_shape())."""
         pb, ab, ms = C.c_int32(0), C.c_int32(0), C.c_double(0.0)
         L.check(self._lib.dpde_autotune(self.h, int(steps), C.byref(pb), C.byref(ab), C.byref(ms)))
         return pb.value, ab.value, ms.value
@@ -327,3 +330,30 @@ def debug_rng(seed: int, replica: int, step: int, lo, hi):
     L.check(lib.dpde_debug_rng(int(seed) & (2**64 - 1), int(replica), int(step), _ptr(lo_d),
                                _ptr(hi_d), n, _ptr(raw), _ptr(g), _ptr(g32)))
     return (raw.cpu().numpy().view(np.uint32), g.cpu().numpy(), g32.cpu().numpy())
+
+
+def tuning_load(path: str) -> None:
+    """Merge a tuning-table file into the library's table."""
+    lib = L.load()
+    L.check(lib.dpde_tuning_load(os.fsencode(path)))
+
+
+def tuning_save(path: str) -> None:
+    """Write the library's tuning table."""
+    lib = L.load()
+    L.check(lib.dpde_tuning_save(os.fsencode(path)))
+
+
+def tuning_clear() -> None:
+    L.check(L.load().dpde_tuning_clear())
+
+
+def tuning_lookup(n: int, nrep: int, precision: int):
+    """The recorded shape for this size class, as (shape dict, ms/step), or None."""
+    sh, ms, found = L.Shape(), C.c_double(0.0), C.c_int32(0)
+    L.check(L.load().dpde_tuning_lookup(int(n), int(nrep), int(precision), C.byref(sh),
+                                        C.byref(ms), C.byref(found)))
+    if not found.value:
+        return None
+    return ({"pair_block": sh.pair_block, "aux_block": sh.aux_block, "pairs": sh.pairs,
+             "order_block": sh.order_block}, ms.value)

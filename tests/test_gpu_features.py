@@ -509,6 +509,10 @@ def test_autotune_leaves_trajectory_unchanged(dp):
     assert pb in (64, 128, 256) and ab in (128, 256, 512) and ms > 0
     assert b.list_builds() == builds
     assert b.history().shape[0] == 0  # trial records were rolled back
+    # the tuned handle continues as an untuned one given the same shape (the
+    # block sizes and the cell order change no bit; the pair forms agree to
+    # rounding, so the reference takes the winner's form)
+    a.set_shape(**b.get_shape())
     a.step(25)
     b.step(25)
     sa, sb = a.get_state(), b.get_state()
@@ -518,6 +522,39 @@ def test_autotune_leaves_trajectory_unchanged(dp):
     assert np.array_equal(a.history(), b.history())
     a.close()
     b.close()
+    dp.tuning_clear()  # later handles of this size class start from the defaults
+
+
+def test_autotune_records_the_shape_of_the_size_class(dp, tmp_path):
+    """The winner goes into the library's tuning table under (size class,
+    replica class, precision); a new handle of that class starts with it, and
+    the table survives a save / clear / load round trip."""
+    n = 5000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=92)
+    dp.tuning_clear()
+    try:
+        s = dp.System(dp.Config(n=n, box=[L] * 3, precision=dp.FP32), q, p, e)
+        s.autotune(2)
+        sh = s.get_shape()
+        s.close()
+        got = dp.tuning_lookup(n, 1, dp.FP32)
+        assert got is not None and got[0] == sh and got[1] > 0
+        assert dp.tuning_lookup(n, 1, dp.FP64) is None
+        assert dp.tuning_lookup(2 * 4096, 1, dp.FP32) is None  # the next size class
+        s2 = dp.System(dp.Config(n=n + 100, box=[W.cubic_side(n + 100)] * 3,
+                                 precision=dp.FP32), *W.equilibrium_state(
+                                     n + 100, [W.cubic_side(n + 100)] * 3, seed=93))
+        assert s2.get_shape() == sh
+        s2.close()
+        path = str(tmp_path / "tuning.txt")
+        dp.tuning_save(path)
+        dp.tuning_clear()
+        assert dp.tuning_lookup(n, 1, dp.FP32) is None
+        dp.tuning_load(path)
+        assert dp.tuning_lookup(n, 1, dp.FP32)[0] == sh
+    finally:
+        dp.tuning_clear()
 
 
 def torch_equal(x, y):
