@@ -906,7 +906,7 @@ constexpr int kTileListLds = 32;  // work-list entries per particle staged in LD
 constexpr int kTileSkinLds = 32;  // skin-list entries per particle staged in LDS
 
 template <bool BATCH, int PREC>
-__global__ __launch_bounds__(kSub * kUniqTile) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_pass_a_uniq(
+__global__ __launch_bounds__(kSub * kUniqTile) __attribute__((amdgpu_waves_per_eu(BATCH ? 4 : 6, 8))) void k_pass_a_uniq(
     PState s, int64_t n, const Geo* __restrict__ geo, Phys P, int mode,
     double* __restrict__ Fx, double* __restrict__ Fy, double* __restrict__ Fz,
     double* __restrict__ Ui, double* __restrict__ Li, SkinList sl, NList nl, uint32_t* status) {
