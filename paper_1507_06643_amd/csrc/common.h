@@ -269,10 +269,12 @@ __device__ __forceinline__ double wrap_coord(double x, double L) {
   return x;
 }
 
+// d - L if d > L/2, d + L if d < -L/2, else d (selects, no branches: the
+// lanes of a wave take different cases)
 __device__ __forceinline__ double min_image(double d, double L, double halfL) {
-  if (d > halfL) d -= L;
-  else if (d < -halfL) d += L;
-  return d;
+  const double lo = d - L, hi = d + L;
+  d = d > halfL ? lo : d;
+  return d < -halfL ? hi : d;
 }
 
 // r^2 evaluated as (dx*dx + dy*dy) + dz*dz with no fused multiply-add, so the

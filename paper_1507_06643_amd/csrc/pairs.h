@@ -199,9 +199,9 @@ __device__ __forceinline__ uint32_t group_ballot(const Lanes& L, bool pred) {
 // `sink(take, j, id_j)` on every trip, `take` being r^2 < rc2 and j != i.
 // The trips are uniform across the group, so `sink` may ballot.
 __device__ __forceinline__ float min_image_f(float d, float L, float halfL) {
-  if (d > halfL) d -= L;
-  else if (d < -halfL) d += L;
-  return d;
+  const float lo = d - L, hi = d + L;
+  d = d > halfL ? lo : d;
+  return d < -halfL ? hi : d;
 }
 
 template <bool MI, typename Sink>
