@@ -597,8 +597,9 @@ def main():
     prof = kernel_profile(sysm, args.profile_steps)
     nbar = mean_neighbours(sysm, n)
     nwork = sysm.mean_work_list()
-    # skin-list length from the density of the uniform fluid: pairs within rc + skin
-    nskin = nbar * ((cfg.rc + cfg.skin) / cfg.rc) ** 3
+    # skin-list length from the density of the uniform fluid: the list's own
+    # pairs (all of them, or a tile's inner pairs once) within rc + skin
+    nskin = nwork * ((cfg.rc + cfg.skin) / cfg.rc) ** 3
     b0 = sysm.list_builds()
     sysm.step(100)
     builds_per_step = (sysm.list_builds() - b0) / 100.0
