@@ -135,6 +135,7 @@ constexpr uint32_t kSubMask = (1u << kSub) - 1u;
 // ~27 skin candidates (pass A, list build) are faster with four.
 constexpr int kSubSer = 2;
 constexpr int kListLds = 64;  // list entries per particle staged in LDS
+constexpr int kBuildLds = 32;  // the same in the list build
 constexpr int kUniqTile = 128;  // particles per tile (= block) of the unique-pair passes
 
 // In the tile form a pair joining two particles of one tile (128 consecutive
@@ -194,40 +195,40 @@ __device__ __forceinline__ uint32_t group_ballot(const Lanes& L, bool pred) {
   return (uint32_t)(__ballot(pred) >> L.shift) & kSubMask;
 }
 
-// Visit the 27-cell stencil; the group's lanes take the candidates of every
-// cell run in turn (lane sub takes run[sub], run[sub + kSub], ...) and call
-// `sink(take, j, id_j)` on every trip, `take` being r^2 < rc2 and j != i.
-// The trips are uniform across the group, so `sink` may ballot.
 __device__ __forceinline__ float min_image_f(float d, float L, float halfL) {
   const float lo = d - L, hi = d + L;
   d = d > halfL ? lo : d;
   return d < -halfL ? hi : d;
 }
 
+// Visit the 27-cell stencil.  Its cells come as runs of consecutive memory
+// (three cells of an x-row in row-major order; one run per cell block an
+// x-row crosses in blocked order; a periodic wrap splits a row), which the
+// group first lists in LDS (`runs`: the runs' first indices, then their
+// cumulative ends); the group's lanes then take the concatenated candidates
+// four at a time (lane sub takes position F + sub), so a trip is cut short
+// only at the end of the stencil, not at the end of every run.  `sink(take,
+// j, id_j)` is called on every trip, `take` being r^2 < thr2 and j != i; the
+// trips are uniform across the group, so `sink` may ballot.
+constexpr int kRunsMax = 28;  // runs per stencil: 9 rows x at most 3 pieces
+
 template <bool MI, typename Sink>
 __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
                                                 const uint32_t* __restrict__ start,
                                                 const QIdF* __restrict__ qid, float xi, float yi,
                                                 float zi, int cx, int cy, int cz, float thr2,
-                                                Sink&& sink) {
+                                                uint32_t* runs, Sink&& sink) {
   const float bx = (float)g.box[0], by = (float)g.box[1], bz = (float)g.box[2];
-  auto range = [&](uint32_t jb, uint32_t je) {
-    for (uint32_t base = jb; base < je; base += kSub) {
-      const uint32_t j = base + L.sub;
-      bool take = false;
-      uint32_t idj = 0;
-      if (j < je) {
-        const QIdF c = qid[j];
-        float dx = xi - c.x, dy = yi - c.y, dz = zi - c.z;
-        idj = c.id;
-        if constexpr (MI) {
-          if (g.periodic[0]) dx = min_image_f(dx, bx, 0.5f * bx);
-          if (g.periodic[1]) dy = min_image_f(dy, by, 0.5f * by);
-          if (g.periodic[2]) dz = min_image_f(dz, bz, 0.5f * bz);
-        }
-        take = (dx * dx + dy * dy) + dz * dz < thr2 && j != (uint32_t)L.i;
+  // the runs, in stencil order (uniform across the group; lane 0 records)
+  uint32_t nr = 0, tot = 0;
+  auto add = [&](uint32_t jb, uint32_t je) {
+    if (je > jb) {
+      tot += je - jb;
+      if (L.sub == 0) {
+        runs[nr] = jb;
+        runs[kRunsMax + nr] = tot;
       }
-      sink(take, j, idj);
+      ++nr;
     }
   };
   const Row row = stencil_row(cx, g.nc[0], g.periodic[0]);
@@ -240,15 +241,15 @@ __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
       if (!wrap_cell(y, g.nc[1], g.periodic[1])) continue;
       if (B == 1) {  // row-major cells: each x range is one run of memory
         const int64_t base = g.cell_base + (int64_t)g.nc[0] * (y + (int64_t)g.nc[1] * z);
-        range(start[base + row.a0], start[base + row.b0 + 1]);
-        if (row.a1 <= row.b1) range(start[base + row.a1], start[base + row.b1 + 1]);
+        add(start[base + row.a0], start[base + row.b0 + 1]);
+        if (row.a1 <= row.b1) add(start[base + row.a1], start[base + row.b1 + 1]);
       } else {
         // blocked order: an x range is one run per cell block it crosses
         auto xrun = [&](int a, int b) {
           for (int x = a; x <= b;) {
             const int e = min(b, (x / B) * B + B - 1);
             const int64_t k0 = g.cell_base + cell_key(g, x, y, z);
-            range(start[k0], start[k0 + (e - x) + 1]);
+            add(start[k0], start[k0 + (e - x) + 1]);
             x = e + 1;
           }
         };
@@ -256,6 +257,35 @@ __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
         if (row.a1 <= row.b1) xrun(row.a1, row.b1);
       }
     }
+  }
+  // the group's lanes read what lane 0 wrote (one wave: a fence suffices)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  // lane-local cursor: run r covers concatenated positions [prev, end)
+  uint32_t r = 0, prev = 0, end = nr ? runs[kRunsMax] : 0u;
+  for (uint32_t F = 0; F < tot; F += kSub) {
+    const uint32_t f = F + L.sub;
+    bool take = false;
+    uint32_t j = 0, idj = 0;
+    if (f < tot) {
+      while (f >= end) {
+        prev = end;
+        ++r;
+        end = runs[kRunsMax + r];
+      }
+      j = runs[r] + (f - prev);
+      const QIdF c = qid[j];
+      float dx = xi - c.x, dy = yi - c.y, dz = zi - c.z;
+      idj = c.id;
+      if constexpr (MI) {
+        if (g.periodic[0]) dx = min_image_f(dx, bx, 0.5f * bx);
+        if (g.periodic[1]) dy = min_image_f(dy, by, 0.5f * by);
+        if (g.periodic[2]) dz = min_image_f(dz, bz, 0.5f * bz);
+      }
+      take = (dx * dx + dy * dy) + dz * dz < thr2 && j != (uint32_t)L.i;
+    }
+    sink(take, j, idj);
   }
 }
 
@@ -290,10 +320,12 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
     PState s, const QIdF* __restrict__ qid, const uint32_t* __restrict__ start, int64_t n,
     const Geo* __restrict__ geo, double rs, double box_max, SkinList sl, const BuildCtl* ctl,
     double half_skin2, int uniq, uint32_t* status) {
-  __shared__ uint32_t lst[kListLds * (kPairBlockMax / kSub)];
+  __shared__ uint32_t lst[kBuildLds * (kPairBlockMax / kSub)];
+  __shared__ uint32_t runs_s[2 * kRunsMax * (kPairBlockMax / kSub)];
   if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;  // uniform
   const Lanes L = lanes();
   if (L.i >= n) return;  // uniform in the group
+  uint32_t* runs = runs_s + 2 * kRunsMax * L.pib;
   const int64_t i = L.i;
   const Rec* __restrict__ R = s.r;
   const double xi = R[i].qx, yi = R[i].qy, zi = R[i].qz;
@@ -321,7 +353,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
     if (take) {
       const uint32_t pos = nn + __popc(bits & ((1u << L.sub) - 1u));
       const uint32_t row = uniq ? j : first + idj;
-      if (pos < (uint32_t)kListLds) lst[pos * L.ppb + L.pib] = row;
+      if (pos < (uint32_t)kBuildLds) lst[pos * L.ppb + L.pib] = row;
       else if (pos < cap) sl.idx[(int64_t)pos * sl.stride + i] = row;
     }
     nn += __popc(bits);
@@ -330,14 +362,14 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
                         interior_dim(cy, g.nc[1], g.periodic[1]) &&
                         interior_dim(cz, g.nc[2], g.periodic[2]);
   if (__all(interior))
-    scan_candidates<false>(L, g, start, qid, own.x, own.y, own.z, cx, cy, cz, thr2, sink);
+    scan_candidates<false>(L, g, start, qid, own.x, own.y, own.z, cx, cy, cz, thr2, runs, sink);
   else
-    scan_candidates<true>(L, g, start, qid, own.x, own.y, own.z, cx, cy, cz, thr2, sink);
+    scan_candidates<true>(L, g, start, qid, own.x, own.y, own.z, cx, cy, cz, thr2, runs, sink);
   if (nn > cap) {
     if (L.sub == 0) atomicOr(status, ST_OVERFLOW);
     nn = cap;
   }
-  const uint32_t staged = nn < (uint32_t)kListLds ? nn : (uint32_t)kListLds;
+  const uint32_t staged = nn < (uint32_t)kBuildLds ? nn : (uint32_t)kBuildLds;
   for (uint32_t k = L.sub; k < staged; k += kSub)
     sl.idx[(int64_t)k * sl.stride + i] = lst[k * L.ppb + L.pib];
   if (L.sub == 0) sl.count[i] = nn;
