@@ -273,8 +273,12 @@ int dpde_set_tuning(dpde_handle* h, int32_t pair_block, int32_t aux_block);
  *                               tiles once per particle; the per-particle
  *                               sums exact in 64-bit fixed point (grid 2^-46,
  *                               a term of magnitude >= 32 fails the step with
- *                               DPDE_ERANGE), rounded once.  The default; SEM
- *                               and Hybrid run the first form.
+ *                               DPDE_ERANGE), rounded once.  The default.  It
+ *                               applies to SER with the soft potential whose
+ *                               force and potential terms fit pass A's grid
+ *                               (a < 1024 and a rc / 4 < 2^20); SEM, Hybrid,
+ *                               the LJ potential and larger a run the first
+ *                               form whatever this field says.
  *   order_block  memory order of the particles: sorted by cell, the cells
  *               taken in blocks of order_block^3 (compact blocks keep more of
  *               a particle's neighbours inside its tile and its cache lines).

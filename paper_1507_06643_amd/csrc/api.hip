@@ -320,7 +320,7 @@ void physics(const dpde_params* P, Phys& ph) {
     while (g > 30 && !(2.0 * bound < std::ldexp(1.0, 51 - g))) --g;
     ph.fix_scale_f = std::ldexp(1.0, g);
     ph.fix_inv_f = std::ldexp(1.0, -g);
-    ph.fix_range_f = (uint32_t)(1023 + 51 - g) << 20;
+    ph.fix_ok = 2.0 * bound < std::ldexp(1.0, 51 - g) ? 1 : 0;
   }
 }
 
@@ -446,7 +446,7 @@ int status_to_code(uint32_t st) {
 // fixed-point sums (the splined LJ force grows without bound as r -> 0).
 bool uniq_form(const dpde_handle* h) {
   return h->pairs_once && h->phys.scheme == DPDE_SCHEME_SER && !h->hybrid &&
-         h->phys.potential == DPDE_POT_SOFT && h->phys.a < 1024.0;
+         h->phys.potential == DPDE_POT_SOFT && h->phys.a < 1024.0 && h->phys.fix_ok;
 }
 
 // Kick and drift; on list-build steps (decided on the device) the binning,

@@ -66,9 +66,11 @@ struct Phys {
   int32_t potential;        // 0: soft, 1: splined LJ
   int32_t project;          // eps projection after every step
   // tile form, pass A: grid 2^-g of the force and potential sums, chosen so
-  // that |term| <= a (soft potential) stays below 2^(51-g) / 2
+  // that every soft-potential term (|f d| <= a, v/2 <= a rc/4) stays below
+  // 2^(51-g) / 2; fix_ok = 0 when no grid down to 2^-30 does (the tile form
+  // is then not used)
   double fix_scale_f, fix_inv_f;
-  uint32_t fix_range_f;     // high word of 2^(51-g): the first |term| out of range
+  int32_t fix_ok;
   int32_t pad_fix;
 };
 

@@ -988,7 +988,7 @@ __global__ __launch_bounds__(kSub * kUniqTile) __attribute__((amdgpu_waves_per_e
   const uint32_t cap = (uint32_t)P.cap;
   long long XF0 = 0, XF1 = 0, XF2 = 0, XU = 0, XLh = 0, XLl = 0;  // raw fixed-point words
   long long terms = 0;
-  uint32_t hi_f = 0u, hi_l = 0u;
+  uint32_t hi_l = 0u;
   uint32_t nn = 0;
   if (live) {
     const GeoRef<BATCH> g = geo[BATCH ? R[i].rep : 0u];
@@ -1014,10 +1014,8 @@ __global__ __launch_bounds__(kSub * kUniqTile) __attribute__((amdgpu_waves_per_e
         const long long fh = fix_raw_g<GH>(lap);
         const double rem = lap - (double)(fh - kFixMagicBits) * 0x1p-20;
         const long long fr = fix_raw_g<GR>(rem);
-        pair_fix_range(gx, hi_f);
-        pair_fix_range(gy, hi_f);
-        pair_fix_range(gz, hi_f);
-        pair_fix_range(0.5 * v, hi_f);
+        // forces and potential shares are within the grid's range by its
+        // choice (|f d| <= a, v/2 <= a rc/4); the Laplacian share grows as 1/r
         pair_fix_range(lap, hi_l);
         XF0 += f0;
         XF1 += f1;
@@ -1091,7 +1089,7 @@ __global__ __launch_bounds__(kSub * kUniqTile) __attribute__((amdgpu_waves_per_e
     XLh += __shfl_xor(XLh, off, kWave);
     XLl += __shfl_xor(XLl, off, kWave);
   }
-  if (hi_f >= P.fix_range_f || hi_l >= fix_range_hi<GH>()) atomicOr(status, ST_RANGE);
+  if (hi_l >= fix_range_hi<GH>()) atomicOr(status, ST_RANGE);
   __syncthreads();
   if (!live) return;
   if (nn > cap) {
