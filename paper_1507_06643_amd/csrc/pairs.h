@@ -195,22 +195,21 @@ __device__ __forceinline__ uint32_t group_ballot(const Lanes& L, bool pred) {
   return (uint32_t)(__ballot(pred) >> L.shift) & kSubMask;
 }
 
-__device__ __forceinline__ float min_image_f(float d, float L, float halfL) {
-  const float lo = d - L, hi = d + L;
-  d = d > halfL ? lo : d;
-  return d < -halfL ? hi : d;
-}
-
 // Visit the 27-cell stencil.  Its cells come as runs of consecutive memory
 // (three cells of an x-row in row-major order; one run per cell block an
 // x-row crosses in blocked order; a periodic wrap splits a row), which the
 // group first lists in LDS (`runs`: the runs' first indices, then their
-// cumulative ends); the group's lanes then take the concatenated candidates
-// four at a time (lane sub takes position F + sub), so a trip is cut short
-// only at the end of the stencil, not at the end of every run.  `sink(take,
-// j, id_j)` is called on every trip, `take` being r^2 < thr2 and j != i; the
-// trips are uniform across the group, so `sink` may ballot.
+// cumulative ends with the run's periodic image in the top bits); the
+// group's lanes then take the concatenated candidates four at a time (lane
+// sub takes position F + sub), so a trip is cut short only at the end of the
+// stencil, not at the end of every run.  A run reached across a periodic face
+// holds images one box length away: its candidates are compared after that
+// shift (d - s with s = +-L), which for every candidate within the list
+// radius is the minimum image itself, with the same two roundings.
+// `sink(take, j, id_j)` is called on every trip, `take` being r^2 < thr2 and
+// j != i; the trips are uniform across the group, so `sink` may ballot.
 constexpr int kRunsMax = 28;  // runs per stencil: 9 rows x at most 3 pieces
+constexpr int kRunEndBits = 26;  // cumulative end; above it 2 bits per axis: 1 = +L, 2 = -L
 
 template <bool MI, typename Sink>
 __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
@@ -221,40 +220,48 @@ __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
   const float bx = (float)g.box[0], by = (float)g.box[1], bz = (float)g.box[2];
   // the runs, in stencil order (uniform across the group; lane 0 records)
   uint32_t nr = 0, tot = 0;
-  auto add = [&](uint32_t jb, uint32_t je) {
+  auto add = [&](uint32_t jb, uint32_t je, uint32_t image) {
     if (je > jb) {
       tot += je - jb;
       if (L.sub == 0) {
         runs[nr] = jb;
-        runs[kRunsMax + nr] = tot;
+        runs[kRunsMax + nr] = tot | (image << kRunEndBits);
       }
       ++nr;
     }
   };
+  // the image code of a neighbour cell index before wrapping: +L from above,
+  // -L from below (2 bits)
+  auto code = [](int c, int nc) -> uint32_t { return c >= nc ? 1u : (c < 0 ? 2u : 0u); };
   const Row row = stencil_row(cx, g.nc[0], g.periodic[0]);
   const int B = g.oblk;
+  // the x image of the second range of a periodic row: the cell left of
+  // cx = 0 or right of cx = nc - 1
+  const uint32_t cx1 = cx == 0 ? 2u : 1u;
   for (int dz = -1; dz <= 1; ++dz) {
     int z = cz + dz;
+    const uint32_t iz = code(z, g.nc[2]) << 4;
     if (!wrap_cell(z, g.nc[2], g.periodic[2])) continue;
     for (int dy = -1; dy <= 1; ++dy) {
       int y = cy + dy;
+      const uint32_t iyz = iz | (code(y, g.nc[1]) << 2);
       if (!wrap_cell(y, g.nc[1], g.periodic[1])) continue;
       if (B == 1) {  // row-major cells: each x range is one run of memory
         const int64_t base = g.cell_base + (int64_t)g.nc[0] * (y + (int64_t)g.nc[1] * z);
-        add(start[base + row.a0], start[base + row.b0 + 1]);
-        if (row.a1 <= row.b1) add(start[base + row.a1], start[base + row.b1 + 1]);
+        add(start[base + row.a0], start[base + row.b0 + 1], iyz);
+        if (row.a1 <= row.b1) add(start[base + row.a1], start[base + row.b1 + 1], iyz | cx1);
       } else {
         // blocked order: an x range is one run per cell block it crosses
-        auto xrun = [&](int a, int b) {
+        auto xrun = [&](int a, int b, uint32_t image) {
           for (int x = a; x <= b;) {
             const int e = min(b, (x / B) * B + B - 1);
             const int64_t k0 = g.cell_base + cell_key(g, x, y, z);
-            add(start[k0], start[k0 + (e - x) + 1]);
+            add(start[k0], start[k0 + (e - x) + 1], image);
             x = e + 1;
           }
         };
-        xrun(row.a0, row.b0);
-        if (row.a1 <= row.b1) xrun(row.a1, row.b1);
+        xrun(row.a0, row.b0, iyz);
+        if (row.a1 <= row.b1) xrun(row.a1, row.b1, iyz | cx1);
       }
     }
   }
@@ -262,39 +269,58 @@ __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  // lane-local cursor: run r covers concatenated positions [prev, end)
-  uint32_t r = 0, prev = 0, end = nr ? runs[kRunsMax] : 0u;
+  constexpr uint32_t kEndMask = (1u << kRunEndBits) - 1u;
+  auto shift = [](uint32_t c2, float l) { return c2 == 1u ? l : (c2 == 2u ? -l : 0.0f); };
+  // lane-local cursor: run r covers concatenated positions [prev, end) and
+  // holds images shifted by (sx, sy, sz)
+  uint32_t r = 0, prev = 0, word = nr ? runs[kRunsMax] : 0u;
+  uint32_t end = word & kEndMask;
+  float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+  auto image = [&]() {
+    if constexpr (MI) {
+      const uint32_t c = word >> kRunEndBits;
+      sx = shift(c & 3u, bx);
+      sy = shift((c >> 2) & 3u, by);
+      sz = shift(c >> 4, bz);
+    }
+  };
+  image();
   for (uint32_t F = 0; F < tot; F += kSub) {
     const uint32_t f = F + L.sub;
     bool take = false;
     uint32_t j = 0, idj = 0;
     if (f < tot) {
-      while (f >= end) {
-        prev = end;
-        ++r;
-        end = runs[kRunsMax + r];
+      if (f >= end) {
+        do {
+          prev = end;
+          ++r;
+          word = runs[kRunsMax + r];
+          end = word & kEndMask;
+        } while (f >= end);
+        image();
       }
       j = runs[r] + (f - prev);
       const QIdF c = qid[j];
       float dx = xi - c.x, dy = yi - c.y, dz = zi - c.z;
-      idj = c.id;
       if constexpr (MI) {
-        if (g.periodic[0]) dx = min_image_f(dx, bx, 0.5f * bx);
-        if (g.periodic[1]) dy = min_image_f(dy, by, 0.5f * by);
-        if (g.periodic[2]) dz = min_image_f(dz, bz, 0.5f * bz);
+        dx -= sx;
+        dy -= sy;
+        dz -= sz;
       }
+      idj = c.id;
       take = (dx * dx + dy * dy) + dz * dz < thr2 && j != (uint32_t)L.i;
     }
     sink(take, j, idj);
   }
 }
 
-__device__ __forceinline__ bool interior_dim(int c, int nc, int periodic) {
-  // cells c-1..c+1 exist without wrapping and are closer than half a box
-  return !periodic || (nc >= 4 && c >= 1 && c <= nc - 2);
-}
 
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ bool interior_dim(int c, int nc, int periodic) {
+  // cells c-1..c+1 exist without wrapping
+  return !periodic || (c >= 1 && c <= nc - 2);
+}
+
 // Neighbour lists with a skin.  On a build step every particle collects the
 // particles within rs = rc + skin through the 27-cell stencil (scan_candidates),
 // and the list is sorted by neighbour identifier.  Every step then keeps the
@@ -358,6 +384,8 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
     }
     nn += __popc(bits);
   };
+  // waves whose particles all sit away from the periodic faces meet no
+  // image across them
   const bool interior = interior_dim(cx, g.nc[0], g.periodic[0]) &&
                         interior_dim(cy, g.nc[1], g.periodic[1]) &&
                         interior_dim(cz, g.nc[2], g.periodic[2]);

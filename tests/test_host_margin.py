@@ -5,7 +5,10 @@ host: the kernel's FP32 steps (conversion of FP64 coordinates, difference,
 minimum image against the FP32 box side, squared sum, with or without fused
 multiply-adds) emulated in numpy, against the exact FP64 distance, on
 coordinates up to Q, including pairs across periodic faces and far outside a
-free boundary."""
+free boundary.  (The kernel subtracts the +-L of a stencil cell reached
+across a periodic face rather than choosing the image by value; for every
+pair within the list radius that is this minimum image, in the same two
+roundings.)"""
 import numpy as np
 
 U = 2.0 ** -24
