@@ -93,6 +93,7 @@ CASES = [
     (3001, None, (1, 1, 1), 2),        # ragged
     (2400, (20.0, 6.5, 6.2), (0, 1, 1), 3),  # free boundaries along x
     (5000, (12.3, 11.7, 11.9), (1, 1, 1), 4),
+    (180, (3.95, 3.95, 3.95), (1, 1, 1), 5),  # 3 cells per side: every stencil wraps
 ]
 
 
@@ -113,6 +114,21 @@ def test_cells_and_pairs_bit_exact(dp, n, box, periodic, seed, skin):
     got = sysm.debug_pairs()
     want = O.pairs(P, q, "cells")
     assert got.shape == want.shape
+    assert np.array_equal(got, want)
+    sysm.close()
+
+
+@pytest.mark.parametrize("order_block", [2, 3])
+@pytest.mark.parametrize("n,box,periodic,seed", [CASES[2], CASES[4]])
+def test_pairs_bit_exact_in_blocked_cell_order(dp, n, box, periodic, seed, order_block):
+    """The same pair set in blocked cell order, where a stencil row is several
+    runs of memory and some runs are reached across a periodic face."""
+    q = _adversarial(n, box, seed)
+    _, p, e = W.equilibrium_state(n, box, seed=seed)
+    sysm = dp.System(_cfg(dp, n, box, periodic=periodic, skin=0.3), q, p, e)
+    sysm.set_shape(order_block=order_block)
+    got = sysm.debug_pairs()
+    want = O.pairs(_oparams(n, box, periodic=periodic), q, "cells")
     assert np.array_equal(got, want)
     sysm.close()
 
