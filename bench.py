@@ -184,7 +184,8 @@ def drift_gpu(dp, W, n=65536, steps=10000, seeds=(1, 2, 3, 4), mlp_iters=20000):
     stored oracle runs (same initial states and noise seeds), with the linear
     EOS (FP64 and FP32 pair terms, dt 0.005 and 0.01) and the Einstein EOS at
     dt 0.005 (FP64 with Newton, FP64 with the surrogate, FP32 with the
-    surrogate).  Each FP64 result is set against the oracle's, in combined
+    surrogate) and 0.0025 (FP64 with Newton, FP32 with the surrogate).  Each
+    FP64 result with a stored oracle run is set against it, in combined
     standard errors of the seed means."""
     L = W.cubic_side(n)
     golden = json.load(open(GOLDEN_DRIFT))["results"] if os.path.exists(GOLDEN_DRIFT) else {}
@@ -196,7 +197,12 @@ def drift_gpu(dp, W, n=65536, steps=10000, seeds=(1, 2, 3, 4), mlp_iters=20000):
             ("fp64_newton_einstein_dt0.005", dp.EOS_EINSTEIN, dp.THETA_NEWTON, dp.FP64, 0.005,
              "einstein_dt0.005"),
             ("fp64_mlp_einstein_dt0.005", dp.EOS_EINSTEIN, dp.THETA_MLP, dp.FP64, 0.005, None),
-            ("fp32_mlp_einstein_dt0.005", dp.EOS_EINSTEIN, dp.THETA_MLP, dp.FP32, 0.005, None)]
+            ("fp32_mlp_einstein_dt0.005", dp.EOS_EINSTEIN, dp.THETA_MLP, dp.FP32, 0.005, None),
+            # the Einstein EOS at half the step, where the drift of both forms
+            # falls below 1e-6 per 10^4 steps
+            ("fp64_newton_einstein_dt0.0025", dp.EOS_EINSTEIN, dp.THETA_NEWTON, dp.FP64, 0.0025,
+             None),
+            ("fp32_mlp_einstein_dt0.0025", dp.EOS_EINSTEIN, dp.THETA_MLP, dp.FP32, 0.0025, None)]
     weights = None
     out = {}
     for name, eos, tm, prec, dt, gkey in legs:
@@ -672,7 +678,11 @@ def main():
         for name, eos, tm, prec, vdt in [
                 ("plain_fp64_linear_eos", dp.EOS_LINEAR, dp.THETA_NEWTON, dp.FP64, 0.005),
                 ("fp32_pairs_learned_eos", dp.EOS_EINSTEIN, dp.THETA_MLP, dp.FP32, 0.005),
-                ("fp64_newton_learned_eos", dp.EOS_EINSTEIN, dp.THETA_NEWTON, dp.FP64, 0.005)]:
+                ("fp64_newton_learned_eos", dp.EOS_EINSTEIN, dp.THETA_NEWTON, dp.FP64, 0.005),
+                # at half the step, where both forms drift below 1e-6 per 10^4 steps
+                ("fp32_pairs_learned_eos_dt0.0025", dp.EOS_EINSTEIN, dp.THETA_MLP, dp.FP32, 0.0025),
+                ("fp64_newton_learned_eos_dt0.0025", dp.EOS_EINSTEIN, dp.THETA_NEWTON, dp.FP64,
+                 0.0025)]:
             log(f"[bench] variant {name}")
             s2, _, _, _ = make_system(dp, W, n, eos=eos, theta_mode=tm, precision=prec, dt=vdt)
             if tm != dp.THETA_NEWTON:
@@ -689,12 +699,15 @@ def main():
         line["variants"] = variants
         # speed of the FP32-pair-term + surrogate form relative to plain FP64
         # (linear EOS) and to FP64 with Newton on the same EOS; the drift legs
-        # give both precisions' drift at dt = 0.005
+        # give both precisions' drift at dt = 0.005 and 0.0025
         v32 = variants["fp32_pairs_learned_eos"]["value"]
         line["fp32_surrogate_speedup"] = {
             "vs_plain_fp64_linear_eos": v32 / variants["plain_fp64_linear_eos"]["value"],
             "vs_fp64_newton_same_eos": v32 / variants["fp64_newton_learned_eos"]["value"],
-            "vs_fp64_surrogate_same_eos": v32 / value}
+            "vs_fp64_surrogate_same_eos": v32 / value,
+            "vs_fp64_newton_same_eos_dt0.0025":
+                variants["fp32_pairs_learned_eos_dt0.0025"]["value"] /
+                variants["fp64_newton_learned_eos_dt0.0025"]["value"]}
     if not args.no_legs:
         log("[bench] batched replicas: 256 systems, one captured graph, autotuned blocks")
         line["batched_replicas"] = batched_leg(dp, W)
@@ -711,11 +724,15 @@ def main():
         if sp is not None:
             # the speedup stated next to the drift of both forms on the same
             # EOS and dt, and their difference in combined standard errors
-            a, b = res["fp32_mlp_einstein_dt0.005"], res["fp64_newton_einstein_dt0.005"]
-            sp["drift_per_1e4_fp32_surrogate"] = a["drift_per_1e4"]
-            sp["drift_per_1e4_fp64_newton"] = b["drift_per_1e4"]
-            sp["drift_diff_over_combined_se"] = abs(a["drift_per_1e4"][0] - b["drift_per_1e4"][0]) / \
-                max(1e-300, math.hypot(a["drift_per_1e4"][1], b["drift_per_1e4"][1]))
+            for dtk in ("0.005", "0.0025"):
+                a = res[f"fp32_mlp_einstein_dt{dtk}"]
+                b = res[f"fp64_newton_einstein_dt{dtk}"]
+                sfx = "" if dtk == "0.005" else "_dt0.0025"
+                sp[f"drift_per_1e4_fp32_surrogate{sfx}"] = a["drift_per_1e4"]
+                sp[f"drift_per_1e4_fp64_newton{sfx}"] = b["drift_per_1e4"]
+                sp[f"drift_diff_over_combined_se{sfx}"] = \
+                    abs(a["drift_per_1e4"][0] - b["drift_per_1e4"][0]) / \
+                    max(1e-300, math.hypot(a["drift_per_1e4"][1], b["drift_per_1e4"][1]))
     if not args.no_cpu:
         log(f"[bench] CPU oracle: {args.cpu_steps} steps at N={n}")
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, 1, dt, eps0)
