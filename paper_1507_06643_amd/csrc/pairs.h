@@ -212,7 +212,7 @@ constexpr int kRunsMax = 28;  // runs per stencil: 9 rows x at most 3 pieces
 constexpr int kRunEndBits = 26;  // cumulative end; above it 2 bits per axis: 1 = +L, 2 = -L
 
 template <bool MI, typename Sink>
-__device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
+__device__ __forceinline__ bool scan_candidates(const Lanes& L, const Geo& g,
                                                 const uint32_t* __restrict__ start,
                                                 const QIdF* __restrict__ qid, float xi, float yi,
                                                 float zi, int cx, int cy, int cz, float thr2,
@@ -220,8 +220,11 @@ __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
   const float bx = (float)g.box[0], by = (float)g.box[1], bz = (float)g.box[2];
   // the runs, in stencil order (uniform across the group; lane 0 records)
   uint32_t nr = 0, tot = 0;
+  bool whole = true;  // false: the stencil holds more candidates than the run ends can count
+  constexpr uint32_t kEndMask = (1u << kRunEndBits) - 1u;
   auto add = [&](uint32_t jb, uint32_t je, uint32_t image) {
-    if (je > jb) {
+    if (je > jb && je - jb > kEndMask - tot) whole = false;
+    if (je > jb && whole) {
       tot += je - jb;
       if (L.sub == 0) {
         runs[nr] = jb;
@@ -269,7 +272,6 @@ __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  constexpr uint32_t kEndMask = (1u << kRunEndBits) - 1u;
   auto shift = [](uint32_t c2, float l) { return c2 == 1u ? l : (c2 == 2u ? -l : 0.0f); };
   // lane-local cursor: run r covers concatenated positions [prev, end) and
   // holds images shifted by (sx, sy, sz)
@@ -312,6 +314,7 @@ __device__ __forceinline__ void scan_candidates(const Lanes& L, const Geo& g,
     }
     sink(take, j, idj);
   }
+  return whole;
 }
 
 
@@ -389,10 +392,14 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
   const bool interior = interior_dim(cx, g.nc[0], g.periodic[0]) &&
                         interior_dim(cy, g.nc[1], g.periodic[1]) &&
                         interior_dim(cz, g.nc[2], g.periodic[2]);
-  if (__all(interior))
-    scan_candidates<false>(L, g, start, qid, own.x, own.y, own.z, cx, cy, cz, thr2, runs, sink);
-  else
-    scan_candidates<true>(L, g, start, qid, own.x, own.y, own.z, cx, cy, cz, thr2, runs, sink);
+  const bool whole =
+      __all(interior)
+          ? scan_candidates<false>(L, g, start, qid, own.x, own.y, own.z, cx, cy, cz, thr2, runs,
+                                   sink)
+          : scan_candidates<true>(L, g, start, qid, own.x, own.y, own.z, cx, cy, cz, thr2, runs,
+                                  sink);
+  // a stencil too full to count is a list overflow
+  if (!whole && L.sub == 0) atomicOr(status, ST_OVERFLOW);
   if (nn > cap) {
     if (L.sub == 0) atomicOr(status, ST_OVERFLOW);
     nn = cap;
@@ -1432,10 +1439,17 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_c_uniq(
   __shared__ float net_x[kUniqTile];
   __shared__ float net_y[kUniqTile];
   __shared__ uint32_t first_s[2 * kUniqTile / kWave][32];
+  __shared__ double hs[3][kUniqTile];  // the tile's h: partners inside the tile read it here
   __shared__ uint32_t st_flag;
   for (int c = threadIdx.x; c < kUniqTile; c += blockDim.x) acc[c] = 0;
-  if (block_status_set(status, &st_flag)) return;  // uniform in the block
   const int64_t tb = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kUniqTile;
+  if (threadIdx.x < kUniqTile && tb + threadIdx.x < n) {
+    const H3 h = hv[tb + threadIdx.x];
+    hs[0][threadIdx.x] = h.x;
+    hs[1][threadIdx.x] = h.y;
+    hs[2][threadIdx.x] = h.z;
+  }
+  if (block_status_set(status, &st_flag)) return;  // uniform in the block (and hs visible)
   const int pl = threadIdx.x >> 1, sub = threadIdx.x & 1;
   const int w = threadIdx.x / kWave;
   uint32_t* first = first_s[w];
@@ -1461,6 +1475,20 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_c_uniq(
     }
   }
   const bool mi = REGEN ? !__all(away) : true;  // uniform in the wave
+  // h_j of a partner: from LDS inside the tile, else from memory
+  auto gather_h = [&](uint32_t j, double& x, double& y, double& z) {
+    const uint32_t rel = in_tile(j, tb);
+    if (rel < (uint32_t)kUniqTile) {
+      x = hs[0][rel];
+      y = hs[1][rel];
+      z = hs[2][rel];
+    } else {
+      const H3 h = hv[j];
+      x = h.x;
+      y = h.y;
+      z = h.z;
+    }
+  };
   // e_ij of entry k of particle ii (record ra, h_i = hi), given the
   // partner's index j and h_j; its share added to the partner inside the tile
   auto term = [&](const Rec& ra, const H3& hi, int64_t ii, uint32_t k, uint32_t j, double hx,
@@ -1501,9 +1529,7 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_c_uniq(
     }
     double hx = 0.0, hy = 0.0, hz = 0.0;
     if ((uint32_t)sub < nreg) {
-      hx = hv[jr[0]].x;
-      hy = hv[jr[0]].y;
-      hz = hv[jr[0]].z;
+      gather_h(jr[0], hx, hy, hz);
     }
 #pragma unroll
     for (int q = 0; q < kTileRegular / 2; ++q) {
@@ -1511,9 +1537,7 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_c_uniq(
       if (k >= nreg) break;
       const double cx = hx, cy = hy, cz = hz;
       if (q + 1 < kTileRegular / 2 && k + 2 < nreg) {
-        hx = hv[jr[q + 1]].x;
-        hy = hv[jr[q + 1]].y;
-        hz = hv[jr[q + 1]].z;
+        gather_h(jr[q + 1], hx, hy, hz);
       }
       X += term(a, hi, i, k, jr[q], cx, cy, cz);
       ++terms;
