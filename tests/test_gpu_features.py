@@ -557,5 +557,35 @@ def test_autotune_records_the_shape_of_the_size_class(dp, tmp_path):
         dp.tuning_clear()
 
 
+def test_autotune_table_keys_batches_by_replica_count(dp):
+    """A batch is its own replica class: its tuned shape is recorded under
+    (size class, 1 + floor(log2 nrep), precision) and does not leak to a
+    single system of the same total size, and the next batch of that class
+    starts with it."""
+    def batch(nrep, seed):
+        sizes, seeds = W.replica_sizes(nrep, 500, 1500, seed=seed)
+        cfgs, qs, ps, es = [], [], [], []
+        for r, (nr, sd) in enumerate(zip(sizes, seeds)):
+            L = W.cubic_side(int(nr))
+            q, p, e = W.equilibrium_state(int(nr), [L] * 3, seed=4000 + r)
+            cfgs.append(dp.Config(n=int(nr), box=[L] * 3, seed=int(sd), replica=r))
+            qs.append(q); ps.append(p); es.append(e)
+        return dp.System(cfgs, np.concatenate(qs), np.concatenate(ps), np.concatenate(es))
+    dp.tuning_clear()
+    try:
+        b = batch(8, 31)
+        b.autotune(2)
+        sh, n = b.get_shape(), b.n
+        b.close()
+        got = dp.tuning_lookup(n, 8, dp.FP64)
+        assert got is not None and got[0] == sh
+        assert dp.tuning_lookup(n, 1, dp.FP64) is None
+        b2 = batch(8, 31)
+        assert b2.get_shape() == sh
+        b2.close()
+    finally:
+        dp.tuning_clear()
+
+
 def torch_equal(x, y):
     return bool((x == y).all().item())
