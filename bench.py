@@ -269,20 +269,24 @@ ALGO_BYTES = {
     "pass_b": 24 + 24 + 8 + 4 + 24,       # q, p~, 1/T, id in | dp_i out  (84)
     "pass_c": 24 + 24 + 8 + 4 + 24 + 8 + 24 + 8 + 8,  # q, p~, 1/T, id, dp_i, eps | p, eps, 1/T (132)
 }
+# The end of the step inside the tile sweep 2 (the observables' sums and the
+# next step's kick and drift): F, U and Laplacian shares, reference position
+# in | q out (88)
+TAIL_BYTES = 24 + 8 + 8 + 24 + 24
 
 
-def pair_kernel_bytes(name, nbar=None, nskin=None, fp32=False):
+def pair_kernel_bytes(name, tail=False):
     for k, v in ALGO_BYTES.items():
         if name.startswith(k):
-            return float(v)
+            return float(v) + (TAIL_BYTES if tail and k == "pass_c" else 0.0)
     return None
 
 
-def pair_kernel_list_bytes(name, nwork, nskin):
+def pair_kernel_list_bytes(name, nwork, nskin, tail=False):
     """The same plus the neighbour-list words (4 B per entry and per count):
     the skin list read and the work list written by pass A, the work list read
     by the sweeps."""
-    b = pair_kernel_bytes(name)
+    b = pair_kernel_bytes(name, tail)
     if b is None:
         return None
     work = 4.0 + 4.0 * nwork
@@ -614,18 +618,21 @@ def main():
     symbols = {"pass_a_forces": "k_pass_a_uniq<false, 0>", "pass_b_ser": "k_pass_b_uniq<false, 0, 0>",
                "pass_c_ser": "k_pass_c_uniq<false, 0, 0, 0, 1>"}
     unique_pairs = 0.5 * nbar * n
+    # the step's end runs inside sweep 2 when the kick is launched less often
+    # than the sweep (once per call rather than once per step)
+    tail = prof.get("kick", {"launches": 0})["launches"] < prof["pass_c_ser"]["launches"]
     pair_roofs = {}
     for k in [k for k in prof if k in symbols]:
-        bpp_k = pair_kernel_bytes(k)
+        bpp_k = pair_kernel_bytes(k, tail)
         t_k = prof[k]["avg_ms"] * 1e-3
         tr = counter_traffic(symbols[k])
         vi = counter_valu(symbols[k])
         r = {"avg_launch_ms": prof[k]["avg_ms"], "algorithmic_bytes_per_particle": bpp_k,
              "algorithmic_bytes": bpp_k * n, "hbm_GBps": bpp_k * n / t_k / 1e9,
              "hbm_frac": bpp_k * n / t_k / 1e9 / HBM_PEAK_GBS,
-             "with_lists_bytes_per_particle": pair_kernel_list_bytes(k, nwork, nskin),
-             "with_lists_hbm_frac": pair_kernel_list_bytes(k, nwork, nskin) * n / t_k / 1e9 /
-             HBM_PEAK_GBS,
+             "with_lists_bytes_per_particle": pair_kernel_list_bytes(k, nwork, nskin, tail),
+             "with_lists_hbm_frac": pair_kernel_list_bytes(k, nwork, nskin, tail) * n / t_k /
+             1e9 / HBM_PEAK_GBS,
              "counter_bytes": None if tr is None else tr[0] + tr[1],
              "counter_GBps": None if tr is None else (tr[0] + tr[1]) / t_k / 1e9,
              "issued_valu_frac": None if vi is None else vi * 64 / t_k / ALU_PEAK_LANE_OPS}
@@ -640,7 +647,8 @@ def main():
     roof = {"kernel": dom, "symbol": symbols[dom], "bound": "hbm", "achieved": d["hbm_GBps"],
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["hbm_frac"],
             "traffic": d["counter_bytes"], "bytes_per_particle": d["algorithmic_bytes_per_particle"],
-            "n": n, "avg_launch_ms": d["avg_launch_ms"], "mean_neighbours": nbar,
+            "n": n, "avg_launch_ms": d["avg_launch_ms"], "step_end_in_sweep_2": tail,
+            "mean_neighbours": nbar,
             "mean_work_list": nwork, "skin_list_estimate": nskin, "pair_kernels": pair_roofs}
     if "alu_frac" in d:
         roof["secondary_alu"] = {"achieved": d["alu_lane_ops_per_s"], "peak": ALU_PEAK_LANE_OPS,

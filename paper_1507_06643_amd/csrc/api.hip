@@ -84,6 +84,7 @@ struct dpde_handle {
   double box_max = 0.0;  // largest box side over the replicas
   uint32_t* slot = nullptr;  // memory index of each identifier row
   BuildCtl* ctl = nullptr;
+  BuildCtl* ctl_next = nullptr;  // maxima of a kick fused into the previous sweep 2
   unsigned long long* builds = nullptr;
   SkinList skin{};
   bool regen = false;  // regenerate the noise in sweep 2 instead of storing dp_ij
@@ -105,6 +106,11 @@ struct dpde_handle {
   int32_t* rep_tile0 = nullptr;
   int ntiles = 0;
   Fix* partials = nullptr;
+  // observables' partial sums added by the tile sweep 2 into kTailSlots
+  // slots (single systems)
+  Fix* partials_u = nullptr;
+  int32_t* rep_tile0_u = nullptr;
+  int nslots_u = 0;
   double* E0 = nullptr;   // per-replica target energy of the projection
   double* Li = nullptr;   // per-particle Laplacian share of U
   // Hybrid: domain of each particle, domain order, bucket offsets
@@ -351,7 +357,7 @@ int allocate(dpde_handle* h) {
   if ((rc = dalloc(h, &h->nl.idx, (size_t)h->phys.cap * n)) || (rc = dalloc(h, &h->nl.count, n)))
     return rc;
   if ((rc = dalloc(h, &h->qref, n)) || (rc = dalloc(h, &h->qid, n)) ||
-      (rc = dalloc(h, &h->ctl, 1)) ||
+      (rc = dalloc(h, &h->ctl, 1)) || (rc = dalloc(h, &h->ctl_next, 1)) ||
       (rc = dalloc(h, &h->builds, 1)) ||
       (rc = dalloc(h, &h->skin.idx, (size_t)h->phys.cap * n)) ||
       (rc = dalloc(h, &h->slot, n)) ||
@@ -386,6 +392,7 @@ int allocate(dpde_handle* h) {
   }
   HIPCHK(hipMemset(h->qref, 0, n * sizeof(QRef)));
   HIPCHK(hipMemset(h->ctl, 0, sizeof(BuildCtl)));
+  HIPCHK(hipMemset(h->ctl_next, 0, sizeof(BuildCtl)));
   HIPCHK(hipMemset(h->builds, 0, sizeof(unsigned long long)));
   h->nl.dex = h->nl.dey = h->nl.dez = nullptr;
   if (!h->regen && ((rc = dalloc(h, &h->nl.dex, (size_t)h->phys.cap * n)) ||
@@ -413,6 +420,16 @@ int allocate(dpde_handle* h) {
     return rc;
   HIPCHK(hipMemcpy(h->tile_begin, tb.data(), tb.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(h->rep_tile0, rt.data(), rt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (!h->batch) {
+    // slots of the partial sums, zero between steps
+    const int32_t slots[2] = {0, (int32_t)std::min<int64_t>(kTailSlots, blocks(n, kUniqTile))};
+    if ((rc = dalloc(h, &h->partials_u, (size_t)slots[1] * kStatVals)) ||
+        (rc = dalloc(h, &h->rep_tile0_u, 2)))
+      return rc;
+    HIPCHK(hipMemset(h->partials_u, 0, (size_t)slots[1] * kStatVals * sizeof(Fix)));
+    HIPCHK(hipMemcpy(h->rep_tile0_u, slots, sizeof(slots), hipMemcpyHostToDevice));
+    h->nslots_u = slots[1];
+  }
   h->hist_cap = std::max<int64_t>(16, std::min<int64_t>(65536, kHistBytes / (h->nrep * kRecLen * 8)));
   if ((rc = dalloc(h, &h->hist, (size_t)h->hist_cap * h->nrep * kRecLen))) return rc;
   if ((rc = dalloc(h, &h->geo, h->nrep))) return rc;
@@ -449,16 +466,28 @@ bool uniq_form(const dpde_handle* h) {
          h->phys.potential == DPDE_POT_SOFT && h->phys.a < 1024.0 && h->phys.fix_ok;
 }
 
-// Kick and drift; on list-build steps (decided on the device) the binning,
-// the reorder and the skin lists.  Buffer roles are the same either way.
-void enqueue_bin(dpde_handle* h, int kick) {
+// The end of the step in the tile sweep 2 (StepTail): for single systems
+// without the projection, whose observables are taken once, from the state
+// the sweep writes.  A batch's tiles can span two replicas.
+bool fused_tail(const dpde_handle* h) {
+  return uniq_form(h) && !h->batch && !h->phys.project;
+}
+
+// What the end of a step's sweep 2 does besides the sweep.
+enum TailMode { kTailNone = 0, kTailStats = 1, kTailStatsKick = 2 };
+
+// Kick and drift (unless the previous step's sweep 2 did them: with_kick
+// false); on list-build steps (decided on the device) the binning, the
+// reorder and the skin lists.  Buffer roles are the same either way.
+void enqueue_bin(dpde_handle* h, int kick, bool with_kick = true) {
   const int b = h->aux_block;
   const int64_t n = h->n;
   const double hs2 = h->half_skin2;
   const BuildCtl* ctl = h->ctl;
-  launch(h, "kick", h->batch ? k_kick<true> : k_kick<false>, blocks(n, b), b, h->cur,
-         (const double*)h->Fx, (const double*)h->Fy, (const double*)h->Fz, n, (const Geo*)h->geo,
-         h->phys, kick, (const QRef*)h->qref, h->ctl, h->status);
+  if (with_kick)
+    launch(h, "kick", h->batch ? k_kick<true> : k_kick<false>, blocks(n, b), b, h->cur,
+           (const double*)h->Fx, (const double*)h->Fy, (const double*)h->Fz, n,
+           (const Geo*)h->geo, h->phys, kick, (const QRef*)h->qref, h->ctl, h->status);
   launch(h, "bin_key", h->batch ? k_bin_key<true> : k_bin_key<false>, blocks(n, b), b, h->cur, n,
          (const Geo*)h->geo, h->key, h->ticket, h->idk, h->cell_count, ctl, hs2, h->status);
   launch(h, "scan_tiles", k_scan_tiles, h->scan_tiles, kScanThreads, (const uint32_t*)h->cell_count,
@@ -573,7 +602,7 @@ void enqueue_hybrid_ssa(dpde_handle* h) {
 }
 
 template <bool B, int PR, int MD>
-void enqueue_fd_t(dpde_handle* h) {
+void enqueue_fd_t(dpde_handle* h, TailMode tm) {
   const int b = h->pair_block;
   const int64_t n = h->n;
   const int inl = eos_inline(h) ? 1 : 0;
@@ -605,20 +634,26 @@ void enqueue_fd_t(dpde_handle* h) {
              h->phys, d_step, (const Vec4*)h->dpi, (const H3*)h->hv, inl, m, mode, h->alt.r,
              h->status);
     };
-    const unsigned gu = blocks(n, kUniqTile), bu = 2 * kUniqTile;
+    StepTail tail{h->Fx, h->Fy, h->Fz, h->Ui, h->Li, h->qref, h->ctl_next, h->partials_u,
+                  h->nslots_u, tm != kTailNone ? 1 : 0, tm == kTailStatsKick ? 1 : 0};
+    auto pass_c_uniq = [&](auto kern) {
+      launch(h, "pass_c_ser", kern, blocks(n, kUniqTile), 2 * kUniqTile, h->cur, h->nl, n,
+             (const Geo*)h->geo, h->phys, d_step, (const Vec4*)h->dpi, (const H3*)h->hv, inl, m,
+             mode, h->alt.r, tail, h->status);
+    };
     const unsigned go = blocks(n * kSubSer, b), bo = (unsigned)b;
     if (h->regen) {
       if (uq) {
-        if (inl) pass_c(k_pass_c_uniq<B, PR, 1, MD, 0>, gu, bu);
-        else pass_c(k_pass_c_uniq<B, PR, 1, MD, 1>, gu, bu);
+        if (inl) pass_c_uniq(k_pass_c_uniq<B, PR, 1, MD, 0>);
+        else pass_c_uniq(k_pass_c_uniq<B, PR, 1, MD, 1>);
       } else {
         if (inl) pass_c(k_pass_c<B, PR, 1, MD, 0>, go, bo);
         else pass_c(k_pass_c<B, PR, 1, MD, 1>, go, bo);
       }
     } else {
       if (uq) {
-        if (inl) pass_c(k_pass_c_uniq<B, PR, 0, MD, 0>, gu, bu);
-        else pass_c(k_pass_c_uniq<B, PR, 0, MD, 1>, gu, bu);
+        if (inl) pass_c_uniq(k_pass_c_uniq<B, PR, 0, MD, 0>);
+        else pass_c_uniq(k_pass_c_uniq<B, PR, 0, MD, 1>);
       } else {
         if (inl) pass_c(k_pass_c<B, PR, 0, MD, 0>, go, bo);
         else pass_c(k_pass_c<B, PR, 0, MD, 1>, go, bo);
@@ -634,35 +669,40 @@ void enqueue_fd_t(dpde_handle* h) {
 }
 
 template <bool B, int PR>
-void enqueue_fd_m(dpde_handle* h) {
-  if (h->phys.model == DPDE_MODEL_PROJECTED) enqueue_fd_t<B, PR, 1>(h);
-  else enqueue_fd_t<B, PR, 0>(h);
+void enqueue_fd_m(dpde_handle* h, TailMode tm) {
+  if (h->phys.model == DPDE_MODEL_PROJECTED) enqueue_fd_t<B, PR, 1>(h, tm);
+  else enqueue_fd_t<B, PR, 0>(h, tm);
 }
 
-void enqueue_fd(dpde_handle* h) {
+void enqueue_fd(dpde_handle* h, TailMode tm) {
   if (h->batch) {
-    if (h->phys.precision == DPDE_FP32) enqueue_fd_m<true, PREC_F32>(h);
-    else enqueue_fd_m<true, PREC_F64>(h);
+    if (h->phys.precision == DPDE_FP32) enqueue_fd_m<true, PREC_F32>(h, tm);
+    else enqueue_fd_m<true, PREC_F64>(h, tm);
   } else {
-    if (h->phys.precision == DPDE_FP32) enqueue_fd_m<false, PREC_F32>(h);
-    else enqueue_fd_m<false, PREC_F64>(h);
+    if (h->phys.precision == DPDE_FP32) enqueue_fd_m<false, PREC_F32>(h, tm);
+    else enqueue_fd_m<false, PREC_F64>(h, tm);
   }
 }
 
-void enqueue_stats_only(dpde_handle* h, int advance, int finish) {
-  launch(h, "stats_tiles", k_stats_tiles, h->ntiles, kStatThreads, h->cur, (const double*)h->Ui,
-         (const double*)h->Li, (const double*)h->Fx, (const double*)h->Fy, (const double*)h->Fz,
-         (const int64_t*)h->tile_begin, h->phys, h->partials);
-  launch(h, "stats_final", k_stats_final, h->nrep, kStatFinalThreads, (const Fix*)h->partials,
-         (const int32_t*)h->rep_tile0, (const Geo*)h->geo, h->d_step, advance, h->rec, h->hist,
-         h->hist_cap, h->d_hist_count, h->nrep, finish, h->stats_ticket, h->ctl, h->builds,
-         h->half_skin2, (const uint32_t*)h->status);
+// With `swept`, the tile sweep 2 has written the partial sums already.
+void enqueue_stats_only(dpde_handle* h, int advance, int finish, bool swept = false) {
+  if (!swept)
+    launch(h, "stats_tiles", k_stats_tiles, h->ntiles, kStatThreads, h->cur,
+           (const double*)h->Ui, (const double*)h->Li, (const double*)h->Fx,
+           (const double*)h->Fy, (const double*)h->Fz, (const int64_t*)h->tile_begin, h->phys,
+           h->partials);
+  launch(h, "stats_final", k_stats_final, h->nrep, kStatFinalThreads,
+         swept ? h->partials_u : h->partials, swept ? 1 : 0,
+         (const int32_t*)(swept ? h->rep_tile0_u : h->rep_tile0), (const Geo*)h->geo, h->d_step,
+         advance, h->rec, h->hist, h->hist_cap, h->d_hist_count, h->nrep, finish,
+         h->stats_ticket, h->ctl, h->ctl_next, h->builds, h->half_skin2,
+         (const uint32_t*)h->status);
 }
 
 // Observables of the step; with the projection (Sec. 4.2) the record of the
 // unconstrained update gives E, the internal energies are shifted, and the
 // record is taken again from the projected state.
-void enqueue_stats(dpde_handle* h, int advance) {
+void enqueue_stats(dpde_handle* h, int advance, bool swept = false) {
   if (advance && h->phys.project) {
     enqueue_stats_only(h, 0, 0);
     const int inl = eos_inline(h) ? 1 : 0;
@@ -674,14 +714,23 @@ void enqueue_stats(dpde_handle* h, int advance) {
                         h->status);
   }
   // the last block of the final pass also ends the step
-  enqueue_stats_only(h, advance, 1);
+  enqueue_stats_only(h, advance, 1, swept);
 }
 
-void enqueue_step(dpde_handle* h) {
-  enqueue_bin(h, 1);
+// One step of a call's sequence.  Where the tile sweep 2 takes the end of the
+// step, the kick of every step but the first runs in the previous step's
+// sweep 2, and the last step leaves its records unkicked: between calls the
+// state is the end of a step, as without the fusion, with the same bits.
+void enqueue_step(dpde_handle* h, bool first, bool last) {
+  const bool fuse = fused_tail(h);
+  enqueue_bin(h, 1, first || !fuse);
   enqueue_forces(h, 1);
-  enqueue_fd(h);
-  enqueue_stats(h, 1);
+  enqueue_fd(h, !fuse ? kTailNone : last ? kTailStats : kTailStatsKick);
+  enqueue_stats(h, 1, fuse);
+}
+
+void enqueue_steps(dpde_handle* h, int64_t nsteps) {
+  for (int64_t s = 0; s < nsteps; ++s) enqueue_step(h, s == 0, s == nsteps - 1);
 }
 
 // Bin, forces, temperatures and observables of the current state.
@@ -966,7 +1015,7 @@ int dpde_list_builds(dpde_handle* h, int64_t* builds) {
 int dpde_step(dpde_handle* h, int64_t nsteps) {
   if (!h) return fail(DPDE_EINVAL, "handle is NULL");
   if (nsteps < 0) return fail(DPDE_EINVAL, "nsteps < 0");
-  for (int64_t s = 0; s < nsteps; ++s) enqueue_step(h);
+  enqueue_steps(h, nsteps);
   HIPCHK(hipGetLastError());
   int rc = read_status(h);
   // device step counter is the truth (a failing step stops the counter)
@@ -994,7 +1043,7 @@ int dpde_step_graph(dpde_handle* h, int64_t nsteps, int64_t reps) {
     // so every replay starts from the same buffers the capture saw
     h->graph_cur = h->cur;
     h->graph_alt = h->alt;
-    for (int64_t s = 0; s < nsteps; ++s) enqueue_step(h);
+    enqueue_steps(h, nsteps);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->stream, &g);
     h->profiling = prof;
@@ -1269,9 +1318,9 @@ int dpde_autotune(dpde_handle* h, int32_t steps, int32_t* pair_block, int32_t* a
     // the shape, then the snapshot state binned and listed under it
     put_shape(h, sh);
     if ((rc = upload_geo(h)) || (rc = restore())) break;
-    enqueue_step(h);  // warm-up (first launch of this shape)
+    enqueue_steps(h, 1);  // warm-up (first launch of this shape)
     (void)hipEventRecord(t0, h->stream);
-    for (int32_t st = 0; st < steps; ++st) enqueue_step(h);
+    enqueue_steps(h, steps);
     (void)hipEventRecord(t1, h->stream);
     if (hipEventSynchronize(t1) != hipSuccess) {
       rc = fail(DPDE_EHIP, "autotune timing failed");

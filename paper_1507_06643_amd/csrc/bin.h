@@ -147,9 +147,59 @@ __global__ void k_store_list_length(PState s, const Geo* __restrict__ geo, int64
 
 constexpr int kAuxMaxThreads = 1024;  // largest block of the per-particle kernels
 
-// First half of velocity-Verlet (Sec. 3.1): p += dt/2 F, q += dt p / m, then
-// the periodic wrap into [0, L); with kick == 0 only the wrap.  Each wave also
-// reports its largest squared displacement since the last list build.
+// First half of velocity-Verlet (Sec. 3.1) on one record: p += dt/2 F and
+// q += dt p / m (kick != 0), then the periodic wrap into [0, L).  Returns the
+// squared displacement since the last list build in d2 and, for a coordinate
+// outside [0, box) (free boundaries), the largest such |q| in qa; a
+// non-finite p or q raises the status.  The one definition of this
+// arithmetic: k_kick and the end of the tile sweep 2 both call it.
+__device__ __forceinline__ void kick_record(Rec& rc, const double F[3], const Geo& g,
+                                            const Phys& P, int kick,
+                                            const QRef* __restrict__ qref, int64_t i,
+                                            double& d2, double& qa, uint32_t* status) {
+  double q[3] = {rc.qx, rc.qy, rc.qz};
+  if (kick) {
+    double p[3] = {rc.px, rc.py, rc.pz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      p[d] = p[d] + P.half_dt * F[d];
+      q[d] = q[d] + P.dt * p[d] / P.mass;
+    }
+    rc.px = p[0]; rc.py = p[1]; rc.pz = p[2];
+    if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) atomicOr(status, ST_NONFINITE);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (g.periodic[d]) q[d] = wrap_coord(q[d], g.box[d]);
+  rc.qx = q[0]; rc.qy = q[1]; rc.qz = q[2];
+  if (!(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]))) {
+    atomicOr(status, ST_NONFINITE);
+  } else {
+    // coordinates outside [0, box) (free boundaries) for the list build's
+    // rounding margin; inside, the box side bounds them already
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (!(q[d] >= 0.0 && q[d] < g.box[d])) qa = fmax(qa, fabs(q[d]));
+    const QRef r0 = qref[i];
+    double dx = q[0] - r0.x, dy = q[1] - r0.y, dz = q[2] - r0.z;
+    if (g.periodic[0]) dx = min_image(dx, g.box[0], g.half_box[0]);
+    if (g.periodic[1]) dy = min_image(dy, g.box[1], g.half_box[1]);
+    if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
+    d2 = dx * dx + dy * dy + dz * dz;
+  }
+}
+
+// Raise a running maximum of non-negative doubles kept as bits (they order
+// like their bit patterns); one atomic, and only when it raises the value (a
+// stale read can only be smaller than the true value, never skip a raise).
+__device__ __forceinline__ void raise_max_bits(unsigned long long* where, double v) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  const unsigned long long cur = __hip_atomic_load(where, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (bits > cur) atomicMax(where, bits);
+}
+
+// The kick of every particle (kick == 0: only the wrap), with the maxima the
+// next list-build decision reads.
 template <bool BATCH>
 __global__ void k_kick(PState s, const double* __restrict__ Fx, const double* __restrict__ Fy,
                        const double* __restrict__ Fz, int64_t n, const Geo* __restrict__ geo,
@@ -163,55 +213,23 @@ __global__ void k_kick(PState s, const double* __restrict__ Fx, const double* __
   if (run && i < n) {
     Rec rc = s.r[i];
     const Geo& g = geo[BATCH ? rc.rep : 0u];
-    double q[3] = {rc.qx, rc.qy, rc.qz};
+    double F[3] = {0.0, 0.0, 0.0};
     if (kick) {
-      double p[3] = {rc.px, rc.py, rc.pz};
-      const double F[3] = {Fx[i], Fy[i], Fz[i]};
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        p[d] = p[d] + P.half_dt * F[d];
-        q[d] = q[d] + P.dt * p[d] / P.mass;
-      }
-      rc.px = p[0]; rc.py = p[1]; rc.pz = p[2];
-      if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) atomicOr(status, ST_NONFINITE);
+      F[0] = Fx[i];
+      F[1] = Fy[i];
+      F[2] = Fz[i];
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      if (g.periodic[d]) q[d] = wrap_coord(q[d], g.box[d]);
-    rc.qx = q[0]; rc.qy = q[1]; rc.qz = q[2];
+    kick_record(rc, F, g, P, kick, qref, i, d2, qa, status);
     s.r[i] = rc;
-    if (!(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]))) {
-      atomicOr(status, ST_NONFINITE);
-    } else {
-      // coordinates outside [0, box) (free boundaries) for the list build's
-      // rounding margin; inside, the box side bounds them already
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-        if (!(q[d] >= 0.0 && q[d] < g.box[d])) qa = fmax(qa, fabs(q[d]));
-      const QRef r0 = qref[i];
-      double dx = q[0] - r0.x, dy = q[1] - r0.y, dz = q[2] - r0.z;
-      if (g.periodic[0]) dx = min_image(dx, g.box[0], g.half_box[0]);
-      if (g.periodic[1]) dy = min_image(dy, g.box[1], g.half_box[1]);
-      if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
-      d2 = dx * dx + dy * dy + dz * dz;
-    }
   }
   // |q| outside the box only occurs with free boundaries: waves that have
   // any take their maximum and one atomic (when it raises the running one)
   if (__any(qa > 0.0)) {
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) qa = fmax(qa, __shfl_xor(qa, off, kWave));
-    if ((threadIdx.x % kWave) == 0 && run) {
-      const unsigned long long qbits = (unsigned long long)__double_as_longlong(qa);
-      const unsigned long long qcur =
-          __hip_atomic_load(&ctl->qmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (qbits > qcur) atomicMax(&ctl->qmax_bits, qbits);
-    }
+    if ((threadIdx.x % kWave) == 0 && run) raise_max_bits(&ctl->qmax_bits, qa);
   }
-  // block maximum of the displacement, then one atomic per block and only
-  // when it raises the running maximum (non-negative doubles order like their
-  // bit patterns; a stale read can only be smaller than the true value, never
-  // skip a raise)
+  // block maximum of the displacement, then one atomic per block
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) d2 = fmax(d2, __shfl_xor(d2, off, kWave));
   __shared__ double wmax[kAuxMaxThreads / kWave];
@@ -220,10 +238,7 @@ __global__ void k_kick(PState s, const double* __restrict__ Fx, const double* __
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < nw; ++w) d2 = fmax(d2, wmax[w]);
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(d2);
-    const unsigned long long cur =
-        __hip_atomic_load(&ctl->dmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (run && bits > cur) atomicMax(&ctl->dmax_bits, bits);
+    if (run) raise_max_bits(&ctl->dmax_bits, d2);
   }
 }
 

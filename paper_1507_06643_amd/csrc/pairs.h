@@ -1423,23 +1423,105 @@ __global__ __launch_bounds__(kPairBlockMax) void k_pass_c(
   }
 }
 
+// Observables of a step (the energy of Sec. 2.1, the temperatures of
+// Sec. 2.2) are sums over particles of
+// U, K, sum eps, Px, Py, Pz, sum 1/T, |grad U|^2, Laplacian U, out-of-range count
+constexpr int kStatVals = 10;
+constexpr int kStatBad = 9;
+constexpr int kRecLen = 12;  // record: U K sum-eps E Px Py Pz Tkin Tint n |gradU|^2 lapU
+
+// The per-particle terms of those sums, defined once so that both producers
+// of the partial sums give the same bits.
+__device__ __forceinline__ double sq3(double x, double y, double z) {
+  return x * x + y * y + z * z;
+}
+__device__ __forceinline__ double kinetic(double px, double py, double pz, double mass) {
+  return sq3(px, py, pz) / (2.0 * mass);
+}
+// A value's fixed-point form; a value outside the range adds one to the
+// out-of-range count instead (the record is then NaN).
+__device__ __forceinline__ Fix stat_fix(double x, int& bad) {
+  if (fabs(x) < 0x1p30) return fix_of(x);
+  ++bad;
+  return fix_zero();
+}
+
+// The end of a step fused into the tile sweep 2 (single systems): each
+// tile's partial sums of the finished step's observables, and the next
+// step's kick and drift on the records it writes, with the maxima of that
+// step's list-build decision.  Kicking requires the sums (the separate
+// observables pass reads the records, which would then be kicked).
+struct StepTail {
+  const double* Fx;  // F of the step (pass A)
+  const double* Fy;
+  const double* Fz;
+  const double* Ui;  // per-particle shares of U and of its Laplacian
+  const double* Li;
+  const QRef* qref;  // positions at the last list build
+  BuildCtl* next;    // the next step's maxima; the step's end moves them into the build control
+  Fix* partials;     // kStatVals per slot, cleared by their reader
+  int nslots;        // tile t adds into slot t % nslots
+  int stats;         // add the partial sums
+  int kick;          // kick and drift the written records
+};
+
+// Slots of the partial sums: tiles in flight together (consecutive ones) add
+// into different slots, and the final pass reads two per lane.
+constexpr int kTailSlots = 128;
+
+// dst += v exactly, in any order of the adds to dst: the low words add
+// modulo 2^64, and the add that wraps them (known from the old value the
+// atomic returns) carries one into the high word.
+__device__ __forceinline__ void fix_atomic_add(Fix* dst, Fix v) {
+  unsigned long long* lo = reinterpret_cast<unsigned long long*>(&dst->lo);
+  unsigned long long* hi = reinterpret_cast<unsigned long long*>(&dst->hi);
+  const unsigned long long old = atomicAdd(lo, (unsigned long long)v.lo);
+  const unsigned long long carry = (old + (unsigned long long)v.lo < old) ? 1ull : 0ull;
+  const unsigned long long h = (unsigned long long)v.hi + carry;
+  if (h) atomicAdd(hi, h);
+}
+
+constexpr int kUniqWaves = 2 * kUniqTile / kWave;  // waves of a tile sweep's block
+
+// One sum over the wave's even lanes and another over its odd lanes (the
+// butterfly rounds never pair an even lane with an odd one); lanes 0 and 1
+// store them as values ke and ko of wave w.
+__device__ __forceinline__ void wave_pair_sums(Fix f, Fix (*out)[kUniqWaves], int ke, int ko,
+                                               int w) {
+#pragma unroll
+  for (int off = kWave / 2; off > 1; off >>= 1) {
+    Fix b;
+    b.lo = (uint64_t)__shfl_xor((long long)f.lo, off, kWave);
+    b.hi = (int64_t)__shfl_xor((long long)f.hi, off, kWave);
+    f = fix_add(f, b);
+  }
+  const int lane = threadIdx.x % kWave;
+  if (lane == 0) out[ke][w] = f;
+  if (lane == 1) out[ko][w] = f;
+}
+
 // Pass C over the tile's unique pairs: the reinjection term
 //   e_ij = -1/2 dp_ij . (h_i - h_j),   h = (p + dp/2)/m
 // is symmetric in (i, j), so a pair inside the tile adds the same e_ij to both
 // internal energies (eq. SER_eint_discretization); then p <- p + dp,
 // eps <- eps + d eps and the next 1/T_i as in k_pass_c (THETA = 1: the
-// surrogate network inside the pass).
+// surrogate network inside the pass); with a StepTail also the observables'
+// partial sums and the next step's kick.  Occupancy: 6 waves per SIMD fit
+// with the network (its registers are dead by the tail); the inline-EOS
+// instances need 5 to keep the tail out of scratch.
 template <bool BATCH, int PREC, int REGEN, int MODEL, int THETA>
-__global__ __launch_bounds__(2 * kUniqTile) void k_pass_c_uniq(
+__global__ __launch_bounds__(2 * kUniqTile)
+__attribute__((amdgpu_waves_per_eu(THETA ? 6 : 5, 8))) void k_pass_c_uniq(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
     const uint64_t* __restrict__ d_step, const Vec4* __restrict__ dpi,
     const H3* __restrict__ hv, int eos_inline, MlpDev m, int mlp_mode, Rec* __restrict__ out,
-    uint32_t* status) {
+    StepTail tail, uint32_t* status) {
   __shared__ unsigned long long acc[kUniqTile];  // two's-complement sums (modular adds)
   __shared__ float net_x[kUniqTile];
   __shared__ float net_y[kUniqTile];
-  __shared__ uint32_t first_s[2 * kUniqTile / kWave][32];
+  __shared__ uint32_t first_s[kUniqWaves][32];
   __shared__ double hs[3][kUniqTile];  // the tile's h: partners inside the tile read it here
+  __shared__ Fix stat_s[kStatVals][kUniqWaves];
   __shared__ uint32_t st_flag;
   for (int c = threadIdx.x; c < kUniqTile; c += blockDim.x) acc[c] = 0;
   const int64_t tb = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kUniqTile;
@@ -1575,11 +1657,13 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_c_uniq(
   // only e and i stay live across it; the new 1/T_i follows.
   const bool own = live && sub == 0;
   bool need_t = false;
+  // the particle's updated record, formed on both of its lanes; the first
+  // lane writes it
+  Rec o = a;
+  o.px = a.px + di.x;
+  o.py = a.py + di.y;
+  o.pz = a.pz + di.z;
   if (own) {
-    Rec o = a;
-    o.px = a.px + di.x;
-    o.py = a.py + di.y;
-    o.pz = a.pz + di.z;
     s.eps[i] = e;
     if (!(e > 0.0)) {
       atomicOr(status, ST_NEG_EINT);
@@ -1588,15 +1672,56 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_c_uniq(
     } else if (eos_inline) {
       o.invT = inv_temperature(P, e, status);
     }
-    out[i] = o;
   }
+  // The finished step's observables: the particle's values split over its
+  // two lanes (first lane: U, sum eps, Py, |grad U|^2, 1/T and the
+  // out-of-range count; second: K, Px, Pz, Laplacian U), each pair summed
+  // over the wave's first and second lanes apart.
+  int bad = 0;
+  double F[3] = {0.0, 0.0, 0.0};
+  const bool ev = sub == 0;
+  if (tail.stats) {  // uniform
+    if (live) {
+      F[0] = tail.Fx[i];
+      F[1] = tail.Fy[i];
+      F[2] = tail.Fz[i];
+    }
+    auto put = [&](double xe, double xo, int ke, int ko) {
+      const Fix f = live ? stat_fix(ev ? xe : xo, bad) : fix_zero();
+      wave_pair_sums(f, stat_s, ke, ko, w);
+    };
+    put(live && ev ? tail.Ui[i] : 0.0, kinetic(o.px, o.py, o.pz, P.mass), 0, 1);
+    put(e, o.px, 2, 3);
+    put(o.py, o.pz, 4, 5);
+    put(sq3(F[0], F[1], F[2]), live && !ev ? tail.Li[i] : 0.0, 7, 8);
+  }
+  if (tail.kick) {  // uniform: the next step's first half-kick and drift
+    double d2 = 0.0, qa = 0.0;
+    if (own) {
+      const GeoRef<BATCH> g = geo[BATCH ? a.rep : 0u];
+      kick_record(o, F, g, P, 1, tail.qref, i, d2, qa, status);
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) d2 = fmax(d2, __shfl_xor(d2, off, kWave));
+    if (threadIdx.x % kWave == 0) raise_max_bits(&tail.next->dmax_bits, d2);
+    if (__any(qa > 0.0)) {
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) qa = fmax(qa, __shfl_xor(qa, off, kWave));
+      if (threadIdx.x % kWave == 0) raise_max_bits(&tail.next->qmax_bits, qa);
+    }
+  }
+  // The record (with the old 1/T_i when the network follows) is written
+  // before the network, so that only e and i stay live across it; the new
+  // 1/T_i follows.
+  if (own) out[i] = o;
+  double inv_t = o.invT;
   if constexpr (THETA) {
     float y = 0.0f;
     if (mlp_mode != 0) {  // uniform
       if (sub == 0) net_x[pl] = mlp_input(m, e);
       __syncthreads();
       // wave w takes particles 32 w .. 32 w + 31 of the tile
-      const int w = threadIdx.x / kWave, col = threadIdx.x % 32;
+      const int col = threadIdx.x % 32;
       const float yw = mlp_wave32(m.wf, m.wb, net_x[32 * w + col]);
       if (threadIdx.x % kWave < 32) net_y[32 * w + col] = yw;
       __syncthreads();
@@ -1606,7 +1731,21 @@ __global__ __launch_bounds__(2 * kUniqTile) void k_pass_c_uniq(
       int it;
       const double th = theta_from_net(P, m, mlp_mode, e, y, it);
       if (!(th > 0.0) || !isfinite(th)) atomicOr(status, ST_EOS);
-      out[i].invT = 1.0 / th;
+      inv_t = 1.0 / th;
+      out[i].invT = inv_t;
+    }
+  }
+  if (tail.stats) {  // uniform: 1/T and the out-of-range count, then the block's sums
+    const Fix ft = live && ev ? stat_fix(inv_t, bad) : fix_zero();
+    const int nbad = bad + __shfl_xor(bad, 1, kWave);  // both lanes of the particle
+    wave_pair_sums(ev ? ft : Fix{(uint64_t)(uint32_t)nbad, 0ll}, stat_s, 6, kStatBad, w);
+    __syncthreads();
+    if (threadIdx.x < kStatVals) {
+      Fix t = fix_zero();
+#pragma unroll
+      for (int q = 0; q < kUniqWaves; ++q) t = fix_add(t, stat_s[threadIdx.x][q]);
+      const int64_t slot = (tb / kUniqTile) % tail.nslots;
+      fix_atomic_add(&tail.partials[slot * kStatVals + threadIdx.x], t);
     }
   }
 }
@@ -1646,16 +1785,13 @@ __global__ void k_inv_temperature(PState s, int64_t n, Phys P, uint32_t* status)
 }
 
 // ---------------------------------------------------------------------------
-// Observables: per-tile partial sums, then one block per replica, all in the
-// fixed-point form above, so a record does not depend on the particles'
-// memory order (list rebuild schedule, batching, resume).
+// Observables: per-tile partial sums (k_stats_tiles, or the end of the tile
+// sweep 2), then one block per replica, all in the fixed-point form above, so
+// a record does not depend on the particles' memory order (list rebuild
+// schedule, batching, resume).
 // Record: U, K, sum eps, E, Px, Py, Pz, T_kin, T_int, step.
 // ---------------------------------------------------------------------------
 constexpr int kStatThreads = 512;
-// U, K, sum eps, Px, Py, Pz, sum 1/T, |grad U|^2, Laplacian U, out-of-range count
-constexpr int kStatVals = 10;
-constexpr int kStatBad = 9;
-constexpr int kRecLen = 12;  // record: U K sum-eps E Px Py Pz Tkin Tint n |gradU|^2 lapU
 
 __global__ __launch_bounds__(kStatThreads) void k_stats_tiles(
     PState s, const double* __restrict__ Ui, const double* __restrict__ Li,
@@ -1668,15 +1804,12 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_tiles(
   for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
     const Rec& rc = s.r[i];
     const double px = rc.px, py = rc.py, pz = rc.pz;
-    const double p2 = px * px + py * py + pz * pz;
-    const double f2 = Fx[i] * Fx[i] + Fy[i] * Fy[i] + Fz[i] * Fz[i];
-    const double x[9] = {Ui[i], p2 / (2.0 * P.mass), s.eps[i], px, py, pz, rc.invT, f2, Li[i]};
+    const double x[9] = {Ui[i], kinetic(px, py, pz, P.mass), s.eps[i], px, py, pz, rc.invT,
+                         sq3(Fx[i], Fy[i], Fz[i]), Li[i]};
+    int bad = 0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      // values outside the fixed-point range are counted, and the record is NaN
-      if (fabs(x[k]) < 0x1p30) v[k] = fix_add(v[k], fix_of(x[k]));
-      else v[kStatBad] = fix_add(v[kStatBad], Fix{1ull, 0ll});
-    }
+    for (int k = 0; k < 9; ++k) v[k] = fix_add(v[k], stat_fix(x[k], bad));
+    v[kStatBad] = fix_add(v[kStatBad], Fix{(uint64_t)(uint32_t)bad, 0ll});
   }
   __shared__ Fix smem[kStatVals * (kStatThreads / kWave)];
   block_sum_fix<kStatVals>(v, smem);
@@ -1684,8 +1817,9 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_tiles(
     for (int k = 0; k < kStatVals; ++k) partials[blockIdx.x * kStatVals + k] = v[k];
 }
 
-// End of the step: count a list build, clear the build control, advance the
-// step and history counters (nothing when the status is raised).  The
+// End of the step: count a list build, reset the build control for the next
+// step, advance the step and history counters (nothing but the reset of the
+// next step's maxima when the status is raised).  The
 // counters' values were read before (no other block writes them).
 struct StepNow {
   uint64_t step;
@@ -1695,12 +1829,18 @@ struct StepNow {
 };
 
 __device__ __forceinline__ void step_end(const StepNow& c, uint64_t* d_step, int64_t* d_hist_count,
-                                         BuildCtl* ctl, unsigned long long* builds, int advance) {
+                                         BuildCtl* ctl, BuildCtl* next,
+                                         unsigned long long* builds, int advance) {
+  // the next step's maxima (nonzero when its kick ran at the end of this
+  // step's sweep 2) become the build control; the slot is left cleared
+  const unsigned long long nd = next->dmax_bits, nq = next->qmax_bits;
+  next->dmax_bits = 0ull;
+  next->qmax_bits = 0ull;
   if (c.failed) return;
   if (c.rebuilt) *builds = c.builds + 1ull;
-  ctl->dmax_bits = 0ull;
+  ctl->dmax_bits = nd;
   ctl->force = 0u;
-  ctl->qmax_bits = 0ull;
+  ctl->qmax_bits = nq;
   if (advance) {
     *d_step = c.step + 1;
     *d_hist_count = c.hist + 1;
@@ -1708,17 +1848,18 @@ __device__ __forceinline__ void step_end(const StepNow& c, uint64_t* d_step, int
 }
 
 // Per replica: sum the tile partials, write the record (and the history
-// row).  With `finish`, the last block to complete also ends the step: a
+// row); with `clear`, leave the partials zero (slots that the tile sweep 2
+// adds into).  With `finish`, the last block to complete also ends the step: a
 // ticket taken after each block's reads of the step and history counters
 // tells it that every other block is done with them.
 constexpr int kStatFinalThreads = kStatVals * kWave;  // one wave per recorded sum
 
 __global__ __launch_bounds__(kStatFinalThreads) void k_stats_final(
-    const Fix* __restrict__ partials, const int32_t* __restrict__ rep_tile0,
+    Fix* __restrict__ partials, int clear, const int32_t* __restrict__ rep_tile0,
     const Geo* __restrict__ geo, uint64_t* d_step, int advance,
     double* __restrict__ rec, double* __restrict__ hist, int64_t hist_cap,
     int64_t* d_hist_count, int nrep, int finish, uint32_t* ticket, BuildCtl* ctl,
-    unsigned long long* builds, double half_skin2, const uint32_t* status) {
+    BuildCtl* next, unsigned long long* builds, double half_skin2, const uint32_t* status) {
   const int r = blockIdx.x;
   const int t0 = rep_tile0[r], t1 = rep_tile0[r + 1];
   // the values the record and the end of the step need, requested before
@@ -1732,8 +1873,26 @@ __global__ __launch_bounds__(kStatFinalThreads) void k_stats_final(
   const double N = (double)geo[r].n;
   // wave k adds value k over the replica's tiles
   const int k0 = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  // eight partials per lane in flight, then (with clear) their slots zeroed
+  constexpr int kAhead = 8;
   Fix acc = fix_zero();
-  for (int t = t0 + lane; t < t1; t += kWave) acc = fix_add(acc, partials[t * kStatVals + k0]);
+  for (int tb = t0 + lane; tb < t1; tb += kAhead * kWave) {
+    Fix v[kAhead];
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      const int t = tb + u * kWave;
+      v[u] = t < t1 ? partials[t * kStatVals + k0] : fix_zero();
+    }
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) acc = fix_add(acc, v[u]);
+    if (clear) {
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const int t = tb + u * kWave;
+        if (t < t1) partials[t * kStatVals + k0] = fix_zero();
+      }
+    }
+  }
   acc = wave_sum_fix(acc);
   __shared__ Fix tot[kStatVals];
   if (lane == 0) tot[k0] = acc;
@@ -1769,7 +1928,7 @@ __global__ __launch_bounds__(kStatFinalThreads) void k_stats_final(
       if (gridDim.x > 1u) __threadfence();
       if (gridDim.x == 1u || atomicAdd(ticket, 1u) == gridDim.x - 1u) {
         if (gridDim.x > 1u) __threadfence();
-        step_end(now, d_step, d_hist_count, ctl, builds, advance);
+        step_end(now, d_step, d_hist_count, ctl, next, builds, advance);
         atomicExch(ticket, 0u);
       }
     }
@@ -1802,9 +1961,6 @@ __global__ void k_capture_e0(const double* __restrict__ rec, double* __restrict_
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < nrep) E0[r] = rec[r * kRecLen + 3];
 }
-
-// End of a step: count a list build, clear the build control, and (when
-// advancing) n <- n + 1 with one more history record (not after an error).
 
 // ---------------------------------------------------------------------------
 // Test hooks.

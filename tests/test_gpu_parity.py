@@ -316,6 +316,38 @@ def test_bit_reproducible_and_resumable(dp):
         s.close()
 
 
+@pytest.mark.parametrize("case", ["periodic", "free_x"])
+def test_step_end_in_sweep_two_equals_separate_passes(dp, case):
+    """Within one call of several steps the tile sweep 2 also takes the
+    step's observables and the next step's kick and drift; a call of one step
+    runs them as separate passes.  Twelve one-step calls and one twelve-step
+    call give the same states, records and list builds bit for bit (a
+    ragged last tile; with a free x boundary particles leave the box, which
+    the kick reports to the list build)."""
+    n = 6007
+    L = W.cubic_side(n)
+    box, per = [L] * 3, [1, 1, 1]
+    if case == "free_x":
+        box, per = [1.6 * L, L / 1.25, L / 1.3], [0, 1, 1]
+    q, p, e = W.equilibrium_state(n, box, seed=313)
+    cfg = _cfg(dp, n, box, periodic=per, dt=0.01, seed=5)
+    a = dp.System(cfg, q, p, e)
+    b = dp.System(cfg, q, p, e)
+    a.step(12)
+    for _ in range(12):
+        b.step(1)
+    sa, sb = _gpu_state(a), _gpu_state(b)
+    for x, y in zip(sa[:3], sb[:3]):
+        assert np.array_equal(x, y)
+    assert sa[3] == sb[3] == 12
+    assert np.array_equal(a.history(), b.history())
+    assert a.list_builds() == b.list_builds() > 1
+    if case == "free_x":
+        assert (np.abs(sa[0][:, 0] - box[0] / 2) > box[0] / 2).any()  # outside the box
+    a.close()
+    b.close()
+
+
 def test_trajectory_independent_of_skin(dp):
     """Neighbour lists built every step (skin 0) and Verlet lists with a skin
     rebuilt on displacement give the same trajectory bit for bit: the lists
