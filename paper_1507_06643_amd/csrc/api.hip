@@ -106,11 +106,12 @@ struct dpde_handle {
   int32_t* rep_tile0 = nullptr;
   int ntiles = 0;
   Fix* partials = nullptr;
-  // observables' partial sums added by the tile sweep 2 into kTailSlots
-  // slots (single systems)
+  // observables' partial sums added by the tile sweep 2 into slots
+  // (nslots_u per replica)
   Fix* partials_u = nullptr;
   int32_t* rep_tile0_u = nullptr;
   int nslots_u = 0;
+  int64_t min_rep_n = 0;  // particles of the smallest replica
   double* E0 = nullptr;   // per-replica target energy of the projection
   double* Li = nullptr;   // per-particle Laplacian share of U
   // Hybrid: domain of each particle, domain order, bucket offsets
@@ -420,15 +421,21 @@ int allocate(dpde_handle* h) {
     return rc;
   HIPCHK(hipMemcpy(h->tile_begin, tb.data(), tb.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(h->rep_tile0, rt.data(), rt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  if (!h->batch) {
-    // slots of the partial sums, zero between steps
-    const int32_t slots[2] = {0, (int32_t)std::min<int64_t>(kTailSlots, blocks(n, kUniqTile))};
-    if ((rc = dalloc(h, &h->partials_u, (size_t)slots[1] * kStatVals)) ||
-        (rc = dalloc(h, &h->rep_tile0_u, 2)))
+  {
+    // slots of the partial sums the tile sweep 2 adds into, zero between steps
+    h->nslots_u = h->batch ? kTailSlotsPerReplica
+                           : (int)std::min<int64_t>(kTailSlots, blocks(n, kUniqTile));
+    std::vector<int32_t> first(h->nrep + 1);
+    for (int r = 0; r <= h->nrep; ++r) first[r] = r * h->nslots_u;
+    const size_t total = (size_t)h->nrep * h->nslots_u * kStatVals;
+    if ((rc = dalloc(h, &h->partials_u, total)) || (rc = dalloc(h, &h->rep_tile0_u, first.size())))
       return rc;
-    HIPCHK(hipMemset(h->partials_u, 0, (size_t)slots[1] * kStatVals * sizeof(Fix)));
-    HIPCHK(hipMemcpy(h->rep_tile0_u, slots, sizeof(slots), hipMemcpyHostToDevice));
-    h->nslots_u = slots[1];
+    HIPCHK(hipMemset(h->partials_u, 0, total * sizeof(Fix)));
+    HIPCHK(hipMemcpy(h->rep_tile0_u, first.data(), first.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice));
+    h->min_rep_n = n;
+    for (int r = 0; r < h->nrep; ++r)
+      h->min_rep_n = std::min(h->min_rep_n, h->offsets[r + 1] - h->offsets[r]);
   }
   h->hist_cap = std::max<int64_t>(16, std::min<int64_t>(65536, kHistBytes / (h->nrep * kRecLen * 8)));
   if ((rc = dalloc(h, &h->hist, (size_t)h->hist_cap * h->nrep * kRecLen))) return rc;
@@ -466,11 +473,12 @@ bool uniq_form(const dpde_handle* h) {
          h->phys.potential == DPDE_POT_SOFT && h->phys.a < 1024.0 && h->phys.fix_ok;
 }
 
-// The end of the step in the tile sweep 2 (StepTail): for single systems
-// without the projection, whose observables are taken once, from the state
-// the sweep writes.  A batch's tiles can span two replicas.
+// The end of the step in the tile sweep 2 (StepTail): without the
+// projection, whose observables are taken once, from the state the sweep
+// writes; in a batch only when every replica fills a tile (a tile then spans
+// at most two replicas).
 bool fused_tail(const dpde_handle* h) {
-  return uniq_form(h) && !h->batch && !h->phys.project;
+  return uniq_form(h) && !h->phys.project && (!h->batch || h->min_rep_n >= kUniqTile);
 }
 
 // What the end of a step's sweep 2 does besides the sweep.

@@ -1446,11 +1446,12 @@ __device__ __forceinline__ Fix stat_fix(double x, int& bad) {
   return fix_zero();
 }
 
-// The end of a step fused into the tile sweep 2 (single systems): each
-// tile's partial sums of the finished step's observables, and the next
-// step's kick and drift on the records it writes, with the maxima of that
-// step's list-build decision.  Kicking requires the sums (the separate
-// observables pass reads the records, which would then be kicked).
+// The end of a step fused into the tile sweep 2: each tile's partial sums of
+// the finished step's observables, and the next step's kick and drift on the
+// records it writes, with the maxima of that step's list-build decision.
+// Kicking requires the sums (the separate observables pass reads the
+// records, which would then be kicked).  In a batch every replica holds at
+// least a tile's particles, so a tile spans at most two replicas.
 struct StepTail {
   const double* Fx;  // F of the step (pass A)
   const double* Fy;
@@ -1460,14 +1461,16 @@ struct StepTail {
   const QRef* qref;  // positions at the last list build
   BuildCtl* next;    // the next step's maxima; the step's end moves them into the build control
   Fix* partials;     // kStatVals per slot, cleared by their reader
-  int nslots;        // tile t adds into slot t % nslots
+  int slots;         // slots per replica: tile t adds into slot t % slots of its replica(s)
   int stats;         // add the partial sums
   int kick;          // kick and drift the written records
 };
 
 // Slots of the partial sums: tiles in flight together (consecutive ones) add
-// into different slots, and the final pass reads two per lane.
+// into different slots, and the final pass reads two per lane; a batch's
+// replicas take a few each.
 constexpr int kTailSlots = 128;
+constexpr int kTailSlotsPerReplica = 4;
 
 // dst += v exactly, in any order of the adds to dst: the low words add
 // modulo 2^64, and the add that wraps them (known from the old value the
@@ -1521,7 +1524,7 @@ __attribute__((amdgpu_waves_per_eu(THETA ? 6 : 5, 8))) void k_pass_c_uniq(
   __shared__ float net_y[kUniqTile];
   __shared__ uint32_t first_s[kUniqWaves][32];
   __shared__ double hs[3][kUniqTile];  // the tile's h: partners inside the tile read it here
-  __shared__ Fix stat_s[kStatVals][kUniqWaves];
+  __shared__ Fix stat_s[BATCH ? 2 : 1][kStatVals][kUniqWaves];
   __shared__ uint32_t st_flag;
   for (int c = threadIdx.x; c < kUniqTile; c += blockDim.x) acc[c] = 0;
   const int64_t tb = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kUniqTile;
@@ -1677,9 +1680,26 @@ __attribute__((amdgpu_waves_per_eu(THETA ? 6 : 5, 8))) void k_pass_c_uniq(
   // two lanes (first lane: U, sum eps, Py, |grad U|^2, 1/T and the
   // out-of-range count; second: K, Px, Pz, Laplacian U), each pair summed
   // over the wave's first and second lanes apart.
+  // A batch's tile: the replica of its first particle (set 0) and, when the
+  // last one differs, the next replica (set 1).
   int bad = 0;
   double F[3] = {0.0, 0.0, 0.0};
   const bool ev = sub == 0;
+  uint32_t rep0 = 0u, rep1 = 0u;
+  if constexpr (BATCH) {
+    if (tail.stats) {
+      rep0 = R[tb].rep;
+      rep1 = R[(tb + kUniqTile < n ? tb + kUniqTile : n) - 1].rep;
+    }
+  }
+  const bool two = rep1 != rep0;
+  const bool in0 = !BATCH || a.rep == rep0;
+  auto sums = [&](Fix f, int ke, int ko) {
+    wave_pair_sums(in0 ? f : fix_zero(), stat_s[0], ke, ko, w);
+    if constexpr (BATCH) {
+      if (two) wave_pair_sums(in0 ? fix_zero() : f, stat_s[1], ke, ko, w);
+    }
+  };
   if (tail.stats) {  // uniform
     if (live) {
       F[0] = tail.Fx[i];
@@ -1687,8 +1707,7 @@ __attribute__((amdgpu_waves_per_eu(THETA ? 6 : 5, 8))) void k_pass_c_uniq(
       F[2] = tail.Fz[i];
     }
     auto put = [&](double xe, double xo, int ke, int ko) {
-      const Fix f = live ? stat_fix(ev ? xe : xo, bad) : fix_zero();
-      wave_pair_sums(f, stat_s, ke, ko, w);
+      sums(live ? stat_fix(ev ? xe : xo, bad) : fix_zero(), ke, ko);
     };
     put(live && ev ? tail.Ui[i] : 0.0, kinetic(o.px, o.py, o.pz, P.mass), 0, 1);
     put(e, o.px, 2, 3);
@@ -1738,14 +1757,16 @@ __attribute__((amdgpu_waves_per_eu(THETA ? 6 : 5, 8))) void k_pass_c_uniq(
   if (tail.stats) {  // uniform: 1/T and the out-of-range count, then the block's sums
     const Fix ft = live && ev ? stat_fix(inv_t, bad) : fix_zero();
     const int nbad = bad + __shfl_xor(bad, 1, kWave);  // both lanes of the particle
-    wave_pair_sums(ev ? ft : Fix{(uint64_t)(uint32_t)nbad, 0ll}, stat_s, 6, kStatBad, w);
+    sums(ev ? ft : Fix{(uint64_t)(uint32_t)nbad, 0ll}, 6, kStatBad);
     __syncthreads();
-    if (threadIdx.x < kStatVals) {
+    if (threadIdx.x < (two ? 2 : 1) * kStatVals) {
+      const int set = threadIdx.x / kStatVals, k = threadIdx.x % kStatVals;
       Fix t = fix_zero();
 #pragma unroll
-      for (int q = 0; q < kUniqWaves; ++q) t = fix_add(t, stat_s[threadIdx.x][q]);
-      const int64_t slot = (tb / kUniqTile) % tail.nslots;
-      fix_atomic_add(&tail.partials[slot * kStatVals + threadIdx.x], t);
+      for (int q = 0; q < kUniqWaves; ++q) t = fix_add(t, stat_s[BATCH ? set : 0][k][q]);
+      const int64_t slot =
+          (int64_t)(set ? rep1 : rep0) * tail.slots + (tb / kUniqTile) % tail.slots;
+      fix_atomic_add(&tail.partials[slot * kStatVals + k], t);
     }
   }
 }

@@ -316,21 +316,37 @@ def test_bit_reproducible_and_resumable(dp):
         s.close()
 
 
-@pytest.mark.parametrize("case", ["periodic", "free_x"])
+@pytest.mark.parametrize("case", ["periodic", "free_x", "batch", "batch_small_replica"])
 def test_step_end_in_sweep_two_equals_separate_passes(dp, case):
     """Within one call of several steps the tile sweep 2 also takes the
     step's observables and the next step's kick and drift; a call of one step
     runs them as separate passes.  Twelve one-step calls and one twelve-step
     call give the same states, records and list builds bit for bit (a
     ragged last tile; with a free x boundary particles leave the box, which
-    the kick reports to the list build)."""
-    n = 6007
-    L = W.cubic_side(n)
-    box, per = [L] * 3, [1, 1, 1]
-    if case == "free_x":
-        box, per = [1.6 * L, L / 1.25, L / 1.3], [0, 1, 1]
-    q, p, e = W.equilibrium_state(n, box, seed=313)
-    cfg = _cfg(dp, n, box, periodic=per, dt=0.01, seed=5)
+    the kick reports to the list build; a batch's tiles span two replicas; a
+    replica smaller than a tile keeps the separate passes)."""
+    if case in ("periodic", "free_x"):
+        n = 6007
+        L = W.cubic_side(n)
+        box, per = [L] * 3, [1, 1, 1]
+        if case == "free_x":
+            box, per = [1.6 * L, L / 1.25, L / 1.3], [0, 1, 1]
+        q, p, e = W.equilibrium_state(n, box, seed=313)
+        cfg = _cfg(dp, n, box, periodic=per, dt=0.01, seed=5)
+    else:
+        sizes = [700, 1290, 533, 1800] if case == "batch" else [700, 100, 533]
+        cfg, qs, ps, es = [], [], [], []
+        for r, nr in enumerate(sizes):
+            L = W.cubic_side(nr)
+            box, per = [L] * 3, [1, 1, 1]
+            if r == 1 and case == "batch":
+                box, per = [1.6 * L, L / 1.25, L / 1.3], [0, 1, 1]
+            elif r == 1:
+                box = [3.95] * 3  # the smallest periodic box of three cells
+            q, p, e = W.equilibrium_state(nr, box, seed=700 + r)
+            cfg.append(_cfg(dp, nr, box, periodic=per, dt=0.01, seed=31 + r, replica=r))
+            qs.append(q); ps.append(p); es.append(e)
+        q, p, e = np.vstack(qs), np.vstack(ps), np.concatenate(es)
     a = dp.System(cfg, q, p, e)
     b = dp.System(cfg, q, p, e)
     a.step(12)
@@ -341,6 +357,7 @@ def test_step_end_in_sweep_two_equals_separate_passes(dp, case):
         assert np.array_equal(x, y)
     assert sa[3] == sb[3] == 12
     assert np.array_equal(a.history(), b.history())
+    assert np.array_equal(a.energies(), b.energies())
     assert a.list_builds() == b.list_builds() > 1
     if case == "free_x":
         assert (np.abs(sa[0][:, 0] - box[0] / 2) > box[0] / 2).any()  # outside the box
