@@ -172,7 +172,12 @@ int dpde_init(const dpde_params* params, const double* q, const double* p, const
  *   dp_ij = -gamma_ij chi v_ij dt + sigma sqrt(chi) G_ij^n sqrt(dt)   (eq. SER_p)
  *   d eps_i = -1/2 sum_j dp_ij . (v_ij + (dp_i - dp_j)/(2m))
  *                                     (eq. SER_eint_discretization)
- * with G_ij^n regenerated from (ids, n) in the second sweep (Sec. 3.2.1).
+ * with the increments dp_ij stored by the first sweep and read back by the
+ * second (DPDE_FLAG_REGENERATE_NOISE: G_ij^n regenerated from (ids, n) in the
+ * second sweep, as in Sec. 3.2.1; the same bits either way).  Between calls
+ * the state is the end of a step: states and records do not depend on how
+ * the steps are split over calls (inside a call the next step's kick may run
+ * at the end of the previous step's sweep 2).
  * Returns the first failure of the run (DPDE_ENEG_EINT, DPDE_EOVERFLOW,
  * DPDE_ENONFINITE, DPDE_EEOS); the state is then that of the failing step,
  * partially updated, and can still be read.
