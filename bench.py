@@ -270,9 +270,10 @@ ALGO_BYTES = {
     "pass_c": 24 + 24 + 8 + 4 + 24 + 8 + 24 + 8 + 8,  # q, p~, 1/T, id, dp_i, eps | p, eps, 1/T (132)
 }
 # The end of the step inside the tile sweep 2 (the observables' sums and the
-# next step's kick and drift): F, U and Laplacian shares, reference position
-# in | q out (88)
-TAIL_BYTES = 24 + 8 + 8 + 24 + 24
+# next step's kick and drift): F, U and Laplacian shares in | q out (64); the
+# build-time position the list-build decision compares with is the lists'
+# machinery, not counted
+TAIL_BYTES = 24 + 8 + 8 + 24
 
 
 def pair_kernel_bytes(name, tail=False):

@@ -79,7 +79,6 @@ struct dpde_handle {
 
   PState cur{}, alt{};
   double half_skin2 = 0.0, rs2 = 0.0;
-  QRef* qref = nullptr;
   QIdF* qid = nullptr;  // build-time FP32 positions and identifiers, cell order
   double box_max = 0.0;  // largest box side over the replicas
   uint32_t* slot = nullptr;  // memory index of each identifier row
@@ -357,7 +356,7 @@ int allocate(dpde_handle* h) {
   h->nl.stride = n;
   if ((rc = dalloc(h, &h->nl.idx, (size_t)h->phys.cap * n)) || (rc = dalloc(h, &h->nl.count, n)))
     return rc;
-  if ((rc = dalloc(h, &h->qref, n)) || (rc = dalloc(h, &h->qid, n)) ||
+  if ((rc = dalloc(h, &h->qid, n)) ||
       (rc = dalloc(h, &h->ctl, 1)) || (rc = dalloc(h, &h->ctl_next, 1)) ||
       (rc = dalloc(h, &h->builds, 1)) ||
       (rc = dalloc(h, &h->skin.idx, (size_t)h->phys.cap * n)) ||
@@ -391,7 +390,7 @@ int allocate(dpde_handle* h) {
     static const BuildCtl now{0ull, 1u, 0u};
     HIPCHK(hipMemcpy(h->always, &now, sizeof(BuildCtl), hipMemcpyHostToDevice));
   }
-  HIPCHK(hipMemset(h->qref, 0, n * sizeof(QRef)));
+  HIPCHK(hipMemset(h->qid, 0, n * sizeof(QIdF)));
   HIPCHK(hipMemset(h->ctl, 0, sizeof(BuildCtl)));
   HIPCHK(hipMemset(h->ctl_next, 0, sizeof(BuildCtl)));
   HIPCHK(hipMemset(h->builds, 0, sizeof(unsigned long long)));
@@ -495,7 +494,7 @@ void enqueue_bin(dpde_handle* h, int kick, bool with_kick = true) {
   if (with_kick)
     launch(h, "kick", h->batch ? k_kick<true> : k_kick<false>, blocks(n, b), b, h->cur,
            (const double*)h->Fx, (const double*)h->Fy, (const double*)h->Fz, n,
-           (const Geo*)h->geo, h->phys, kick, (const QRef*)h->qref, h->ctl, h->status);
+           (const Geo*)h->geo, h->phys, kick, (const QIdF*)h->qid, h->ctl, h->status);
   launch(h, "bin_key", h->batch ? k_bin_key<true> : k_bin_key<false>, blocks(n, b), b, h->cur, n,
          (const Geo*)h->geo, h->key, h->ticket, h->idk, h->cell_count, ctl, hs2, h->status);
   launch(h, "scan_tiles", k_scan_tiles, h->scan_tiles, kScanThreads, (const uint32_t*)h->cell_count,
@@ -510,7 +509,7 @@ void enqueue_bin(dpde_handle* h, int kick, bool with_kick = true) {
          (const uint32_t*)h->cell_start, (const uint32_t*)h->key, (const uint32_t*)h->idk, n,
          h->perm, ctl, hs2, (const uint32_t*)h->status);
   launch(h, "gather", h->batch ? k_gather<true> : k_gather<false>, blocks(n, b), b, h->cur, h->alt,
-         (const uint32_t*)h->perm, n, (const Geo*)h->geo, h->qref, h->qid, h->slot, ctl, hs2,
+         (const uint32_t*)h->perm, n, (const Geo*)h->geo, h->qid, h->slot, ctl, hs2,
          (const uint32_t*)h->status);
   launch(h, "copy_back", k_copy_back, blocks(n, b), b, h->alt, h->cur, n, ctl, hs2,
          (const uint32_t*)h->status);
@@ -642,7 +641,7 @@ void enqueue_fd_t(dpde_handle* h, TailMode tm) {
              h->phys, d_step, (const Vec4*)h->dpi, (const H3*)h->hv, inl, m, mode, h->alt.r,
              h->status);
     };
-    StepTail tail{h->Fx, h->Fy, h->Fz, h->Ui, h->Li, h->qref, h->ctl_next, h->partials_u,
+    StepTail tail{h->Fx, h->Fy, h->Fz, h->Ui, h->Li, h->qid, h->ctl_next, h->partials_u,
                   h->nslots_u, tm != kTailNone ? 1 : 0, tm == kTailStatsKick ? 1 : 0};
     auto pass_c_uniq = [&](auto kern) {
       launch(h, "pass_c_ser", kern, blocks(n, kUniqTile), 2 * kUniqTile, h->cur, h->nl, n,

@@ -51,12 +51,9 @@ __device__ __forceinline__ bool rebuild_now(const BuildCtl* c, double half_skin2
   return c->force != 0u || __longlong_as_double((long long)c->dmax_bits) > half_skin2;
 }
 
-struct alignas(32) QRef {
-  double x, y, z, pad;
-};
-
 // Position (FP32) and identifier of a particle in 16 bytes: what the list
-// build's candidate scans read (written by the reorder).  The FP32 distance
+// build's candidate scans read (written by the reorder), and the reference
+// of the kick's displacement test until the next build.  The FP32 distance
 // test is widened by a bound on its rounding error, so a list still holds
 // every pair within rc + skin; the exact r < rc filter of each step is FP64.
 struct alignas(16) QIdF {
@@ -148,14 +145,15 @@ __global__ void k_store_list_length(PState s, const Geo* __restrict__ geo, int64
 constexpr int kAuxMaxThreads = 1024;  // largest block of the per-particle kernels
 
 // First half of velocity-Verlet (Sec. 3.1) on one record: p += dt/2 F and
-// q += dt p / m (kick != 0), then the periodic wrap into [0, L).  Returns the
-// squared displacement since the last list build in d2 and, for a coordinate
-// outside [0, box) (free boundaries), the largest such |q| in qa; a
-// non-finite p or q raises the status.  The one definition of this
-// arithmetic: k_kick and the end of the tile sweep 2 both call it.
+// q += dt p / m (kick != 0), then the periodic wrap into [0, L).  Returns in
+// d2 the square of an upper bound on the displacement since the last list
+// build and, for a coordinate outside [0, box) (free boundaries), the
+// largest such |q| in qa; a non-finite p or q raises the status.  The one
+// definition of this arithmetic: k_kick and the end of the tile sweep 2
+// both call it.
 __device__ __forceinline__ void kick_record(Rec& rc, const double F[3], const Geo& g,
                                             const Phys& P, int kick,
-                                            const QRef* __restrict__ qref, int64_t i,
+                                            const QIdF* __restrict__ ref, int64_t i,
                                             double& d2, double& qa, uint32_t* status) {
   double q[3] = {rc.qx, rc.qy, rc.qz};
   if (kick) {
@@ -180,12 +178,20 @@ __device__ __forceinline__ void kick_record(Rec& rc, const double F[3], const Ge
 #pragma unroll
     for (int d = 0; d < 3; ++d)
       if (!(q[d] >= 0.0 && q[d] < g.box[d])) qa = fmax(qa, fabs(q[d]));
-    const QRef r0 = qref[i];
-    double dx = q[0] - r0.x, dy = q[1] - r0.y, dz = q[2] - r0.z;
+    // The reference is the build-time position rounded to FP32, each
+    // coordinate within 2^-24 |x| of the exact one, which is below
+    // 2^-23 |x_f| for its FP32 value x_f (2^-149 covers subnormals); the sum
+    // of those bounds and 2^-50 of the FP64 distance for its own rounding
+    // make d an upper bound on the true displacement.
+    const QIdF r0 = ref[i];
+    double dx = q[0] - (double)r0.x, dy = q[1] - (double)r0.y, dz = q[2] - (double)r0.z;
     if (g.periodic[0]) dx = min_image(dx, g.box[0], g.half_box[0]);
     if (g.periodic[1]) dy = min_image(dy, g.box[1], g.half_box[1]);
     if (g.periodic[2]) dz = min_image(dz, g.box[2], g.half_box[2]);
-    d2 = dx * dx + dy * dy + dz * dz;
+    const double slack =
+        0x1p-23 * ((double)fabsf(r0.x) + (double)fabsf(r0.y) + (double)fabsf(r0.z)) + 0x1p-147;
+    const double d = sqrt(dx * dx + dy * dy + dz * dz) * (1.0 + 0x1p-50) + slack;
+    d2 = d * d;
   }
 }
 
@@ -203,7 +209,7 @@ __device__ __forceinline__ void raise_max_bits(unsigned long long* where, double
 template <bool BATCH>
 __global__ void k_kick(PState s, const double* __restrict__ Fx, const double* __restrict__ Fy,
                        const double* __restrict__ Fz, int64_t n, const Geo* __restrict__ geo,
-                       Phys P, int kick, const QRef* __restrict__ qref, BuildCtl* ctl,
+                       Phys P, int kick, const QIdF* __restrict__ ref, BuildCtl* ctl,
                        uint32_t* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // no early return: every thread reaches the block barrier below (another
@@ -219,7 +225,7 @@ __global__ void k_kick(PState s, const double* __restrict__ Fx, const double* __
       F[1] = Fy[i];
       F[2] = Fz[i];
     }
-    kick_record(rc, F, g, P, kick, qref, i, d2, qa, status);
+    kick_record(rc, F, g, P, kick, ref, i, d2, qa, status);
     s.r[i] = rc;
   }
   // |q| outside the box only occurs with free boundaries: waves that have
@@ -428,11 +434,11 @@ __global__ void k_cell_rank(const uint32_t* __restrict__ bucket, const uint32_t*
 
 // ---- gather into the new order (list-build steps) ------------------------------
 // Writes the cell-ordered records into the spare buffer and the build-time
-// positions; k_copy_back then returns them to the working buffer, so the
-// buffer roles never depend on whether this step rebuilt.
+// positions (FP32); k_copy_back then returns them to the working buffer, so
+// the buffer roles never depend on whether this step rebuilt.
 template <bool BATCH>
 __global__ void k_gather(PState src, PState dst, const uint32_t* __restrict__ perm, int64_t n,
-                         const Geo* __restrict__ geo, QRef* __restrict__ qref,
+                         const Geo* __restrict__ geo,
                          QIdF* __restrict__ qid, uint32_t* __restrict__ slot, const BuildCtl* ctl,
                          double half_skin2, const uint32_t* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -442,7 +448,6 @@ __global__ void k_gather(PState src, PState dst, const uint32_t* __restrict__ pe
   const Rec rc = src.r[k];
   dst.r[i] = rc;
   dst.eps[i] = src.eps[k];
-  qref[i] = QRef{rc.qx, rc.qy, rc.qz, 0.0};
   qid[i] = QIdF{(float)rc.qx, (float)rc.qy, (float)rc.qz, rc.id};
   // memory index of every identifier row, for the neighbour-list build
   slot[(BATCH ? (uint32_t)geo[rc.rep].first : 0u) + rc.id] = (uint32_t)i;

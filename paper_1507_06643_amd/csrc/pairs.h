@@ -1458,7 +1458,7 @@ struct StepTail {
   const double* Fz;
   const double* Ui;  // per-particle shares of U and of its Laplacian
   const double* Li;
-  const QRef* qref;  // positions at the last list build
+  const QIdF* ref;   // positions at the last list build (FP32)
   BuildCtl* next;    // the next step's maxima; the step's end moves them into the build control
   Fix* partials;     // kStatVals per slot, cleared by their reader
   int slots;         // slots per replica: tile t adds into slot t % slots of its replica(s)
@@ -1718,7 +1718,7 @@ __attribute__((amdgpu_waves_per_eu(THETA ? 6 : 5, 8))) void k_pass_c_uniq(
     double d2 = 0.0, qa = 0.0;
     if (own) {
       const GeoRef<BATCH> g = geo[BATCH ? a.rep : 0u];
-      kick_record(o, F, g, P, 1, tail.qref, i, d2, qa, status);
+      kick_record(o, F, g, P, 1, tail.ref, i, d2, qa, status);
     }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) d2 = fmax(d2, __shfl_xor(d2, off, kWave));
