@@ -100,3 +100,52 @@ def test_margin_keeps_pairs_that_fp32_alone_loses():
     assert rf >= rc
     Q = 900.0 + rc
     assert rf < rc + 16.0 * U * (Q + rc)
+
+
+def _min_image64(d, L):
+    h = 0.5 * L
+    return np.where(d > h, d - L, np.where(d < -h, d + L, d))
+
+
+def test_displacement_bound_from_fp32_reference():
+    """The list-build decision measures a particle's displacement from its
+    build-time position kept in FP32 and widens it by 2^-23 (|x_f| + |y_f| +
+    |z_f|) plus 2^-50 of the FP64 distance; the result must never fall below
+    the true displacement from the exact FP64 position (the decision may only
+    err towards an extra build).  Positions fill a periodic box (wrapped,
+    some exactly at 0 or just below L, which FP32 may round up to L) and lie
+    far outside a free boundary."""
+    rng = np.random.default_rng(5)
+    for box, periodic, spread in (([70.5, 70.5, 70.5], (1, 1, 1), 0.2),
+                                  ([400.0, 20.0, 20.0], (0, 1, 1), 0.2),
+                                  ([3.95, 3.95, 3.95], (1, 1, 1), 0.2)):
+        box = np.asarray(box)
+        n = 200000
+        ref = rng.random((n, 3)) * box
+        ref[:100] = 0.0
+        ref[100:200] = np.nextafter(box, 0.0)
+        if not periodic[0]:
+            ref[200:400, 0] = rng.choice([-1.0, 1.0], 200) * rng.random(200) * 1e4
+        move = (rng.random((n, 3)) - 0.5) * 2.0 * spread
+        move[:1000] *= 1e-6  # displacements far below the FP32 rounding
+        q = ref + move
+        for k in range(3):
+            if periodic[k]:
+                q[:, k] = np.mod(q[:, k], box[k])
+        rf = _f32(ref)
+        d_true = np.zeros(n)
+        d_comp = np.zeros((n, 3))
+        for k in range(3):
+            dt = q[:, k] - ref[:, k]
+            dc = q[:, k] - rf[:, k].astype(np.float64)
+            if periodic[k]:
+                dt = _min_image64(dt, box[k])
+                dc = _min_image64(dc, box[k])
+            d_true += dt * dt
+            d_comp[:, k] = dc
+        d_true = np.sqrt(d_true)
+        slack = 2.0 ** -23 * np.abs(rf.astype(np.float64)).sum(axis=1) + 2.0 ** -147
+        bound = np.sqrt((d_comp * d_comp).sum(axis=1)) * (1.0 + 2.0 ** -50) + slack
+        assert (bound >= d_true).all()
+        # and the widening is small against any skin
+        assert slack.max() < 1e-4 * max(1.0, np.abs(ref).max() / 100.0)
