@@ -499,7 +499,6 @@ void enqueue_bin(dpde_handle* h, int kick, bool with_kick = true) {
          (const Geo*)h->geo, h->key, h->ticket, h->idk, h->cell_count, ctl, hs2, h->status);
   launch(h, "scan_tiles", k_scan_tiles, h->scan_tiles, kScanThreads, (const uint32_t*)h->cell_count,
          h->ncells, h->scan_tmp, ctl, hs2);
-  launch(h, "scan_tile_sums", k_scan_tile_sums, 1, 1024, h->scan_tmp, h->scan_tiles, ctl, hs2);
   launch(h, "scan_apply", k_scan_apply, h->scan_tiles, kScanThreads, h->cell_count, h->ncells,
          (const uint32_t*)h->scan_tmp, h->cell_start, ctl, hs2);
   launch(h, "scatter", k_scatter, blocks(n, b), b, (const uint32_t*)h->key,
@@ -511,14 +510,14 @@ void enqueue_bin(dpde_handle* h, int kick, bool with_kick = true) {
   launch(h, "gather", h->batch ? k_gather<true> : k_gather<false>, blocks(n, b), b, h->cur, h->alt,
          (const uint32_t*)h->perm, n, (const Geo*)h->geo, h->qid, h->slot, ctl, hs2,
          (const uint32_t*)h->status);
-  launch(h, "copy_back", k_copy_back, blocks(n, b), b, h->alt, h->cur, n, ctl, hs2,
-         (const uint32_t*)h->status);
   const int uniq = uniq_form(h) ? 1 : 0;
   const int pb = h->pair_block;
+  // the list build reads the reordered records from the spare buffer and
+  // returns them to the working one
   launch(h, "build_skin", h->batch ? k_build_skin<true> : k_build_skin<false>,
-         blocks(n * kSub, pb), pb,
-         h->cur, (const QIdF*)h->qid, (const uint32_t*)h->cell_start, n, (const Geo*)h->geo,
-         std::sqrt(h->rs2), h->box_max, h->skin, ctl, hs2, uniq, h->status);
+         blocks(n * kSub, pb), pb, h->alt, h->cur, (const QIdF*)h->qid,
+         (const uint32_t*)h->cell_start, n, (const Geo*)h->geo, std::sqrt(h->rs2), h->box_max,
+         h->skin, ctl, hs2, uniq, h->status);
   // the tile form adds every pair term in fixed point: its lists need no order
   if (!uniq)
     launch(h, "sort_skin", h->skin.cap > 96 ? k_sort_skin<128> : k_sort_skin<64>,
@@ -574,8 +573,6 @@ void enqueue_hybrid_ssa(dpde_handle* h) {
   // the scan writes dstart[0..ndoms), and dstart[ndoms] = n closes the last domain
   launch(h, "dom_scan_tiles", k_scan_tiles, h->dscan_tiles, kScanThreads,
          (const uint32_t*)h->dcount, h->ndoms, h->dscan_tmp, now, 0.0);
-  launch(h, "dom_scan_tile_sums", k_scan_tile_sums, 1, 1024, h->dscan_tmp, h->dscan_tiles, now,
-         0.0);
   launch(h, "dom_scan_apply", k_scan_apply, h->dscan_tiles, kScanThreads, h->dcount, h->ndoms,
          (const uint32_t*)h->dscan_tmp, h->dstart, now, 0.0);
   launch(h, "dom_scatter", k_scatter, blocks(n, b), b, (const uint32_t*)h->key,
@@ -587,8 +584,6 @@ void enqueue_hybrid_ssa(dpde_handle* h) {
   // poff[k] = first pair of sorted slot k, poff[n] = all pairs
   launch(h, "ssa_scan_tiles", k_scan_tiles, h->pscan_tiles, kScanThreads,
          (const uint32_t*)h->pcnt, n, h->pscan_tmp, now, 0.0);
-  launch(h, "ssa_scan_tile_sums", k_scan_tile_sums, 1, 1024, h->pscan_tmp, h->pscan_tiles, now,
-         0.0);
   launch(h, "ssa_scan_apply", k_scan_apply, h->pscan_tiles, kScanThreads, h->pcnt, n,
          (const uint32_t*)h->pscan_tmp, h->poff, now, 0.0);
   const int pb = h->pair_block;

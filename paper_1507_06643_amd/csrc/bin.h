@@ -352,34 +352,18 @@ __global__ void k_scan_tiles(const uint32_t* __restrict__ in, int64_t n,
   if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
 }
 
-// One block: exclusive scan of the tile sums in place (ntiles <= 1024*8);
-// the grand total goes to tile_sums[ntiles].
-__global__ void k_scan_tile_sums(uint32_t* tile_sums, int ntiles, const BuildCtl* ctl,
-                                 double half_skin2) {
-  if (!rebuild_now(ctl, half_skin2)) return;
-  const int per = (ntiles + blockDim.x - 1) / blockDim.x;
-  const int b = threadIdx.x * per;
-  uint32_t s = 0;
-  for (int k = 0; k < per; ++k)
-    if (b + k < ntiles) s += tile_sums[b + k];
-  __shared__ uint32_t smem[1024 / kWave + 1];
-  uint32_t total;
-  uint32_t run = block_exclusive_scan(s, smem, &total);
-  for (int k = 0; k < per; ++k)
-    if (b + k < ntiles) {
-      const uint32_t t = tile_sums[b + k];
-      tile_sums[b + k] = run;
-      run += t;
-    }
-  if (threadIdx.x == 0) tile_sums[ntiles] = total;
-}
-
 // out[c] = sum_{c' < c} in[c'] for c <= n; the histogram is cleared for the
-// next step.
+// next step.  Each block first adds the totals of the tiles before it (at
+// most 1024 * 8 tiles: 32 per thread), so no separate pass scans them.
 __global__ void k_scan_apply(uint32_t* __restrict__ in, int64_t n,
                              const uint32_t* __restrict__ tile_sums, uint32_t* __restrict__ out,
                              const BuildCtl* ctl, double half_skin2) {
   if (!rebuild_now(ctl, half_skin2)) return;
+  __shared__ uint32_t smem[kScanThreads / kWave + 1];
+  uint32_t before = 0;
+  for (unsigned t = threadIdx.x; t < blockIdx.x; t += blockDim.x) before += tile_sums[t];
+  uint32_t offset;
+  block_exclusive_scan(before, smem, &offset);
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint32_t s = 0;
@@ -388,9 +372,8 @@ __global__ void k_scan_apply(uint32_t* __restrict__ in, int64_t n,
     v[k] = (base + k < n) ? in[base + k] : 0u;
     s += v[k];
   }
-  __shared__ uint32_t smem[kScanThreads / kWave + 1];
   uint32_t total;
-  uint32_t run = block_exclusive_scan(s, smem, &total) + tile_sums[blockIdx.x];
+  uint32_t run = block_exclusive_scan(s, smem, &total) + offset;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     if (base + k < n) {
@@ -399,7 +382,7 @@ __global__ void k_scan_apply(uint32_t* __restrict__ in, int64_t n,
     }
     run += v[k];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tile_sums[gridDim.x];
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = offset + total;
 }
 
 // perm[offset[key] + ticket] = old slot.
@@ -434,8 +417,8 @@ __global__ void k_cell_rank(const uint32_t* __restrict__ bucket, const uint32_t*
 
 // ---- gather into the new order (list-build steps) ------------------------------
 // Writes the cell-ordered records into the spare buffer and the build-time
-// positions (FP32); k_copy_back then returns them to the working buffer, so
-// the buffer roles never depend on whether this step rebuilt.
+// positions (FP32); the list build then returns them to the working buffer,
+// so the buffer roles never depend on whether this step rebuilt.
 template <bool BATCH>
 __global__ void k_gather(PState src, PState dst, const uint32_t* __restrict__ perm, int64_t n,
                          const Geo* __restrict__ geo,
@@ -453,13 +436,5 @@ __global__ void k_gather(PState src, PState dst, const uint32_t* __restrict__ pe
   slot[(BATCH ? (uint32_t)geo[rc.rep].first : 0u) + rc.id] = (uint32_t)i;
 }
 
-__global__ void k_copy_back(PState src, PState dst, int64_t n, const BuildCtl* ctl,
-                            double half_skin2, const uint32_t* status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;
-  dst.r[i] = src.r[i];
-  dst.eps[i] = src.eps[i];
-}
 
 }  // namespace dpde

@@ -344,11 +344,14 @@ struct SkinList {
 // With `uniq` (the tile form) the list keeps only the pairs tile_listed
 // assigns to this particle, holds memory indices, and is not sorted: the
 // passes that read it add their pair terms in fixed point, in any order.
+// s holds the records the reorder has just written in cell order (its
+// candidates come from qid); the group's first lane also returns its
+// particle's record and internal energy to the working buffer `work`.
 template <bool BATCH>
 __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
-    PState s, const QIdF* __restrict__ qid, const uint32_t* __restrict__ start, int64_t n,
-    const Geo* __restrict__ geo, double rs, double box_max, SkinList sl, const BuildCtl* ctl,
-    double half_skin2, int uniq, uint32_t* status) {
+    PState s, PState work, const QIdF* __restrict__ qid, const uint32_t* __restrict__ start,
+    int64_t n, const Geo* __restrict__ geo, double rs, double box_max, SkinList sl,
+    const BuildCtl* ctl, double half_skin2, int uniq, uint32_t* status) {
   __shared__ uint32_t lst[kBuildLds * (kPairBlockMax / kSub)];
   __shared__ uint32_t runs_s[2 * kRunsMax * (kPairBlockMax / kSub)];
   if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;  // uniform
@@ -357,6 +360,10 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
   uint32_t* runs = runs_s + 2 * kRunsMax * L.pib;
   const int64_t i = L.i;
   const Rec* __restrict__ R = s.r;
+  if (L.sub == 0) {
+    work.r[i] = R[i];
+    work.eps[i] = s.eps[i];
+  }
   const double xi = R[i].qx, yi = R[i].qy, zi = R[i].qz;
   const GeoRef<BATCH> g = geo[BATCH ? R[i].rep : 0u];
   // FP32 test radius: rs plus a bound on the rounding of the FP32 distance
