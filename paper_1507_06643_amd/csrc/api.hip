@@ -93,7 +93,7 @@ struct dpde_handle {
   double* deps = nullptr;
   uint32_t* idk = nullptr;
   double* Ui = nullptr;
-  uint32_t *key = nullptr, *ticket = nullptr, *perm = nullptr;
+  uint32_t *key = nullptr, *ticket = nullptr;
   uint32_t* bucket = nullptr;  // cell buckets in ticket order (before the ranking)
   uint32_t *cell_count = nullptr, *cell_start = nullptr, *scan_tmp = nullptr;
   int scan_tiles = 0;
@@ -346,7 +346,7 @@ int allocate(dpde_handle* h) {
       (rc = dalloc(h, &h->idk, n)))
     return rc;
   if ((rc = dalloc(h, &h->key, n)) || (rc = dalloc(h, &h->ticket, n)) ||
-      (rc = dalloc(h, &h->perm, n)) || (rc = dalloc(h, &h->bucket, n)))
+      (rc = dalloc(h, &h->bucket, n)))
     return rc;
   if ((rc = dalloc(h, &h->cell_count, h->ncells)) || (rc = dalloc(h, &h->cell_start, h->ncells + 1)))
     return rc;
@@ -504,12 +504,10 @@ void enqueue_bin(dpde_handle* h, int kick, bool with_kick = true) {
   launch(h, "scatter", k_scatter, blocks(n, b), b, (const uint32_t*)h->key,
          (const uint32_t*)h->ticket, (const uint32_t*)h->cell_start, n, h->bucket, ctl, hs2,
          (const uint32_t*)h->status);
-  launch(h, "cell_rank", k_cell_rank, blocks(n, b), b, (const uint32_t*)h->bucket,
-         (const uint32_t*)h->cell_start, (const uint32_t*)h->key, (const uint32_t*)h->idk, n,
-         h->perm, ctl, hs2, (const uint32_t*)h->status);
-  launch(h, "gather", h->batch ? k_gather<true> : k_gather<false>, blocks(n, b), b, h->cur, h->alt,
-         (const uint32_t*)h->perm, n, (const Geo*)h->geo, h->qid, h->slot, ctl, hs2,
-         (const uint32_t*)h->status);
+  launch(h, "rank_gather", h->batch ? k_rank_gather<true> : k_rank_gather<false>, blocks(n, b),
+         b, h->cur, h->alt, (const uint32_t*)h->bucket, (const uint32_t*)h->cell_start,
+         (const uint32_t*)h->key, (const uint32_t*)h->idk, n, (const Geo*)h->geo, h->qid, h->slot,
+         ctl, hs2, (const uint32_t*)h->status);
   const int uniq = uniq_form(h) ? 1 : 0;
   const int pb = h->pair_block;
   // the list build reads the reordered records from the spare buffer and

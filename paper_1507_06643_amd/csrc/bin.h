@@ -396,13 +396,21 @@ __global__ void k_scatter(const uint32_t* __restrict__ key, const uint32_t* __re
   perm[start[key[i]] + ticket[i]] = (uint32_t)i;
 }
 
-// ---- digit 2: order each cell bucket by identifier ---------------------------
-// Out of place: one thread per bucket slot counts the smaller identifiers of
-// its cell's bucket, which is its place in the cell.
-__global__ void k_cell_rank(const uint32_t* __restrict__ bucket, const uint32_t* __restrict__ start,
-                            const uint32_t* __restrict__ key, const uint32_t* __restrict__ idk,
-                            int64_t n, uint32_t* __restrict__ perm, const BuildCtl* ctl,
-                            double half_skin2, const uint32_t* status) {
+// ---- digit 2 and the move into the new order (list-build steps) ------------
+// One thread per bucket slot counts the smaller identifiers of its cell's
+// bucket, which is its place in the cell, and writes its particle's record
+// and internal energy there in the spare buffer, with the build-time position
+// (FP32) and the memory index of the particle's identifier row (for the
+// neighbour-list build).  The list build then returns the records to the
+// working buffer, so the buffer roles never depend on whether this step
+// rebuilt.
+template <bool BATCH>
+__global__ void k_rank_gather(PState src, PState dst, const uint32_t* __restrict__ bucket,
+                              const uint32_t* __restrict__ start, const uint32_t* __restrict__ key,
+                              const uint32_t* __restrict__ idk, int64_t n,
+                              const Geo* __restrict__ geo, QIdF* __restrict__ qid,
+                              uint32_t* __restrict__ slot, const BuildCtl* ctl, double half_skin2,
+                              const uint32_t* status) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;
@@ -412,29 +420,12 @@ __global__ void k_cell_rank(const uint32_t* __restrict__ bucket, const uint32_t*
   const uint32_t my = idk[i];
   uint32_t r = 0;
   for (uint32_t m = b; m < e; ++m) r += idk[bucket[m]] < my ? 1u : 0u;
-  perm[b + r] = i;
+  const uint32_t p = b + r;
+  const Rec rc = src.r[i];
+  dst.r[p] = rc;
+  dst.eps[p] = src.eps[i];
+  qid[p] = QIdF{(float)rc.qx, (float)rc.qy, (float)rc.qz, rc.id};
+  slot[(BATCH ? (uint32_t)geo[rc.rep].first : 0u) + rc.id] = p;
 }
-
-// ---- gather into the new order (list-build steps) ------------------------------
-// Writes the cell-ordered records into the spare buffer and the build-time
-// positions (FP32); the list build then returns them to the working buffer,
-// so the buffer roles never depend on whether this step rebuilt.
-template <bool BATCH>
-__global__ void k_gather(PState src, PState dst, const uint32_t* __restrict__ perm, int64_t n,
-                         const Geo* __restrict__ geo,
-                         QIdF* __restrict__ qid, uint32_t* __restrict__ slot, const BuildCtl* ctl,
-                         double half_skin2, const uint32_t* status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;
-  const uint32_t k = perm[i];
-  const Rec rc = src.r[k];
-  dst.r[i] = rc;
-  dst.eps[i] = src.eps[k];
-  qid[i] = QIdF{(float)rc.qx, (float)rc.qy, (float)rc.qz, rc.id};
-  // memory index of every identifier row, for the neighbour-list build
-  slot[(BATCH ? (uint32_t)geo[rc.rep].first : 0u) + rc.id] = (uint32_t)i;
-}
-
 
 }  // namespace dpde
