@@ -976,8 +976,8 @@ __device__ __forceinline__ void pair_conservative(const Phys& P, double dx, doub
 // the Laplacian shares, which grow as 1/r, in two words: the term on the grid
 // 2^-20 and its remainder on 2^-50.  Mode 1 also applies p += dt/2 F (end of
 // velocity-Verlet).
-constexpr int kTileListLds = 32;  // work-list entries per particle staged in LDS
-constexpr int kTileSkinLds = 32;  // skin-list entries per particle staged in LDS
+constexpr int kTileListLds = 16;  // work-list entries per particle staged in LDS
+constexpr int kTileSkinLds = 28;  // skin-list entries per particle staged in LDS (a block loads every row)
 
 template <bool BATCH, int PREC>
 __global__ __launch_bounds__(kSub * kUniqTile) __attribute__((amdgpu_waves_per_eu(BATCH ? 4 : 6, 8))) void k_pass_a_uniq(
