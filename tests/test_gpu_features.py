@@ -449,6 +449,38 @@ def test_negative_internal_energy_reported(dp):
     s.close()
 
 
+def test_handle_steps_on_after_a_failed_step(dp):
+    """A call that fails mid-way (an internal energy driven below zero, the
+    next kick possibly already done at the end of sweep 2) leaves nothing
+    behind: after set_state the handle steps in one call exactly like a fresh
+    handle from the same state, up to the step before the failure."""
+    # a heat capacity of 20 with strong friction: the CPU oracle completes
+    # four steps from this state before an internal energy turns negative
+    n = 2000
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=71, eps0=20.0)
+    cfg = dp.Config(n=n, box=[L] * 3, cv=20.0, gamma=20.0, dt=0.02)
+    s = dp.System(cfg, q, p, e)
+    assert s.step_raw(30) == dp._lib.DPDE_ENEG_EINT
+    failed_at = s.get_state()[3]
+    print("steps completed before the failure:", failed_at)
+    assert failed_at >= 3
+    k = failed_at - 1
+    s.set_state(q, p, e, 0)
+    s.history()
+    s.step(k)
+    f = dp.System(cfg, q, p, e)
+    f.history()
+    f.step(k)
+    a, b = _gpu_state(s), _gpu_state(f)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    assert a[3] == b[3] == k
+    assert np.array_equal(s.history(), f.history())
+    s.close()
+    f.close()
+
+
 def test_invalid_inputs_rejected(dp):
     n = 300
     L = W.cubic_side(n)
