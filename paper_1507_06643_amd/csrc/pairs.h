@@ -1684,8 +1684,8 @@ __attribute__((amdgpu_waves_per_eu(THETA ? 6 : 5, 8))) void k_pass_c_uniq(
     }
   }
   // The finished step's observables: the particle's values split over its
-  // two lanes (first lane: U, sum eps, Py, |grad U|^2, 1/T and the
-  // out-of-range count; second: K, Px, Pz, Laplacian U), each pair summed
+  // two lanes (first lane: U, sum eps, Py, |grad U|^2, 1/T; second: K, Px,
+  // Pz, Laplacian U and the particle's out-of-range count), each pair summed
   // over the wave's first and second lanes apart.
   // A batch's tile: the replica of its first particle (set 0) and, when the
   // last one differs, the next replica (set 1).
@@ -1707,12 +1707,12 @@ __attribute__((amdgpu_waves_per_eu(THETA ? 6 : 5, 8))) void k_pass_c_uniq(
       if (two) wave_pair_sums(in0 ? fix_zero() : f, stat_s[1], ke, ko, w);
     }
   };
+  if ((tail.stats || tail.kick) && live) {
+    F[0] = tail.Fx[i];
+    F[1] = tail.Fy[i];
+    F[2] = tail.Fz[i];
+  }
   if (tail.stats) {  // uniform
-    if (live) {
-      F[0] = tail.Fx[i];
-      F[1] = tail.Fy[i];
-      F[2] = tail.Fz[i];
-    }
     auto put = [&](double xe, double xo, int ke, int ko) {
       sums(live ? stat_fix(ev ? xe : xo, bad) : fix_zero(), ke, ko);
     };
