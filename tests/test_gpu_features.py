@@ -420,6 +420,35 @@ def test_batched_learned_eos_replicas_match_single_systems(dp, eos_system, preci
     b.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_step_end_in_sweep_two_with_the_surrogate(dp, eos_system, precision):
+    """With the learned EOS the network runs inside sweep 2, before the
+    step's end that a call of several steps also does there: eight one-step
+    calls (separate kick and observables passes) and one eight-step call
+    give the same states and records bit for bit, in FP64 and FP32."""
+    eos_system.mlp_train(nsamples=200000, iters=300, batch=4096, lr=3e-3, seed=9)
+    w, norm = eos_system.mlp_get()
+    n = 3001
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=4100, eps0=25.0)
+    cfg = dp.Config(n=n, box=[L] * 3, dt=0.005, eos=dp.EOS_EINSTEIN, theta_mode=dp.THETA_MLP,
+                    precision=precision, seed=17)
+    a = dp.System(cfg, q, p, e)
+    b = dp.System(cfg, q, p, e)
+    for s_ in (a, b):
+        s_.mlp_set(w, norm)
+        s_.history()
+    a.step(8)
+    for _ in range(8):
+        b.step(1)
+    sa, sb = _gpu_state(a), _gpu_state(b)
+    for x, y in zip(sa[:3], sb[:3]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.history(), b.history())
+    a.close()
+    b.close()
+
+
 # ---------------------------------------------------------------------------
 # SEM (Sec. 3.1.1): one step against the oracle's SEM.
 # ---------------------------------------------------------------------------
