@@ -836,13 +836,20 @@ bool shape_valid(const dpde_shape& sh) {
 
 // Shape fields of the handle (host side; the caller uploads the geometry
 // and rebuilds the lists where the order or the form changed).
+// A captured step graph holds its kernels' arguments (launch shapes, the
+// physics block, the surrogate's mode and normalisation): whatever changes
+// them drops it, and the next dpde_step_graph captures again.
+void drop_graph(dpde_handle* h) {
+  if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
+  if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+}
+
 void put_shape(dpde_handle* h, const dpde_shape& sh) {
   h->pair_block = sh.pair_block;
   h->aux_block = sh.aux_block;
   h->pairs_once = sh.pairs == DPDE_PAIRS_ONCE_PER_TILE;
   for (Geo& g : h->geo_h) g.oblk = sh.order_block;
-  if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
-  if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+  drop_graph(h);
 }
 
 dpde_shape get_shape(const dpde_handle* h) {
@@ -1423,6 +1430,7 @@ int dpde_mlp_train(dpde_handle* h, const dpde_mlp_cfg* cfg, float* loss_curve) {
   int rc = mlp_train(h->mlp, h->stream, h->phys, *cfg, loss_curve, err);
   if (rc) return fail(rc, "%s", err.c_str());
   mlp_attach(h->mlp, h->phys);
+  drop_graph(h);
   return DPDE_OK;
 }
 
@@ -1439,6 +1447,7 @@ int dpde_mlp_set(dpde_handle* h, const float* weights, const double* norm4) {
   int rc = mlp_set(h->mlp, h->phys, weights, norm4, err);
   if (rc) return fail(rc, "%s", err.c_str());
   mlp_attach(h->mlp, h->phys);
+  drop_graph(h);
   return DPDE_OK;
 }
 

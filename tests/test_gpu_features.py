@@ -449,6 +449,36 @@ def test_step_end_in_sweep_two_with_the_surrogate(dp, eos_system, precision):
     b.close()
 
 
+def test_graph_follows_new_surrogate_weights(dp, eos_system):
+    """A captured step graph holds the surrogate's mode and normalisation as
+    kernel arguments: a graph captured before the network had weights (the
+    inversion by Newton) is dropped when weights are set, and the replays
+    that follow (captured again) step like eager steps with the network,
+    bit for bit."""
+    eos_system.mlp_train(nsamples=200000, iters=300, batch=4096, lr=3e-3, seed=10)
+    w, norm = eos_system.mlp_get()
+    n = 3001
+    L = W.cubic_side(n)
+    q, p, e = W.equilibrium_state(n, [L] * 3, seed=4200, eps0=25.0)
+    cfg = dp.Config(n=n, box=[L] * 3, dt=0.005, eos=dp.EOS_EINSTEIN, theta_mode=dp.THETA_MLP,
+                    seed=23)
+    g = dp.System(cfg, q, p, e)
+    g.step_graph(2, 1)  # captured without weights
+    g.mlp_set(w, norm)
+    g.step_graph(2, 2)
+    a = dp.System(cfg, q, p, e)
+    a.step(2)
+    a.mlp_set(w, norm)
+    a.step(2)
+    a.step(2)
+    sg, sa = _gpu_state(g), _gpu_state(a)
+    for x, y in zip(sg[:3], sa[:3]):
+        assert np.array_equal(x, y)
+    assert sg[3] == sa[3] == 6
+    g.close()
+    a.close()
+
+
 # ---------------------------------------------------------------------------
 # SEM (Sec. 3.1.1): one step against the oracle's SEM.
 # ---------------------------------------------------------------------------
