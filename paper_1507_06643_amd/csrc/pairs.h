@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kPairBlockMax) void k_build_skin(
     work.eps[i] = s.eps[i];
   }
   const double xi = R[i].qx, yi = R[i].qy, zi = R[i].qz;
-  const GeoRef<BATCH> g = geo[BATCH ? R[i].rep : 0u];
+  const Geo& g = geo[BATCH ? R[i].rep : 0u];
   // FP32 test radius: rs plus a bound on the rounding of the FP32 distance
   // (conversions of coordinates up to Q = max(|q|, box), their difference,
   // the minimum image and the squared sum stay below 8 2^-24 (Q + rs); twice
