@@ -252,8 +252,9 @@ int dpde_energies_batch(dpde_handle* h, double* out);
 /*
  * Capture nsteps steps (even, > 0) into one HIP graph and replay it reps
  * times: equivalent to dpde_step(h, nsteps * reps), with one launch per
- * replay.  The graph is cached per nsteps and rebuilt when nsteps or the
- * tuning changes.
+ * replay.  The graph is cached per nsteps and captured again when nsteps,
+ * the launch shape or the surrogate's weights (dpde_mlp_set, dpde_mlp_train)
+ * change.
  */
 int dpde_step_graph(dpde_handle* h, int64_t nsteps, int64_t reps);
 
