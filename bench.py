@@ -647,7 +647,10 @@ def main():
     d = pair_roofs[dom]
     roof = {"kernel": dom, "symbol": symbols[dom], "bound": "hbm", "achieved": d["hbm_GBps"],
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["hbm_frac"],
-            "traffic": d["counter_bytes"], "bytes_per_particle": d["algorithmic_bytes_per_particle"],
+            "traffic": d["counter_bytes"],
+            # the kernel's measured HBM traffic (counters) against the same peak
+            "traffic_frac": None if d["counter_GBps"] is None else d["counter_GBps"] / HBM_PEAK_GBS,
+            "bytes_per_particle": d["algorithmic_bytes_per_particle"],
             "n": n, "avg_launch_ms": d["avg_launch_ms"], "step_end_in_sweep_2": tail,
             "mean_neighbours": nbar,
             "mean_work_list": nwork, "skin_list_estimate": nskin, "pair_kernels": pair_roofs}
