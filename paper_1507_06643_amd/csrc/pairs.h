@@ -1180,8 +1180,14 @@ __device__ __forceinline__ int overflow_owner(const uint32_t* first, uint32_t x)
   return lo;
 }
 
+// Occupancy: the batched FP64 vector-model instance, which holds its
+// replica's geometry per lane, fits 6 waves per SIMD only when asked (79
+// VGPRs, no spills); asked the same, the FP32 and projected-model instances
+// would spill, and keep the compiler's choice.
 template <bool BATCH, int PREC, int MODEL>
-__global__ __launch_bounds__(2 * kUniqTile) void k_pass_b_uniq(
+__global__ __launch_bounds__(2 * kUniqTile)
+__attribute__((amdgpu_waves_per_eu(BATCH && PREC == PREC_F64 && MODEL == 0 ? 6 : 1, 8)))
+void k_pass_b_uniq(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
     const uint64_t* __restrict__ d_step, Vec4* __restrict__ dpi, H3* __restrict__ hv, int store,
     uint32_t* status) {
@@ -1516,12 +1522,15 @@ __device__ __forceinline__ void wave_pair_sums(Fix f, Fix (*out)[kUniqWaves], in
 // internal energies (eq. SER_eint_discretization); then p <- p + dp,
 // eps <- eps + d eps and the next 1/T_i as in k_pass_c (THETA = 1: the
 // surrogate network inside the pass); with a StepTail also the observables'
-// partial sums and the next step's kick.  Occupancy: 6 waves per SIMD fit
-// with the network (its registers are dead by the tail); the inline-EOS
-// instances need 5 to keep the tail out of scratch.
+// partial sums and the next step's kick.  Occupancy, with stored
+// increments: 6 waves per SIMD fit with the network (its registers are dead
+// by the tail); the inline-EOS instances need 5 to keep the tail out of
+// scratch.  The instances that regenerate the noise hold the pair term's
+// registers as well and keep the compiler's choice (asked for 5 or 6 they
+// spill).
 template <bool BATCH, int PREC, int REGEN, int MODEL, int THETA>
 __global__ __launch_bounds__(2 * kUniqTile)
-__attribute__((amdgpu_waves_per_eu(THETA ? 6 : 5, 8))) void k_pass_c_uniq(
+__attribute__((amdgpu_waves_per_eu(REGEN ? 1 : (THETA ? 6 : 5), 8))) void k_pass_c_uniq(
     PState s, NList nl, int64_t n, const Geo* __restrict__ geo, Phys P,
     const uint64_t* __restrict__ d_step, const Vec4* __restrict__ dpi,
     const H3* __restrict__ hv, int eos_inline, MlpDev m, int mlp_mode, Rec* __restrict__ out,
