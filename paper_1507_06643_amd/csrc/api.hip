@@ -271,6 +271,7 @@ int geometry(const dpde_params* P, Geo& g) {
     g.periodic[d] = P->periodic[d];
   }
   g.oblk = 1;
+  g.oblk_inv = 1.0f;
   g.key0 = (uint32_t)P->seed;
   g.key1 = (uint32_t)(P->seed >> 32) ^ P->replica;
   for (int d = 0; d < 3; ++d) {
@@ -848,7 +849,10 @@ void put_shape(dpde_handle* h, const dpde_shape& sh) {
   h->pair_block = sh.pair_block;
   h->aux_block = sh.aux_block;
   h->pairs_once = sh.pairs == DPDE_PAIRS_ONCE_PER_TILE;
-  for (Geo& g : h->geo_h) g.oblk = sh.order_block;
+  for (Geo& g : h->geo_h) {
+    g.oblk = sh.order_block;
+    g.oblk_inv = 1.0f / (float)sh.order_block;
+  }
   drop_graph(h);
 }
 

@@ -257,7 +257,7 @@ __device__ __forceinline__ bool scan_candidates(const Lanes& L, const Geo& g,
         // blocked order: an x range is one run per cell block it crosses
         auto xrun = [&](int a, int b, uint32_t image) {
           for (int x = a; x <= b;) {
-            const int e = min(b, (x / B) * B + B - 1);
+            const int e = min(b, block_of(x, g) * B + B - 1);
             const int64_t k0 = g.cell_base + cell_key(g, x, y, z);
             add(start[k0], start[k0 + (e - x) + 1], image);
             x = e + 1;
