@@ -149,3 +149,17 @@ def test_displacement_bound_from_fp32_reference():
         assert (bound >= d_true).all()
         # and the widening is small against any skin
         assert slack.max() < 1e-4 * max(1.0, np.abs(ref).max() / 100.0)
+
+
+def test_block_quotient_from_fp32_reciprocal_is_exact():
+    """The list build takes a cell's block coordinate c / B (B the block
+    edge, 1 to 8) as trunc(fma(c, r, r / 2)) with r = 1/B rounded to FP32.
+    The fused multiply-add rounds r (c + 1/2) once to FP32; for c below 2^21
+    that product has at most 46 significant bits, so FP64 holds it exactly
+    and one cast to FP32 reproduces the kernel's rounding.  Checked here for
+    every c below 2^21, above the largest cell index the host admits."""
+    c = np.arange(1 << 21, dtype=np.int64)
+    for b in range(1, 9):
+        r = np.float32(1.0) / np.float32(b)
+        q = (np.float64(r) * (c.astype(np.float64) + 0.5)).astype(np.float32)
+        assert (q.astype(np.int64) == c // b).all(), b
