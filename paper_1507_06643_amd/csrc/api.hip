@@ -533,7 +533,10 @@ void enqueue_forces(dpde_handle* h, int mode) {
              (const Geo*)h->geo, h->phys, mode, h->Fx, h->Fy, h->Fz, h->Ui, h->Li, h->skin,
              h->nl, h->status);
     };
-    if (h->batch) {
+    if (h->batch && h->min_rep_n < kWave / kSub) {  // a wave may meet more than two replicas
+      if (h->phys.precision == DPDE_FP32) go(k_pass_a_uniq<true, PREC_F32, true>);
+      else go(k_pass_a_uniq<true, PREC_F64, true>);
+    } else if (h->batch) {
       if (h->phys.precision == DPDE_FP32) go(k_pass_a_uniq<true, PREC_F32>);
       else go(k_pass_a_uniq<true, PREC_F64>);
     } else {

@@ -979,8 +979,13 @@ __device__ __forceinline__ void pair_conservative(const Phys& P, double dx, doub
 constexpr int kTileListLds = 16;  // work-list entries per particle staged in LDS
 constexpr int kTileSkinLds = 28;  // skin-list entries per particle staged in LDS (a block loads every row)
 
-template <bool BATCH, int PREC>
-__global__ __launch_bounds__(kSub * kUniqTile) __attribute__((amdgpu_waves_per_eu(BATCH ? 4 : 6, 8))) void k_pass_a_uniq(
+// In a batch a wave walks its particles one replica at a time, with that
+// replica's geometry uniform (in scalar registers).  Replicas of at least a
+// wave's 16 particles (SMALL false) let a wave meet at most two, walked in
+// straight-line code; with smaller ones (SMALL) a loop takes as many as the
+// wave meets, at the cost of registers.
+template <bool BATCH, int PREC, bool SMALL = false>
+__global__ __launch_bounds__(kSub * kUniqTile) __attribute__((amdgpu_waves_per_eu(BATCH && SMALL ? 4 : 6, 8))) void k_pass_a_uniq(
     PState s, int64_t n, const Geo* __restrict__ geo, Phys P, int mode,
     double* __restrict__ Fx, double* __restrict__ Fy, double* __restrict__ Fz,
     double* __restrict__ Ui, double* __restrict__ Li, SkinList sl, NList nl, uint32_t* status) {
@@ -1016,24 +1021,25 @@ __global__ __launch_bounds__(kSub * kUniqTile) __attribute__((amdgpu_waves_per_e
   const bool live = i < n;
   const Rec* __restrict__ R = s.r;
   double xi = 0.0, yi = 0.0, zi = 0.0;
-  uint32_t ns = 0;
-  bool away = true;
+  uint32_t ns = 0, rep = 0u;
   if (live) {
     xi = R[i].qx;
     yi = R[i].qy;
     zi = R[i].qz;
     ns = sl.count[i];
-    const GeoRef<BATCH> g = geo[BATCH ? R[i].rep : 0u];
-    away = away_from_faces(g, P, xi, yi, zi);
+    if constexpr (BATCH) rep = R[i].rep;
   }
-  const bool mi = !__all(away);  // uniform in the wave
   const uint32_t cap = (uint32_t)P.cap;
   long long XF0 = 0, XF1 = 0, XF2 = 0, XU = 0, XLh = 0, XLl = 0;  // raw fixed-point words
   long long terms = 0;
   uint32_t hi_l = 0u;
   uint32_t nn = 0;
-  if (live) {
-    const GeoRef<BATCH> g = geo[BATCH ? R[i].rep : 0u];
+  // The walk of the lanes in `mine` over their lists, with the geometry g of
+  // their replica uniform in the wave (every pair term is a fixed-point sum,
+  // so splitting a wave between replicas leaves the results' bits alone).
+  auto walk = [&](const Geo& g, bool mine) {
+    const bool mi = !__all(!mine || away_from_faces(g, P, xi, yi, zi));  // uniform in the wave
+    if (!mine) return;
     // one trip of the group over entries base + sub (uniform in the group)
     auto trip = [&](uint32_t k, uint32_t j, double qjx, double qjy, double qjz) {
       bool take = false;
@@ -1114,6 +1120,26 @@ __global__ __launch_bounds__(kSub * kUniqTile) __attribute__((amdgpu_waves_per_e
       }
       trip(k, j, qjx, qjy, qjz);
     }
+  };
+  if constexpr (BATCH && SMALL) {
+    bool todo = live;
+    while (__any(todo)) {
+      const uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)rep, __builtin_ctzll(__ballot(todo)));
+      const bool mine = todo && rep == r;
+      walk(geo[r], mine);
+      todo = todo && !mine;
+    }
+  } else if constexpr (BATCH) {
+    // the wave's first replica, then the next one if the wave reaches it
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)rep);
+    walk(geo[r0], live && rep == r0);
+    const bool rest = live && rep != r0;
+    if (__any(rest)) {
+      const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)rep, __builtin_ctzll(__ballot(rest)));
+      walk(geo[r1], rest);
+    }
+  } else {
+    walk(geo[0], live);
   }
   const long long m = terms * kFixMagicBits;
   XF0 -= m;

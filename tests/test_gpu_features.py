@@ -305,6 +305,34 @@ def test_batched_replicas_match_single_systems(dp):
     b.close()
 
 
+def test_batched_replicas_smaller_than_a_wave_match_single_systems(dp):
+    """Replicas of fewer particles than a force-pass wave serves (16), so that
+    one wave meets up to five replicas, next to larger ones: each replica
+    still equals its own single system bit for bit."""
+    sizes = [600, 7, 3, 12, 2, 20, 5, 9, 300]
+    cfgs, qs, ps, es = [], [], [], []
+    for r, nr in enumerate(sizes):
+        L = W.cubic_side(nr) if nr >= 300 else 3.95
+        q, p, e = W.equilibrium_state(nr, [L] * 3, seed=1500 + r)
+        cfgs.append(dp.Config(n=nr, box=[L] * 3, seed=40 + r, replica=r))
+        qs.append(q); ps.append(p); es.append(e)
+    b = dp.System(cfgs, np.concatenate(qs), np.concatenate(ps), np.concatenate(es))
+    b.step(12)
+    qb, pb, eb, _ = _gpu_state(b)
+    enb = b.energies()
+    for r in range(len(cfgs)):
+        s = dp.System(cfgs[r], qs[r], ps[r], es[r])
+        s.step(12)
+        q1, p1, e1, _ = _gpu_state(s)
+        lo, hi = b.offsets[r], b.offsets[r + 1]
+        assert np.array_equal(qb[lo:hi], q1), r
+        assert np.array_equal(pb[lo:hi], p1), r
+        assert np.array_equal(eb[lo:hi], e1), r
+        assert np.array_equal(enb[r], s.energies(), equal_nan=True), r
+        s.close()
+    b.close()
+
+
 def test_batched_256_replicas_one_step_vs_oracle(dp):
     """The batched workload itself (256 replicas, sizes uniform in
     [500, 8000] at density 3, one seed per replica, dt = 0.01): after 3 steps
