@@ -317,6 +317,13 @@ def _profile_lines():
     return lines
 
 
+# The pair kernels of the headline workload as rocprofv3 names them (batch,
+# precision, model and, for sweep 2, the surrogate fused in: the learned EOS).
+PAIR_KERNEL_SYMBOLS = {"pass_a_forces": "k_pass_a_uniq<false, 0, false>",
+                       "pass_b_ser": "k_pass_b_uniq<false, 0, 0>",
+                       "pass_c_ser": "k_pass_c_uniq<false, 0, 0, 0, 1>"}
+
+
 def counter_traffic(kernel):
     """HBM bytes per launch (read, write) of a kernel from the committed
     rocprofv3 counter summary (None if stale)."""
@@ -614,10 +621,7 @@ def main():
     b0 = sysm.list_builds()
     sysm.step(100)
     builds_per_step = (sysm.list_builds() - b0) / 100.0
-    # kernel names as rocprofv3 reports them (batch, precision, model and, for
-    # sweep 2, the surrogate fused in: this workload's learned EOS)
-    symbols = {"pass_a_forces": "k_pass_a_uniq<false, 0>", "pass_b_ser": "k_pass_b_uniq<false, 0, 0>",
-               "pass_c_ser": "k_pass_c_uniq<false, 0, 0, 0, 1>"}
+    symbols = PAIR_KERNEL_SYMBOLS
     unique_pairs = 0.5 * nbar * n
     # the step's end runs inside sweep 2 when the kick is launched less often
     # than the sweep (once per call rather than once per step)

@@ -42,3 +42,15 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, cwd=ROOT, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_pair_kernel_symbols_are_in_the_profile_summaries():
+    """The names the bench looks up in the committed rocprofv3 summaries are
+    the ones rocprofv3 reported, so no counter figure drops out silently."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    stats = open(os.path.join(root, "profiles", "learned_eos_n1m_kernel_stats.md")).read()
+    traffic = open(bench.PROFILE_TRAFFIC).read().splitlines()
+    named = {l.rsplit(" ", 2)[0] for l in traffic if l.startswith("k_")}
+    for sym in bench.PAIR_KERNEL_SYMBOLS.values():
+        assert f"| {sym} |" in stats, sym
+        assert sym in named, sym
