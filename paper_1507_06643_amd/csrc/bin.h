@@ -411,15 +411,38 @@ __global__ void k_rank_gather(PState src, PState dst, const uint32_t* __restrict
                               const Geo* __restrict__ geo, QIdF* __restrict__ qid,
                               uint32_t* __restrict__ slot, const BuildCtl* ctl, double half_skin2,
                               const uint32_t* status) {
+  if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;  // uniform
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  if (status_set(status) || !rebuild_now(ctl, half_skin2)) return;
-  const uint32_t i = bucket[k];
-  const uint32_t c = key[i];
-  const uint32_t b = start[c], e = start[c + 1];
-  const uint32_t my = idk[i];
+  const bool live = k < n;
+  uint32_t i = 0, b = 0, e = 0, my = 0;
+  if (live) {
+    i = bucket[k];
+    const uint32_t c = key[i];
+    b = start[c];
+    e = start[c + 1];
+    my = idk[i];
+  }
+  // A cell's members hold consecutive slots, so a cell that lies within the
+  // wave's 64 slots finds its members' identifiers on the other lanes; a
+  // cell that crosses the wave's ends reads them from memory.
+  const int lane = (int)(threadIdx.x % kWave);
+  const int64_t w0 = k - lane;  // the wave's first slot
+  const bool inwave = live && (int64_t)b >= w0 && (int64_t)e <= w0 + kWave;
+  const uint32_t span = inwave ? e - b : 0u;
+  uint32_t smax = span;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1)
+    smax = max(smax, (uint32_t)__shfl_xor((int)smax, off, kWave));
+  smax = (uint32_t)__builtin_amdgcn_readfirstlane((int)smax);
   uint32_t r = 0;
-  for (uint32_t m = b; m < e; ++m) r += idk[bucket[m]] < my ? 1u : 0u;
+  for (uint32_t t = 0; t < smax; ++t) {  // every lane takes part in each read
+    const int from = t < span ? (int)((int64_t)b - w0) + (int)t : lane;
+    const uint32_t o = (uint32_t)__shfl((int)my, from, kWave);
+    r += (t < span && o < my) ? 1u : 0u;
+  }
+  if (!live) return;
+  if (!inwave)
+    for (uint32_t m = b; m < e; ++m) r += idk[bucket[m]] < my ? 1u : 0u;
   const uint32_t p = b + r;
   const Rec rc = src.r[i];
   dst.r[p] = rc;
