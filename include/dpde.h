@@ -429,6 +429,12 @@ int dpde_mlp_eval(dpde_handle* h, const float* x, float* y, int64_t n);
 /* Linear cell index (within its replica) of every particle, by ID (device int32 n). */
 int dpde_debug_cells(dpde_handle* h, int32_t* cell_of_id);
 
+/* The memory order the last list build chose: for every memory slot, the
+ * identifier row (the replica's first row + the particle's ID) of the particle
+ * it holds (device int32 n).  The particles of one cell (side at least rc, as
+ * the cells of Sec. 3.1.2) fill consecutive slots in increasing ID order. */
+int dpde_debug_order(dpde_handle* h, int32_t* row_of_slot);
+
 /* 1/T_i of every particle as the last step left it (device FP64 n, ID order):
  * the inverse temperature of eq. DPDE_internalEOS that the next step's
  * friction gamma_ij uses (eq. DPDE_fd). */

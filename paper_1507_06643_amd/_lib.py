@@ -122,6 +122,7 @@ SIGNATURES = [
                                         C.POINTER(C.c_float)]),
     ("dpde_mlp_eval", C.c_int, [_vp, _vp, _vp, _i64]),
     ("dpde_debug_cells", C.c_int, [_vp, _vp]),
+    ("dpde_debug_order", C.c_int, [_vp, _vp]),
     ("dpde_debug_inv_temperature", C.c_int, [_vp, _vp]),
     ("dpde_debug_list_lengths", C.c_int, [_vp, _vp]),
     ("dpde_debug_pairs", C.c_int, [_vp, _vp, _i64, C.POINTER(_i64)]),

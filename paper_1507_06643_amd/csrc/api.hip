@@ -1512,6 +1512,15 @@ int dpde_debug_cells(dpde_handle* h, int32_t* cell_of_id) {
   return DPDE_OK;
 }
 
+int dpde_debug_order(dpde_handle* h, int32_t* row_of_slot) {
+  if (!h || !row_of_slot) return fail(DPDE_EINVAL, "NULL argument");
+  launch(h, "debug_order", k_debug_order, blocks(h->n, 256), 256, h->cur, h->n,
+         (const Geo*)h->geo, row_of_slot);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  return DPDE_OK;
+}
+
 int dpde_debug_inv_temperature(dpde_handle* h, double* inv_t) {
   if (!h || !inv_t) return fail(DPDE_EINVAL, "NULL argument");
   launch(h, "debug_inv_temperature", k_store_inv_temperature, blocks(h->n, 256), 256, h->cur,

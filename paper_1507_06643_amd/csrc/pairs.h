@@ -2039,6 +2039,15 @@ __global__ void k_debug_cells(PState s, int64_t n, const Geo* __restrict__ geo, 
   out[g.first + rc.id] = cx + g.nc[0] * (cy + g.nc[1] * cz);
 }
 
+// The identifier row (replica's first row + ID) of the particle in every
+// memory slot.
+__global__ void k_debug_order(PState s, int64_t n, const Geo* __restrict__ geo, int32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Rec& rc = s.r[i];
+  out[i] = (int32_t)(geo[rc.rep].first + rc.id);
+}
+
 // Every pair of the lists once, as (lower id, higher id) rows.  A pair
 // joining two tiles is in both lists (taken from the lower identifier); with
 // the tile work lists (uniq) a pair inside a tile is in one list only.

@@ -292,6 +292,11 @@ class System:
         L.check(self._lib.dpde_debug_cells(self.h, _ptr(out)))
         return out
 
+    def debug_order(self):
+        out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        L.check(self._lib.dpde_debug_order(self.h, _ptr(out)))
+        return out
+
     def debug_inv_temperature(self):
         out = torch.empty(self.n, dtype=torch.float64, device="cuda")
         L.check(self._lib.dpde_debug_inv_temperature(self.h, _ptr(out)))

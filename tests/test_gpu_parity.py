@@ -118,6 +118,61 @@ def test_cells_and_pairs_bit_exact(dp, n, box, periodic, seed, skin):
     sysm.close()
 
 
+def _check_cell_order(sysm, offsets):
+    """The memory order of the last list build: a permutation of the
+    identifier rows in which every cell's particles fill consecutive slots in
+    increasing identifier order.  Cells are taken from the current positions,
+    so the positions must be those of the build."""
+    rows = sysm.debug_order().cpu().numpy().astype(np.int64)
+    cells = sysm.debug_cells().cpu().numpy().astype(np.int64)  # by identifier row
+    assert np.array_equal(np.sort(rows), np.arange(len(rows)))
+    rep = np.searchsorted(np.asarray(offsets), rows, side="right") - 1
+    key = rep * (cells.max() + 1) + cells[rows]
+    same = np.diff(key) == 0
+    assert np.count_nonzero(~same) + 1 == len(np.unique(key))  # one run per cell
+    assert (np.diff(rows)[same] > 0).all()  # increasing identifiers inside it
+
+
+@pytest.mark.parametrize("case", ["uniform", "clustered", "blocked", "batch"])
+def test_memory_order_is_identifier_order_within_cells(dp, case):
+    """The reorder ranks each particle in its cell by identifier, from the
+    other lanes where the cell lies within one wave's 64 slots and from
+    memory otherwise (a cell of 300 particles, cells across wave ends): after
+    the set-up build and after a step that rebuilds (skin 0), each cell's
+    particles sit in consecutive slots in increasing identifier order.  The
+    clustered state is checked after the set-up build only: at a hundred
+    times the workload's density one step drives internal energies negative,
+    which the step reports as an error."""
+    if case == "batch":
+        sizes = [700, 100, 533]
+        cfgs, qs, ps, es = [], [], [], []
+        for r, nr in enumerate(sizes):
+            L = W.cubic_side(nr) if nr != 100 else 3.95
+            q, p, e = W.equilibrium_state(nr, [L] * 3, seed=900 + r)
+            cfgs.append(_cfg(dp, nr, [L] * 3, skin=0.0, seed=3 + r, replica=r))
+            qs.append(q); ps.append(p); es.append(e)
+        sysm = dp.System(cfgs, np.vstack(qs), np.vstack(ps), np.concatenate(es))
+        offsets = sysm.offsets
+    else:
+        n = 3001
+        L = W.cubic_side(n)
+        q, p, e = W.equilibrium_state(n, [L] * 3, seed=77)
+        cap = 0
+        if case == "clustered":  # 300 particles in one cell (side L / 10 > 1.0)
+            rng = np.random.default_rng(78)
+            q[:300] = 2.2 + 0.5 * rng.random((300, 3))
+            cap = 512
+        sysm = dp.System(_cfg(dp, n, [L] * 3, skin=0.0, neighbor_cap=cap), q, p, e)
+        if case == "blocked":
+            sysm.set_shape(order_block=2)
+        offsets = [0, n]
+    _check_cell_order(sysm, offsets)
+    if case != "clustered":
+        sysm.step(1)
+        _check_cell_order(sysm, offsets)
+    sysm.close()
+
+
 @pytest.mark.parametrize("order_block", [2, 3])
 @pytest.mark.parametrize("n,box,periodic,seed", [CASES[2], CASES[4]])
 def test_pairs_bit_exact_in_blocked_cell_order(dp, n, box, periodic, seed, order_block):
