@@ -1618,11 +1618,14 @@ __attribute__((amdgpu_waves_per_eu(REGEN ? 1 : (THETA ? 6 : 5), 8))) void k_pass
   };
   // e_ij of entry k of particle ii (record ra, h_i = hi), given the
   // partner's index j and h_j; its share added to the partner inside the tile
+  // (dx, dy, dz: the stored increment when the caller has loaded it, with
+  // `have`)
   auto term = [&](const Rec& ra, const H3& hi, int64_t ii, uint32_t k, uint32_t j, double hx,
-                  double hy, double hz) -> long long {
+                  double hy, double hz, bool have = false, double dx = 0.0, double dy = 0.0,
+                  double dz = 0.0) -> long long {
     const int64_t e = (int64_t)k * st + ii;
     const double ux = hi.x - hx, uy = hi.y - hy, uz = hi.z - hz;
-    double ex, ey, ez;
+    double ex = dx, ey = dy, ez = dz;
     if constexpr (REGEN) {
       const Rec b = R[j];
       const GeoRef<BATCH> g = geo[BATCH ? ra.rep : 0u];
@@ -1633,7 +1636,7 @@ __attribute__((amdgpu_waves_per_eu(REGEN ? 1 : (THETA ? 6 : 5), 8))) void k_pass
       ey = o.dp[1];
       ez = o.dp[2];
     } else {
-      load_dp<PREC>(nl, e, ex, ey, ez);
+      if (!have) load_dp<PREC>(nl, e, ex, ey, ez);
     }
     const double eij = -0.5 * (ex * ux + ey * uy + ez * uz);
     const long long f = pair_fix_raw(eij);
@@ -1655,18 +1658,22 @@ __attribute__((amdgpu_waves_per_eu(REGEN ? 1 : (THETA ? 6 : 5), 8))) void k_pass
       jr[q] = nreg ? nl.idx[(int64_t)kc * st + i] : 0u;
     }
     double hx = 0.0, hy = 0.0, hz = 0.0;
+    double sx = 0.0, sy = 0.0, sz = 0.0;  // the stored increment, likewise one entry ahead
     if ((uint32_t)sub < nreg) {
       gather_h(jr[0], hx, hy, hz);
+      if constexpr (!REGEN) load_dp<PREC>(nl, (int64_t)sub * st + i, sx, sy, sz);
     }
 #pragma unroll
     for (int q = 0; q < kTileRegular / 2; ++q) {
       const uint32_t k = (uint32_t)(sub + 2 * q);
       if (k >= nreg) break;
       const double cx = hx, cy = hy, cz = hz;
+      const double ex = sx, ey = sy, ez = sz;
       if (q + 1 < kTileRegular / 2 && k + 2 < nreg) {
         gather_h(jr[q + 1], hx, hy, hz);
+        if constexpr (!REGEN) load_dp<PREC>(nl, (int64_t)(k + 2) * st + i, sx, sy, sz);
       }
-      X += term(a, hi, i, k, jr[q], cx, cy, cz);
+      X += term(a, hi, i, k, jr[q], cx, cy, cz, !REGEN, ex, ey, ez);
       ++terms;
     }
   }
